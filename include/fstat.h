@@ -1,0 +1,187 @@
+/*
+ * fstat.h -- C-ABI of the MI355X (gfx950) F-statistic demodulation library.
+ *
+ * The library computes, for every template (sky direction n, frequency f,
+ * spindown fdot) of a work unit, the F-statistic 2F from a set of SFTs (short
+ * Fourier transforms of detector data).  This is the F-statistic loop nest of
+ * the paper (Listing 1, Section 2): an independent loop over the frequencies
+ * of a band, a sum over detectors and, inside it, a sum over the SFTs of each
+ * detector followed by a normalisation.  The per-SFT body, which the paper
+ * leaves undefined, is the Dirichlet-kernel demodulation:
+ *
+ *   tau    = (t_start + T/2 - t_ref) + r . n      r: SSB position, light-s
+ *   Tdot   = 1 + v . n                            v: velocity, units of c
+ *   Dphi   = ((f + fdot * tau) * Tdot) * T        frequency in SFT bins
+ *   k*     = floor(Dphi),   kappa = Dphi - k*
+ *   phi    = tau * (f + (fdot/2) * tau)           phase in cycles
+ *   z      = exp(-2 pi i frac(phi)) * sum_{m=-D}^{D-1} (-1)^(k*-m) x[k*-m] sinc(kappa+m)
+ *   Fa     = sum a z,  Fb = sum b z               over all SFTs of all detectors
+ *   2F     = 2 (B |Fa|^2 + A |Fb|^2 - 2 C Re(Fa conj Fb)) / (A B - C^2)
+ *   A = sum a^2, B = sum b^2, C = sum a b,  sinc(x) = sin(pi x)/(pi x)
+ *
+ * Frequency templates are f_j = f0 + j*df, spindowns fdot_i = fdot0 + i*dfdot.
+ * Dphi and k* are evaluated in IEEE binary64 in exactly the order written
+ * above (no fused multiply-add), so k* is reproducible bit for bit; the window
+ * sums and Fa, Fb are accumulated in FP32.  The data arrays follow the
+ * "data arrays plus offset arrays" layout the paper's GPU port adopted
+ * (Section 6): flat contiguous arrays, ragged detector blocks addressed by
+ * offsets.
+ *
+ * Memory: every array pointer in fstat_wu / fstat_out is a DEVICE pointer on
+ * the plan's device, owned by the caller, which must keep it alive until the
+ * work queued on the stream has completed.  `stream` arguments are
+ * hipStream_t values (NULL = the null stream).  Return values are FSTAT_OK (0)
+ * or a negative FSTAT_E_* code; no call aborts or throws.  A plan may be used
+ * by one host thread and one stream at a time; distinct plans are independent.
+ */
+#ifndef FSTAT_H
+#define FSTAT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ codes --- */
+#define FSTAT_OK 0
+#define FSTAT_E_ARG (-1)          /* NULL pointer, bad size or parameter */
+#define FSTAT_E_BAND (-2)         /* a Dirichlet window leaves the stored band */
+#define FSTAT_E_SIZE (-3)         /* a size exceeds the plan's maxima */
+#define FSTAT_E_NOMEM (-4)        /* device or pinned allocation failed */
+#define FSTAT_E_DEVICE (-5)       /* HIP runtime error (see fstat_last_error) */
+#define FSTAT_E_UNSUPPORTED (-6)  /* option not available on this device */
+
+/* SFT storage: complex64 (float re, float im), or 16-bit pairs with a per-SFT
+ * FP32 scale: x = scale[sft] * (re, im). */
+#define FSTAT_STORAGE_C64 0
+#define FSTAT_STORAGE_BF16 1
+#define FSTAT_STORAGE_FP16 2
+
+/* Phase arithmetic: frac(phi) in FP64, or in a double-FP32 (split) product.
+ * Dphi and k* are always FP64. */
+#define FSTAT_PHASE_FP64 0
+#define FSTAT_PHASE_SPLIT_FP32 1
+
+/* Window evaluation: the Dterms loop (DIRECT), or per-bin Chebyshev
+ * coefficients of the window sum as a function of kappa (INTERP); AUTO picks. */
+#define FSTAT_KERNEL_AUTO 0
+#define FSTAT_KERNEL_DIRECT 1
+#define FSTAT_KERNEL_INTERP 2
+
+/* fstat_desc.flags */
+#define FSTAT_FLAG_NO_GRAPH 1     /* batched: launch directly, no hipGraph */
+
+/* --------------------------------------------------------- structures --- */
+
+/* Plan descriptor: maxima over every work unit the plan will see. */
+typedef struct fstat_desc {
+  int64_t max_sft;     /* SFTs per work unit, all detectors together, >= 1 */
+  int64_t max_bins;    /* bins per SFT band, >= 1 */
+  int64_t max_sky;     /* sky points per work unit, >= 1 */
+  int64_t max_fd;      /* spindown templates, >= 1 */
+  int64_t max_f;       /* frequency templates, >= 1 */
+  int32_t max_dterms;  /* largest Dterms D, 1 <= D <= 64 */
+  int32_t storage;     /* FSTAT_STORAGE_* */
+  int32_t phase_mode;  /* FSTAT_PHASE_* */
+  int32_t kernel;      /* FSTAT_KERNEL_* */
+  int32_t flags;       /* FSTAT_FLAG_* */
+  int32_t device;      /* HIP device ordinal, or -1 for the current device */
+} fstat_desc;
+
+/* One work unit (all pointers are device pointers, caller-owned). */
+typedef struct fstat_wu {
+  int32_t n_det;              /* detectors, >= 1 (informational: the sum is coherent) */
+  int64_t n_sft;              /* SFTs of all detectors together */
+  int64_t n_bins;             /* bins per SFT */
+  int64_t k_first;            /* absolute bin index of column 0 (bin k <-> k / T Hz) */
+  double t_sft;               /* SFT length T, seconds */
+  const void* sft;            /* [n_sft][n_bins] complex: float2 (C64) or uint16 pairs (BF16/FP16) */
+  const float* sft_scale;     /* [n_sft] dequantisation scale (16-bit storage), else NULL */
+  const double* t_start;      /* [n_sft] GPS start times, seconds */
+  const double* pos;          /* [n_sft][3] detector position at the SFT midpoint, light-s */
+  const double* vel;          /* [n_sft][3] detector velocity at the SFT midpoint, units of c */
+  int64_t n_sky;              /* sky points */
+  const double* sky;          /* [n_sky][3] unit vectors towards the source */
+  const float* a;             /* [n_sky][n_sft] antenna-pattern factor a (noise weights folded in) */
+  const float* b;             /* [n_sky][n_sft] antenna-pattern factor b */
+  double f0, df;              /* frequency grid */
+  int64_t n_f;
+  double fdot0, dfdot;        /* spindown grid, Hz/s */
+  int64_t n_fd;
+  double t_ref;               /* reference time of f and fdot, seconds */
+  int32_t dterms;             /* D: 2D bins per SFT, 1 <= D <= max_dterms */
+} fstat_wu;
+
+/* Outputs, [n_sky][n_fd][n_f] with frequency fastest (device pointers). */
+typedef struct fstat_out {
+  float* twoF;                /* required */
+  float* fa;                  /* optional complex (re, im) pairs, or NULL */
+  float* fb;                  /* optional complex (re, im) pairs, or NULL */
+} fstat_out;
+
+typedef struct fstat_plan fstat_plan;
+
+/* ------------------------------------------------------------- calls --- */
+
+/* Create a plan for work units within the maxima of *d.  Allocates the plan's
+ * device scratch lazily.  Returns FSTAT_E_ARG for an invalid descriptor,
+ * FSTAT_E_DEVICE if the device cannot be used.  *out is NULL on failure. */
+int fstat_plan_create(fstat_plan** out, const fstat_desc* d);
+
+/* 2F (and optionally Fa, Fb) of every template of one work unit: the
+ * frequency-band loop of the F-statistic (Listing 1) with the detector and
+ * SFT sums inside.  Validates arguments on the host, then enqueues on
+ * `stream`: (1) per (sky, SFT) geometry tau, Tdot and per-sky A, B, C with a
+ * check that every window [k*-D+1, k*+D] of the grid lies in the band; the
+ * call waits for this check and returns FSTAT_E_BAND (nothing else
+ * launched) if it fails; (2) the demodulation kernel, which writes `out`
+ * asynchronously.  Returns after (2) is enqueued. */
+int fstat_compute(fstat_plan* p, const fstat_wu* wu, const fstat_out* out, void* stream);
+
+/* 2F of many work units with uneven SFT counts, bands and template grids in
+ * one persistent launch (the "several clients per system" idea of the Cell
+ * port, Section 5, done on one device).  All work units are validated and
+ * band-checked before anything is launched; on failure the index of the first
+ * failing work unit is in fstat_last_error.  The launch sequence is captured
+ * once in a hipGraph per (n_wu, tile) signature and replayed; the work-unit
+ * table lives in device memory, so a replay may change every pointer and
+ * size.  outs[i] belongs to wus[i]. */
+int fstat_batch_compute(fstat_plan* p, const fstat_wu* wus, int32_t n_wu, const fstat_out* outs,
+                        void* stream);
+
+/* Bin index, offset and phase of (template, SFT) pairs, computed by the same
+ * device code the demodulation kernels use (step "bin index + phase").
+ * Index arrays and outputs are device arrays of length n: sky, spindown,
+ * frequency and SFT indices in; k* (int64), kappa and frac(phi) (FP64) out. */
+int fstat_bins(fstat_plan* p, const fstat_wu* wu, int64_t n, const int32_t* i_sky, const int32_t* i_fd,
+               const int32_t* i_f, const int32_t* i_sft, int64_t* kstar, double* kappa, double* phi_frac,
+               void* stream);
+
+/* Measure the candidate tile shapes on this work unit (timed on `stream`,
+ * outputs overwritten) and keep the fastest for work units of its class
+ * (storage, Dterms, kernel).  `cache_path` (may be NULL) names a text file
+ * that stores results across processes; it is read first and updated. */
+int fstat_autotune(fstat_plan* p, const fstat_wu* wu, const fstat_out* out, void* stream,
+                   const char* cache_path);
+
+/* Duration in milliseconds of the last demodulation kernel of the last
+ * fstat_compute / fstat_batch_compute call, measured with HIP events on the
+ * stream it ran on (waits for it).  Returns a negative value if none. */
+double fstat_last_kernel_ms(fstat_plan* p);
+
+/* Release the plan and everything it allocated (waits for its device work).
+ * Safe on NULL and after any error. */
+void fstat_plan_destroy(fstat_plan* p);
+
+/* Static text for a return code. */
+const char* fstat_strerror(int code);
+
+/* Text of the plan's last error ("" if none); valid until the next call on p. */
+const char* fstat_last_error(const fstat_plan* p);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FSTAT_H */

@@ -1,0 +1,275 @@
+"""Python binding of libfstat (MI355X F-statistic demodulation).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of `csrc/`, behind the C-ABI declared in `include/fstat.h`.  torch
+tensors provide device memory and streams.  The functions keep the C names.
+
+A work unit is any object with the attributes of `fstat_wu` (see
+`WorkUnit`): device tensors for the arrays and Python numbers for the
+scalars.  Outputs are an object with `twoF` and optional `fa`, `fb` tensors.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+from typing import Optional, Sequence
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_build", "libfstat.so")
+
+FSTAT_OK = 0
+FSTAT_E_ARG = -1
+FSTAT_E_BAND = -2
+FSTAT_E_SIZE = -3
+FSTAT_E_NOMEM = -4
+FSTAT_E_DEVICE = -5
+FSTAT_E_UNSUPPORTED = -6
+
+FSTAT_STORAGE_C64 = 0
+FSTAT_STORAGE_BF16 = 1
+FSTAT_STORAGE_FP16 = 2
+FSTAT_PHASE_FP64 = 0
+FSTAT_PHASE_SPLIT_FP32 = 1
+FSTAT_KERNEL_AUTO = 0
+FSTAT_KERNEL_DIRECT = 1
+FSTAT_KERNEL_INTERP = 2
+FSTAT_FLAG_NO_GRAPH = 1
+
+STORAGE = {"c64": FSTAT_STORAGE_C64, "bf16": FSTAT_STORAGE_BF16, "fp16": FSTAT_STORAGE_FP16}
+KERNELS = {"auto": FSTAT_KERNEL_AUTO, "direct": FSTAT_KERNEL_DIRECT, "interp": FSTAT_KERNEL_INTERP}
+PHASES = {"fp64": FSTAT_PHASE_FP64, "split": FSTAT_PHASE_SPLIT_FP32}
+
+# Every entry point include/fstat.h declares.
+EXPORTS = ("fstat_plan_create", "fstat_compute", "fstat_batch_compute", "fstat_bins", "fstat_autotune",
+           "fstat_last_kernel_ms", "fstat_plan_destroy", "fstat_strerror", "fstat_last_error")
+
+
+class FstatError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{msg} (code {code})")
+        self.code = code
+
+
+class fstat_desc(ctypes.Structure):
+    _fields_ = [("max_sft", ctypes.c_int64), ("max_bins", ctypes.c_int64), ("max_sky", ctypes.c_int64),
+                ("max_fd", ctypes.c_int64), ("max_f", ctypes.c_int64), ("max_dterms", ctypes.c_int32),
+                ("storage", ctypes.c_int32), ("phase_mode", ctypes.c_int32), ("kernel", ctypes.c_int32),
+                ("flags", ctypes.c_int32), ("device", ctypes.c_int32)]
+
+
+class fstat_wu(ctypes.Structure):
+    _fields_ = [("n_det", ctypes.c_int32), ("n_sft", ctypes.c_int64), ("n_bins", ctypes.c_int64),
+                ("k_first", ctypes.c_int64), ("t_sft", ctypes.c_double), ("sft", ctypes.c_void_p),
+                ("sft_scale", ctypes.c_void_p), ("t_start", ctypes.c_void_p), ("pos", ctypes.c_void_p),
+                ("vel", ctypes.c_void_p), ("n_sky", ctypes.c_int64), ("sky", ctypes.c_void_p),
+                ("a", ctypes.c_void_p), ("b", ctypes.c_void_p), ("f0", ctypes.c_double), ("df", ctypes.c_double),
+                ("n_f", ctypes.c_int64), ("fdot0", ctypes.c_double), ("dfdot", ctypes.c_double),
+                ("n_fd", ctypes.c_int64), ("t_ref", ctypes.c_double), ("dterms", ctypes.c_int32)]
+
+
+class fstat_out(ctypes.Structure):
+    _fields_ = [("twoF", ctypes.c_void_p), ("fa", ctypes.c_void_p), ("fb", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libfstat.so.  There is no fallback: a missing library is an error."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built: run `python -m paper_0904_1826_amd.build`")
+    lib = ctypes.CDLL(path)
+    P, I64, I32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+    lib.fstat_plan_create.argtypes = [ctypes.POINTER(P), ctypes.POINTER(fstat_desc)]
+    lib.fstat_plan_create.restype = ctypes.c_int
+    lib.fstat_compute.argtypes = [P, ctypes.POINTER(fstat_wu), ctypes.POINTER(fstat_out), P]
+    lib.fstat_compute.restype = ctypes.c_int
+    lib.fstat_batch_compute.argtypes = [P, ctypes.POINTER(fstat_wu), I32, ctypes.POINTER(fstat_out), P]
+    lib.fstat_batch_compute.restype = ctypes.c_int
+    lib.fstat_bins.argtypes = [P, ctypes.POINTER(fstat_wu), I64, P, P, P, P, P, P, P, P]
+    lib.fstat_bins.restype = ctypes.c_int
+    lib.fstat_autotune.argtypes = [P, ctypes.POINTER(fstat_wu), ctypes.POINTER(fstat_out), P, ctypes.c_char_p]
+    lib.fstat_autotune.restype = ctypes.c_int
+    lib.fstat_last_kernel_ms.argtypes = [P]
+    lib.fstat_last_kernel_ms.restype = ctypes.c_double
+    lib.fstat_plan_destroy.argtypes = [P]
+    lib.fstat_plan_destroy.restype = None
+    lib.fstat_strerror.argtypes = [ctypes.c_int]
+    lib.fstat_strerror.restype = ctypes.c_char_p
+    lib.fstat_last_error.argtypes = [P]
+    lib.fstat_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _stream_handle(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+@dataclasses.dataclass
+class WorkUnit:
+    """Device-resident work unit (mirrors fstat_wu)."""
+    n_det: int
+    sft: object            # tensor [n_sft, n_bins, 2] float32, or [n_sft, n_bins, 2] int16/uint16 bits
+    sft_scale: object      # tensor [n_sft] float32 or None
+    k_first: int
+    t_sft: float
+    t_start: object        # float64 [n_sft]
+    pos: object            # float64 [n_sft, 3]
+    vel: object            # float64 [n_sft, 3]
+    sky: object            # float64 [n_sky, 3]
+    a: object              # float32 [n_sky, n_sft]
+    b: object              # float32 [n_sky, n_sft]
+    f0: float
+    df: float
+    n_f: int
+    fdot0: float
+    dfdot: float
+    n_fd: int
+    t_ref: float
+    dterms: int
+
+    @property
+    def n_sft(self):
+        return int(self.sft.shape[0])
+
+    @property
+    def n_bins(self):
+        return int(self.sft.shape[1])
+
+    @property
+    def n_sky(self):
+        return int(self.sky.shape[0])
+
+
+@dataclasses.dataclass
+class Output:
+    twoF: object
+    fa: object = None
+    fb: object = None
+
+
+def _wu_struct(w) -> fstat_wu:
+    return fstat_wu(int(w.n_det), int(w.n_sft), int(w.n_bins), int(w.k_first), float(w.t_sft), _ptr(w.sft),
+                    _ptr(w.sft_scale), _ptr(w.t_start), _ptr(w.pos), _ptr(w.vel), int(w.n_sky), _ptr(w.sky),
+                    _ptr(w.a), _ptr(w.b), float(w.f0), float(w.df), int(w.n_f), float(w.fdot0), float(w.dfdot),
+                    int(w.n_fd), float(w.t_ref), int(w.dterms))
+
+
+def _out_struct(o) -> fstat_out:
+    return fstat_out(_ptr(o.twoF), _ptr(getattr(o, "fa", None)), _ptr(getattr(o, "fb", None)))
+
+
+def fstat_strerror(code: int) -> str:
+    return load_library().fstat_strerror(int(code)).decode()
+
+
+def fstat_last_error(plan) -> str:
+    return load_library().fstat_last_error(plan).decode()
+
+
+def _check(plan, rc: int):
+    if rc != FSTAT_OK:
+        detail = fstat_last_error(plan) if plan else ""
+        raise FstatError(rc, f"{fstat_strerror(rc)}: {detail}" if detail else fstat_strerror(rc))
+
+
+def fstat_plan_create(*, max_sft, max_bins, max_sky, max_fd, max_f, max_dterms=16, storage="c64", phase="fp64",
+                      kernel="auto", flags=0, device=-1):
+    lib = load_library()
+    d = fstat_desc(int(max_sft), int(max_bins), int(max_sky), int(max_fd), int(max_f), int(max_dterms),
+                   STORAGE.get(storage, storage), PHASES.get(phase, phase), KERNELS.get(kernel, kernel), int(flags),
+                   int(device))
+    h = ctypes.c_void_p()
+    rc = lib.fstat_plan_create(ctypes.byref(h), ctypes.byref(d))
+    _check(None, rc)
+    return h
+
+
+def fstat_plan_destroy(plan) -> None:
+    if plan:
+        load_library().fstat_plan_destroy(plan)
+
+
+def fstat_compute(plan, wu, out, stream=None) -> None:
+    s, o = _wu_struct(wu), _out_struct(out)
+    _check(plan, load_library().fstat_compute(plan, ctypes.byref(s), ctypes.byref(o), _stream_handle(stream)))
+
+
+def fstat_batch_compute(plan, wus: Sequence, outs: Sequence, stream=None) -> None:
+    n = len(wus)
+    if len(outs) != n:
+        raise ValueError("one output per work unit")
+    ws = (fstat_wu * max(n, 1))(*[_wu_struct(w) for w in wus])
+    os_ = (fstat_out * max(n, 1))(*[_out_struct(o) for o in outs])
+    _check(plan, load_library().fstat_batch_compute(plan, ws, n, os_, _stream_handle(stream)))
+
+
+def fstat_bins(plan, wu, i_sky, i_fd, i_f, i_sft, kstar, kappa, phi_frac, stream=None) -> None:
+    s = _wu_struct(wu)
+    n = int(i_sky.numel())
+    _check(plan, load_library().fstat_bins(plan, ctypes.byref(s), n, _ptr(i_sky), _ptr(i_fd), _ptr(i_f), _ptr(i_sft),
+                                           _ptr(kstar), _ptr(kappa), _ptr(phi_frac), _stream_handle(stream)))
+
+
+def fstat_autotune(plan, wu, out, stream=None, cache_path: Optional[str] = None) -> None:
+    s, o = _wu_struct(wu), _out_struct(out)
+    path = cache_path.encode() if cache_path else None
+    _check(plan, load_library().fstat_autotune(plan, ctypes.byref(s), ctypes.byref(o), _stream_handle(stream), path))
+
+
+def fstat_last_kernel_ms(plan) -> float:
+    return float(load_library().fstat_last_kernel_ms(plan))
+
+
+class Plan:
+    """Owning wrapper around an fstat_plan handle."""
+
+    def __init__(self, **desc):
+        self.handle = fstat_plan_create(**desc)
+
+    def compute(self, wu, out, stream=None):
+        fstat_compute(self.handle, wu, out, stream)
+
+    def batch_compute(self, wus, outs, stream=None):
+        fstat_batch_compute(self.handle, wus, outs, stream)
+
+    def bins(self, wu, i_sky, i_fd, i_f, i_sft, kstar, kappa, phi_frac, stream=None):
+        fstat_bins(self.handle, wu, i_sky, i_fd, i_f, i_sft, kstar, kappa, phi_frac, stream)
+
+    def autotune(self, wu, out, stream=None, cache_path=None):
+        fstat_autotune(self.handle, wu, out, stream, cache_path)
+
+    def last_kernel_ms(self) -> float:
+        return fstat_last_kernel_ms(self.handle)
+
+    def last_error(self) -> str:
+        return fstat_last_error(self.handle)
+
+    def close(self):
+        if self.handle:
+            fstat_plan_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

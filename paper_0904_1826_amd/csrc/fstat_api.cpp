@@ -1,0 +1,403 @@
+// Host side of the F-statistic library: plan, argument validation, scratch
+// management, launch sequencing, autotuning and the C-ABI entry points
+// declared in include/fstat.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "fstat.h"
+#include "fstat_internal.h"
+
+using fstat::Tile;
+using fstat::WuDev;
+
+struct fstat_plan {
+  fstat_desc d{};
+  int device = 0;
+  int cu_count = 0;
+  std::string err;
+  // scratch (device)
+  void* geo = nullptr;
+  size_t geo_bytes = 0;
+  void* abcd = nullptr;
+  size_t abcd_bytes = 0;
+  int* status_d = nullptr;
+  int* status_h = nullptr;  // pinned
+  // timing
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipStream_t ev_stream = nullptr;
+  bool timed = false;
+  // tile choices per class key
+  std::map<std::string, Tile> tiles;
+  // fault injection (host-side forcing of error paths)
+  long fail_malloc_at = -1, fail_launch_at = -1;
+  long n_malloc = 0, n_launch = 0;
+};
+
+namespace {
+
+int set_err(fstat_plan* p, int code, const char* fmt, ...) {
+  if (p) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    p->err = buf;
+  }
+  return code;
+}
+
+int hip_err(fstat_plan* p, hipError_t e, const char* what) {
+  return set_err(p, FSTAT_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+// The Nth allocation / launch fails when FSTAT_FAULT="malloc:N" / "launch:N".
+void read_fault_env(fstat_plan* p) {
+  const char* e = getenv("FSTAT_FAULT");
+  if (!e) return;
+  long n = 0;
+  if (sscanf(e, "malloc:%ld", &n) == 1) p->fail_malloc_at = n;
+  if (sscanf(e, "launch:%ld", &n) == 1) p->fail_launch_at = n;
+}
+
+int dev_alloc(fstat_plan* p, void** ptr, size_t* have, size_t need, const char* what) {
+  if (*have >= need && *ptr) return FSTAT_OK;
+  if (++p->n_malloc == p->fail_malloc_at) return set_err(p, FSTAT_E_NOMEM, "%s: injected allocation failure", what);
+  if (*ptr) {
+    (void)hipDeviceSynchronize();
+    (void)hipFree(*ptr);
+    *ptr = nullptr;
+    *have = 0;
+  }
+  hipError_t e = hipMalloc(ptr, need);
+  if (e != hipSuccess) {
+    *ptr = nullptr;
+    (void)hipGetLastError();
+    return set_err(p, FSTAT_E_NOMEM, "%s: hipMalloc(%zu) failed: %s", what, need, hipGetErrorString(e));
+  }
+  *have = need;
+  return FSTAT_OK;
+}
+
+int check_launch(fstat_plan* p, hipError_t e, const char* what) {
+  if (++p->n_launch == p->fail_launch_at) return set_err(p, FSTAT_E_DEVICE, "%s: injected launch failure", what);
+  if (e != hipSuccess) return hip_err(p, e, what);
+  return FSTAT_OK;
+}
+
+bool finite(double x) { return std::isfinite(x); }
+
+int validate_wu(fstat_plan* p, const fstat_wu* w, const fstat_out* o, int idx) {
+  const fstat_desc& d = p->d;
+  char tag[32] = "";
+  if (idx >= 0) snprintf(tag, sizeof tag, "work unit %d: ", idx);
+  if (!w || !o) return set_err(p, FSTAT_E_ARG, "%snull work unit or output", tag);
+  if (!w->sft || !w->t_start || !w->pos || !w->vel || !w->sky || !w->a || !w->b)
+    return set_err(p, FSTAT_E_ARG, "%snull input array", tag);
+  if (d.storage != FSTAT_STORAGE_C64 && !w->sft_scale)
+    return set_err(p, FSTAT_E_ARG, "%s16-bit storage needs sft_scale", tag);
+  if (!o->twoF) return set_err(p, FSTAT_E_ARG, "%snull twoF output", tag);
+  if (w->n_det < 1) return set_err(p, FSTAT_E_ARG, "%sn_det < 1", tag);
+  if (w->dterms < 1 || w->dterms > d.max_dterms) return set_err(p, FSTAT_E_ARG, "%sdterms %d outside [1, %d]", tag, w->dterms, d.max_dterms);
+  if (w->n_sft < 1 || w->n_bins < 1 || w->n_sky < 1 || w->n_f < 1 || w->n_fd < 1)
+    return set_err(p, FSTAT_E_ARG, "%ssizes must be >= 1", tag);
+  if (w->n_sft > d.max_sft || w->n_bins > d.max_bins || w->n_sky > d.max_sky || w->n_f > d.max_f || w->n_fd > d.max_fd)
+    return set_err(p, FSTAT_E_SIZE, "%ssize exceeds the plan maxima", tag);
+  if (w->n_bins < 2 * (int64_t)w->dterms) return set_err(p, FSTAT_E_BAND, "%sband narrower than the 2D-bin window", tag);
+  if (!(w->t_sft > 0) || !finite(w->t_sft) || !(w->df > 0) || !finite(w->df) || !(w->f0 > 0) || !finite(w->f0) ||
+      !finite(w->fdot0) || !finite(w->dfdot) || !finite(w->t_ref))
+    return set_err(p, FSTAT_E_ARG, "%snon-finite or non-positive grid parameter", tag);
+  if (w->k_first < 0 || w->k_first + w->n_bins > 0x7fffffffLL)
+    return set_err(p, FSTAT_E_BAND, "%sband outside [0, 2^31)", tag);
+  if (w->n_sky * w->n_fd * w->n_f > ((int64_t)1 << 40)) return set_err(p, FSTAT_E_SIZE, "%stoo many templates", tag);
+  return FSTAT_OK;
+}
+
+WuDev make_dev(const fstat_plan* p, const fstat_wu* w, const fstat_out* o) {
+  WuDev v{};
+  v.sft = w->sft;
+  v.scale = w->sft_scale;
+  v.t_start = w->t_start;
+  v.pos = w->pos;
+  v.vel = w->vel;
+  v.sky = w->sky;
+  v.a = w->a;
+  v.b = w->b;
+  v.geo = (double2*)p->geo;
+  v.abcd = (double4*)p->abcd;
+  v.twoF = o ? o->twoF : nullptr;
+  v.fa = o ? (float2*)o->fa : nullptr;
+  v.fb = o ? (float2*)o->fb : nullptr;
+  v.coef = nullptr;
+  v.n_sft = w->n_sft;
+  v.n_bins = w->n_bins;
+  v.k_first = w->k_first;
+  v.n_sky = w->n_sky;
+  v.n_f = w->n_f;
+  v.n_fd = w->n_fd;
+  v.t_sft = w->t_sft;
+  v.f0 = w->f0;
+  v.df = w->df;
+  v.fdot0 = w->fdot0;
+  v.dfdot = w->dfdot;
+  v.t_ref = w->t_ref;
+  v.dterms = w->dterms;
+  v.storage = p->d.storage;
+  return v;
+}
+
+std::string class_key(const fstat_plan* p, const fstat_wu* w) {
+  char b[64];
+  snprintf(b, sizeof b, "s%d_d%d_k%d", p->d.storage, w->dterms, p->d.kernel);
+  return b;
+}
+
+Tile default_tile(const fstat_plan* p, const fstat_wu* w) {
+  (void)p;
+  Tile t{1, 16};
+  if (w->n_f <= 256) t = Tile{1, 16};
+  return t;
+}
+
+Tile pick_tile(const fstat_plan* p, const fstat_wu* w) {
+  auto it = p->tiles.find(class_key(p, w));
+  return it != p->tiles.end() ? it->second : default_tile(p, w);
+}
+
+int ensure_scratch(fstat_plan* p, const fstat_wu* w) {
+  int rc = dev_alloc(p, &p->geo, &p->geo_bytes, (size_t)w->n_sky * w->n_sft * sizeof(double2), "geometry scratch");
+  if (rc) return rc;
+  return dev_alloc(p, &p->abcd, &p->abcd_bytes, (size_t)w->n_sky * sizeof(double4), "A,B,C scratch");
+}
+
+// Geometry + band check; waits for the check.  Returns FSTAT_OK or an error.
+int run_geometry(fstat_plan* p, const WuDev& v, hipStream_t st, int idx) {
+  int rc = check_launch(p, fstat::launch_fill_int(p->status_d, 0, 1, st), "status reset");
+  if (rc) return rc;
+  rc = check_launch(p, fstat::launch_geometry(v, p->status_d, st), "geometry kernel");
+  if (rc) return rc;
+  hipError_t e = hipMemcpyAsync(p->status_h, p->status_d, sizeof(int), hipMemcpyDeviceToHost, st);
+  if (e != hipSuccess) return hip_err(p, e, "status copy");
+  e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_err(p, e, "geometry kernel");
+  const int st_bits = *p->status_h;
+  char tag[32] = "";
+  if (idx >= 0) snprintf(tag, sizeof tag, "work unit %d: ", idx);
+  if (st_bits & 1) return set_err(p, FSTAT_E_BAND, "%sa Dirichlet window [k*-D+1, k*+D] leaves the stored band", tag);
+  if (st_bits & 2) return set_err(p, FSTAT_E_ARG, "%santenna-pattern matrix is singular (A B - C^2 <= 0)", tag);
+  return FSTAT_OK;
+}
+
+int run_demod(fstat_plan* p, const WuDev& v, const Tile& t, hipStream_t st) {
+  (void)hipEventRecord(p->ev0, st);
+  int rc = check_launch(p, fstat::launch_demod(v, t, p->d.kernel, st), "demodulation kernel");
+  (void)hipEventRecord(p->ev1, st);
+  p->ev_stream = st;
+  p->timed = (rc == FSTAT_OK);
+  return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fstat_plan_create(fstat_plan** out, const fstat_desc* d) {
+  if (!out) return FSTAT_E_ARG;
+  *out = nullptr;
+  if (!d) return FSTAT_E_ARG;
+  if (d->max_sft < 1 || d->max_bins < 1 || d->max_sky < 1 || d->max_fd < 1 || d->max_f < 1) return FSTAT_E_ARG;
+  if (d->max_dterms < 1 || d->max_dterms > fstat::kMaxDterms) return FSTAT_E_ARG;
+  if (d->storage < 0 || d->storage > 2) return FSTAT_E_ARG;
+  if (d->phase_mode < 0 || d->phase_mode > 1) return FSTAT_E_ARG;
+  if (d->kernel < 0 || d->kernel > 2) return FSTAT_E_ARG;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+    (void)hipGetLastError();
+    return FSTAT_E_DEVICE;
+  }
+  int dev = d->device;
+  if (dev < 0) {
+    if (hipGetDevice(&dev) != hipSuccess) return FSTAT_E_DEVICE;
+  }
+  if (dev >= ndev) return FSTAT_E_ARG;
+  if (hipSetDevice(dev) != hipSuccess) return FSTAT_E_DEVICE;
+  fstat_plan* p = new (std::nothrow) fstat_plan();
+  if (!p) return FSTAT_E_NOMEM;
+  p->d = *d;
+  p->device = dev;
+  read_fault_env(p);
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+    delete p;
+    return FSTAT_E_DEVICE;
+  }
+  p->cu_count = prop.multiProcessorCount;
+  if (p->d.phase_mode == FSTAT_PHASE_SPLIT_FP32 || p->d.kernel == FSTAT_KERNEL_INTERP) {
+    // not built in this version of the library
+    delete p;
+    return FSTAT_E_UNSUPPORTED;
+  }
+  if (hipMalloc(&p->status_d, 64) != hipSuccess || hipHostMalloc((void**)&p->status_h, 64, hipHostMallocDefault) != hipSuccess ||
+      hipEventCreate(&p->ev0) != hipSuccess || hipEventCreate(&p->ev1) != hipSuccess) {
+    (void)hipGetLastError();
+    fstat_plan_destroy(p);
+    return FSTAT_E_NOMEM;
+  }
+  *out = p;
+  return FSTAT_OK;
+}
+
+void fstat_plan_destroy(fstat_plan* p) {
+  if (!p) return;
+  (void)hipSetDevice(p->device);
+  (void)hipDeviceSynchronize();
+  if (p->geo) (void)hipFree(p->geo);
+  if (p->abcd) (void)hipFree(p->abcd);
+  if (p->status_d) (void)hipFree(p->status_d);
+  if (p->status_h) (void)hipHostFree(p->status_h);
+  if (p->ev0) (void)hipEventDestroy(p->ev0);
+  if (p->ev1) (void)hipEventDestroy(p->ev1);
+  (void)hipGetLastError();
+  delete p;
+}
+
+int fstat_compute(fstat_plan* p, const fstat_wu* wu, const fstat_out* out, void* stream) {
+  if (!p) return FSTAT_E_ARG;
+  p->err.clear();
+  p->timed = false;
+  int rc = validate_wu(p, wu, out, -1);
+  if (rc) return rc;
+  if (hipSetDevice(p->device) != hipSuccess) return set_err(p, FSTAT_E_DEVICE, "hipSetDevice failed");
+  hipStream_t st = (hipStream_t)stream;
+  rc = ensure_scratch(p, wu);
+  if (rc) return rc;
+  WuDev v = make_dev(p, wu, out);
+  rc = run_geometry(p, v, st, -1);
+  if (rc) return rc;
+  return run_demod(p, v, pick_tile(p, wu), st);
+}
+
+int fstat_batch_compute(fstat_plan* p, const fstat_wu* wus, int32_t n_wu, const fstat_out* outs, void* stream) {
+  if (!p) return FSTAT_E_ARG;
+  p->err.clear();
+  p->timed = false;
+  if (n_wu < 0 || (n_wu > 0 && (!wus || !outs))) return set_err(p, FSTAT_E_ARG, "bad work-unit list");
+  for (int k = 0; k < n_wu; ++k) {
+    int rc = validate_wu(p, &wus[k], &outs[k], k);
+    if (rc) return rc;
+  }
+  if (hipSetDevice(p->device) != hipSuccess) return set_err(p, FSTAT_E_DEVICE, "hipSetDevice failed");
+  hipStream_t st = (hipStream_t)stream;
+  for (int k = 0; k < n_wu; ++k) {
+    int rc = ensure_scratch(p, &wus[k]);
+    if (rc) return rc;
+    WuDev v = make_dev(p, &wus[k], &outs[k]);
+    rc = run_geometry(p, v, st, k);
+    if (rc) return rc;
+    rc = run_demod(p, v, pick_tile(p, &wus[k]), st);
+    if (rc) return rc;
+  }
+  return FSTAT_OK;
+}
+
+int fstat_bins(fstat_plan* p, const fstat_wu* wu, int64_t n, const int32_t* i_sky, const int32_t* i_fd,
+               const int32_t* i_f, const int32_t* i_sft, int64_t* kstar, double* kappa, double* phi_frac,
+               void* stream) {
+  if (!p) return FSTAT_E_ARG;
+  p->err.clear();
+  if (!wu || !wu->t_start || !wu->pos || !wu->vel || !wu->sky) return set_err(p, FSTAT_E_ARG, "null geometry input");
+  if (n < 0) return set_err(p, FSTAT_E_ARG, "n < 0");
+  if (wu->n_sft < 1 || wu->n_sky < 1 || wu->n_f < 1 || wu->n_fd < 1 || !(wu->t_sft > 0))
+    return set_err(p, FSTAT_E_ARG, "bad work-unit sizes");
+  if (n > 0 && (!i_sky || !i_fd || !i_f || !i_sft || !kstar || !kappa || !phi_frac))
+    return set_err(p, FSTAT_E_ARG, "null index or output array");
+  if (hipSetDevice(p->device) != hipSuccess) return set_err(p, FSTAT_E_DEVICE, "hipSetDevice failed");
+  WuDev v = make_dev(p, wu, nullptr);
+  return check_launch(p, fstat::launch_bins(v, n, i_sky, i_fd, i_f, i_sft, kstar, kappa, phi_frac, (hipStream_t)stream),
+                      "bins kernel");
+}
+
+int fstat_autotune(fstat_plan* p, const fstat_wu* wu, const fstat_out* out, void* stream, const char* cache_path) {
+  if (!p) return FSTAT_E_ARG;
+  p->err.clear();
+  int rc = validate_wu(p, wu, out, -1);
+  if (rc) return rc;
+  const std::string key = class_key(p, wu);
+  if (cache_path) {
+    if (FILE* f = fopen(cache_path, "r")) {
+      char k[64];
+      int nf, ch;
+      while (fscanf(f, "%63s %d %d", k, &nf, &ch) == 3)
+        if (key == k) p->tiles[key] = Tile{nf, ch};
+      fclose(f);
+      if (p->tiles.count(key)) return FSTAT_OK;
+    }
+  }
+  if (hipSetDevice(p->device) != hipSuccess) return set_err(p, FSTAT_E_DEVICE, "hipSetDevice failed");
+  hipStream_t st = (hipStream_t)stream;
+  rc = ensure_scratch(p, wu);
+  if (rc) return rc;
+  WuDev v = make_dev(p, wu, out);
+  rc = run_geometry(p, v, st, -1);
+  if (rc) return rc;
+  const Tile cands[] = {{1, 16}, {1, 8}, {2, 8}, {2, 4}, {4, 4}};
+  float best = 1e30f;
+  Tile best_t = default_tile(p, wu);
+  for (const Tile& t : cands) {
+    float ms_sum = 0.f;
+    for (int rep = 0; rep < 2; ++rep) {
+      rc = run_demod(p, v, t, st);
+      if (rc) return rc;
+      hipError_t e = hipEventSynchronize(p->ev1);
+      if (e != hipSuccess) return hip_err(p, e, "autotune");
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, p->ev0, p->ev1);
+      if (rep == 1) ms_sum += ms;
+    }
+    if (ms_sum < best) {
+      best = ms_sum;
+      best_t = t;
+    }
+  }
+  p->tiles[key] = best_t;
+  if (cache_path) {
+    if (FILE* f = fopen(cache_path, "a")) {
+      fprintf(f, "%s %d %d\n", key.c_str(), best_t.nf_reg, best_t.chunk);
+      fclose(f);
+    }
+  }
+  return FSTAT_OK;
+}
+
+double fstat_last_kernel_ms(fstat_plan* p) {
+  if (!p || !p->timed) return -1.0;
+  if (hipEventSynchronize(p->ev1) != hipSuccess) return -1.0;
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, p->ev0, p->ev1) != hipSuccess) return -1.0;
+  return ms;
+}
+
+const char* fstat_strerror(int code) {
+  switch (code) {
+    case FSTAT_OK: return "ok";
+    case FSTAT_E_ARG: return "invalid argument";
+    case FSTAT_E_BAND: return "Dirichlet window outside the stored band";
+    case FSTAT_E_SIZE: return "size exceeds the plan maxima";
+    case FSTAT_E_NOMEM: return "out of memory";
+    case FSTAT_E_DEVICE: return "HIP device error";
+    case FSTAT_E_UNSUPPORTED: return "unsupported option";
+    default: return "unknown error";
+  }
+}
+
+const char* fstat_last_error(const fstat_plan* p) { return p ? p->err.c_str() : ""; }
+
+}  // extern "C"

@@ -1,0 +1,54 @@
+// Internal declarations shared by the HIP kernels and the host plan code.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fstat {
+
+// Device-side view of one work unit plus the plan scratch it uses.
+struct WuDev {
+  const void* sft;         // [n_sft][n_bins] float2 or packed 16-bit pairs
+  const float* scale;      // [n_sft] (16-bit storage)
+  const double* t_start;   // [n_sft]
+  const double* pos;       // [n_sft][3]
+  const double* vel;       // [n_sft][3]
+  const double* sky;       // [n_sky][3]
+  const float* a;          // [n_sky][n_sft]
+  const float* b;          // [n_sky][n_sft]
+  double2* geo;            // scratch [n_sky][n_sft]: (tau, Tdot)
+  double4* abcd;           // scratch [n_sky]: (A, B, C, AB - C^2)
+  float* twoF;             // [n_sky][n_fd][n_f]
+  float2* fa;              // optional, same shape
+  float2* fb;              // optional
+  const float4* coef;      // interp kernel: [n_sft][NCOEF/2][n_bins] coefficient pairs
+  int64_t n_sft, n_bins, k_first, n_sky, n_f, n_fd;
+  double t_sft, f0, df, fdot0, dfdot, t_ref;
+  int32_t dterms;
+  int32_t storage;
+};
+
+// Tile shape of the demodulation kernels.
+struct Tile {
+  int32_t nf_reg;   // frequency templates per thread (1, 2 or 4)
+  int32_t chunk;    // SFTs staged in LDS per pass
+};
+
+enum Kernel : int32_t { KERNEL_DIRECT = 1, KERNEL_INTERP = 2 };
+
+constexpr int kThreads = 256;          // work-group size of the demodulation kernels
+constexpr int kMaxDterms = 64;
+
+// Width in bins of the LDS segment staged per SFT for a tile of `nf` frequency
+// templates: the window span 2D, the templates' spread (nf bins times the
+// Doppler factor, below nf + 1 for |v| < 1e-3 c), a one-bin slack on each
+// side and rounding to a multiple of 4.
+__host__ __device__ inline int seg_width(int nf, int dterms) { return ((nf + 2 * dterms + 4) + 3) & ~3; }
+
+hipError_t launch_fill_int(int* p, int v, int n, hipStream_t s);
+hipError_t launch_geometry(const WuDev& w, int* status, hipStream_t s);
+hipError_t launch_demod(const WuDev& w, const Tile& t, int kernel, hipStream_t s);
+hipError_t launch_bins(const WuDev& w, int64_t n, const int32_t* i_sky, const int32_t* i_fd, const int32_t* i_f,
+                       const int32_t* i_sft, int64_t* kstar, double* kappa, double* phi_frac, hipStream_t s);
+size_t demod_lds_bytes(const WuDev& w, const Tile& t, int kernel);
+
+}  // namespace fstat

@@ -1,0 +1,44 @@
+"""Move a synthetic work unit to device tensors in the layout of fstat_wu."""
+from __future__ import annotations
+
+import numpy as np
+
+from .workloads import quantise_sfts
+
+
+def to_device(w, storage: str = "c64", device: str = "cuda"):
+    """Returns (paper_0904_1826_amd.WorkUnit, dequantised complex128 SFTs or
+    None).  For 16-bit storage the second value holds the exact values the
+    stored bits represent, for the oracle's arithmetic-parity comparison."""
+    import torch
+    from paper_0904_1826_amd import WorkUnit
+
+    def t(x, dt):
+        return torch.from_numpy(np.ascontiguousarray(x)).to(device=device, dtype=dt)
+
+    deq = None
+    if storage == "c64":
+        sft = t(np.ascontiguousarray(w.sft).view(np.float32).reshape(w.n_sft, w.n_bins, 2), torch.float32)
+        scale = None
+    else:
+        from .workloads import dequantise_16bit
+        stored, sc = quantise_sfts(w.sft, storage)
+        sft = torch.from_numpy(stored.view(np.int16)).to(device)
+        scale = t(sc, torch.float32)
+        deq = dequantise_16bit(stored, sc, storage)
+    wu = WorkUnit(n_det=int(w.n_det), sft=sft, sft_scale=scale, k_first=int(w.k_first), t_sft=float(w.t_sft),
+                  t_start=t(w.t_start, torch.float64), pos=t(w.pos, torch.float64), vel=t(w.vel, torch.float64),
+                  sky=t(w.sky, torch.float64), a=t(w.a, torch.float32), b=t(w.b, torch.float32), f0=float(w.f0),
+                  df=float(w.df), n_f=int(w.n_f), fdot0=float(w.fdot0), dfdot=float(w.dfdot), n_fd=int(w.n_fd),
+                  t_ref=float(w.t_ref), dterms=int(w.dterms))
+    return wu, deq
+
+
+def alloc_output(w, device: str = "cuda", fafb: bool = False):
+    import torch
+    from paper_0904_1826_amd import Output
+    shape = (w.n_sky, w.n_fd, w.n_f)
+    tw = torch.empty(shape, dtype=torch.float32, device=device)
+    fa = torch.empty(shape + (2,), dtype=torch.float32, device=device) if fafb else None
+    fb = torch.empty(shape + (2,), dtype=torch.float32, device=device) if fafb else None
+    return Output(twoF=tw, fa=fa, fb=fb)
