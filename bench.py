@@ -1,0 +1,214 @@
+#!/usr/bin/env python3
+"""Benchmark of the F-statistic demodulation on one MI355X.
+
+A step is one full pass of the hot path over one work unit: per (sky, SFT)
+geometry and band check, then the demodulation kernel (bin index, phase,
+Dirichlet window sums, a/b weighting, sum over SFTs and detectors, 2F).  The
+workload is the work-unit-shaped case: 2 detectors x 1000 SFTs of 1800 s,
+a 3600-bin band at 1000 Hz, 2000 sky points x 8 spindowns x 3600
+frequencies, Dterms = 8 (5.76e7 templates, 1.15e11 template-SFT pairs).
+Inputs are synthetic (seeded noise and injected signals) and resident in HBM
+before the timed region.  Prints one JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--forms c64,bf16,fp16]
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X (gfx950): 256 CUs at 2.4 GHz.  FP32 VALU issues 128 lane-ops per CU
+# per clock (157.3 TFLOP/s counting an FMA as two flops), FP64 64 (78.6
+# TFLOP/s), transcendental ops (sin, cos, rcp) 32.  One "slot" is one FP32
+# lane-op: an FP64 op costs 2 slots, a transcendental 4.
+N_CU, CLK, FP32_LANES = 256, 2.4e9, 128
+PEAK_SLOTS = N_CU * FP32_LANES * CLK          # 7.86e13 slot/s
+HBM_PEAK = 8.0e12
+
+
+def slots_per_pair(kernel: str, dterms: int, nfd: int = 8) -> float:
+    """Algorithmic VALU slots per (template, SFT) pair of each kernel's
+    formulation (instruction count of the arithmetic the method needs; no
+    addressing, staging or loop control)."""
+    if kernel == "direct":
+        # FP64 bin index + phase 12 ops (24), near weights 19, far terms
+        # (2D-2) x 6, two fraction folds 12, near terms 8, sign 3,
+        # exp(-2 pi i phi) 12, Fa/Fb 4
+        return 12 * dterms + 70
+    if kernel == "interp":
+        # FP64 Dphi 3 ops + k* + kappa + conversion (13 with u), degree-7
+        # complex Horner 14, phase factor product 4 + rotation 4, Fa/Fb 4;
+        # frac(tau f) and its sin/cos (14) shared by the nfd spindowns of a thread
+        return 39 + 14.0 / nfd
+    raise ValueError(kernel)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("fstat_kernels.hip", "fstat_internal.h"):
+        with open(os.path.join(ROOT, "paper_0904_1826_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel_name: str, workload: str):
+    """HBM bytes per launch of the dominant kernel from the committed
+    rocprofv3 counter summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    e = d.get(f"{kernel_name}:{workload}")
+    if not e or e.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def cpu_baseline(w, budget_s: float):
+    """The FP64 oracle on the first sky points of the same work unit (every
+    spindown, frequency and SFT), as many as fit in about `budget_s`."""
+    import numpy as np
+    import oracle
+    nthreads = min(16, os.cpu_count() or 1)
+    prep = oracle.Prepared(w)
+    done_pairs, elapsed, n_sky = 0, 0.0, 0
+    while elapsed < budget_s and n_sky < w.n_sky:
+        tmpl = oracle.all_templates(w, [n_sky])
+        t0 = time.perf_counter()
+        prep.fstat(tmpl, nthreads=nthreads)
+        elapsed += time.perf_counter() - t0
+        done_pairs += len(tmpl[0]) * w.n_sft
+        n_sky += 1
+    return {"value": done_pairs / elapsed, "unit": "templates*SFTs/s", "cores": nthreads, "kind": "oracle",
+            "sample": f"sky points 0..{n_sky - 1} of the same work unit: {n_sky * w.n_fd * w.n_f} templates "
+                      f"x {w.n_sft} SFTs, FP64, {elapsed:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--forms", default="c64,bf16,fp16")
+    ap.add_argument("--kernel", default="auto", help="auto (= interp), interp or direct")
+    ap.add_argument("--compare-direct", type=int, default=2,
+                    help="also time this many steps of the direct kernel on complex64 storage")
+    ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="run one device-to-device copy of this many MiB first (HBM counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: the F-statistic shards by work unit or sky point with no exchange, "
+              "and this build runs and reports a single MI355X only (use --gpus 1).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import synth
+    from synth.device import to_device, alloc_output
+    import paper_0904_1826_amd as P
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.calibrate_copy_mib > 0:
+        n = args.calibrate_copy_mib << 20
+        src = torch.ones(n // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] calibration copy: {n} bytes read, {n} bytes written", file=sys.stderr, flush=True)
+        del src, dst
+    t0 = time.time()
+    w = synth.make_config(1)
+    print(f"[bench] workload {w.name}: {w.n_sft} SFTs x {w.n_bins} bins, {w.n_templates} templates "
+          f"(generated in {time.time() - t0:.1f} s)", file=sys.stderr, flush=True)
+    pairs = w.n_templates * w.n_sft
+    forms = [f for f in args.forms.split(",") if f]
+    results = {}
+    for form in forms:
+        wu, _ = to_device(w, form)
+        out = alloc_output(w)
+        torch.cuda.synchronize()
+        with P.Plan(max_sft=w.n_sft, max_bins=w.n_bins, max_sky=w.n_sky, max_fd=w.n_fd, max_f=w.n_f,
+                    max_dterms=w.dterms, storage=form, kernel=args.kernel) as plan:
+            steps = args.steps if form == forms[0] else max(2, args.steps // 2)
+            for _ in range(args.warmup):
+                plan.compute(wu, out)
+            torch.cuda.synchronize()
+            kms = []
+            t_start = time.perf_counter()
+            for _ in range(steps):
+                plan.compute(wu, out)
+                kms.append(plan.last_kernel_ms())
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t_start
+        results[form] = {"steps": steps, "ms_per_step": 1e3 * el / steps, "value": steps * pairs / el,
+                         "kernel_ms": float(np.mean(kms))}
+        print(f"[bench] {form}: {results[form]}", file=sys.stderr, flush=True)
+        del wu, out
+        torch.cuda.empty_cache()
+
+    kernel = "direct" if args.kernel == "direct" else "interp"     # the library resolves auto to interp
+    kernels = {}
+    if args.compare_direct > 0 and kernel != "direct":
+        wu, _ = to_device(w, "c64")
+        out = alloc_output(w)
+        with P.Plan(max_sft=w.n_sft, max_bins=w.n_bins, max_sky=w.n_sky, max_fd=w.n_fd, max_f=w.n_f,
+                    max_dterms=w.dterms, storage="c64", kernel="direct") as plan:
+            plan.compute(wu, out)
+            torch.cuda.synchronize()
+            kms = []
+            t_start = time.perf_counter()
+            for _ in range(args.compare_direct):
+                plan.compute(wu, out)
+                kms.append(plan.last_kernel_ms())
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t_start
+        kernels["direct"] = {"value": args.compare_direct * pairs / el, "kernel_ms": float(np.mean(kms)),
+                             "roofline_frac": slots_per_pair("direct", w.dterms) * pairs / (np.mean(kms) * 1e-3) / PEAK_SLOTS}
+        print(f"[bench] direct c64: {kernels['direct']}", file=sys.stderr, flush=True)
+        del wu, out
+        torch.cuda.empty_cache()
+    main_form = forms[0]
+    r = results[main_form]
+    slots = slots_per_pair(kernel, w.dterms) * pairs
+    achieved = slots / (r["kernel_ms"] * 1e-3)
+    line = {
+        "metric": "templates*SFTs/s for 2F",
+        "value": r["value"],
+        "unit": "templates*SFTs/s",
+        "n_gpus": 1,
+        "steps": r["steps"],
+        "warmup": args.warmup,
+        "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "n_det": w.n_det, "n_sft": w.n_sft, "n_bins": w.n_bins, "n_sky": w.n_sky,
+                   "n_fd": w.n_fd, "n_f": w.n_f, "dterms": w.dterms, "storage": main_form, "phase": "fp64",
+                   "kernel": kernel, "templates": w.n_templates, "pairs_per_step": pairs},
+        "forms": {k: {"value": v["value"], "ms_per_step": v["ms_per_step"], "kernel_ms": v["kernel_ms"]}
+                  for k, v in results.items()},
+        "kernels": kernels,
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12, "unit": "TOP/s",
+                     "frac": achieved / PEAK_SLOTS, "traffic": measured_traffic(f"demod_{kernel}", "config1"),
+                     "kernel": f"demod_{kernel}", "slots_per_pair": slots_per_pair(kernel, w.dterms),
+                     "kernel_ms": r["kernel_ms"]},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -98,12 +98,23 @@ def all_templates(w, sky_indices=None):
     return (s.ravel().astype(np.int32), i.ravel().astype(np.int32), j.ravel().astype(np.int32))
 
 
-def fstat(w, templates=None, *, sft: Optional[np.ndarray] = None, nthreads: Optional[int] = None):
+class Prepared:
+    """A work unit converted once to the oracle's FP64 layout, for repeated calls."""
+
+    def __init__(self, w, sft: Optional[np.ndarray] = None):
+        self.w = w
+        self.packed = _Packed(w, sft)
+
+    def fstat(self, templates=None, nthreads: Optional[int] = None):
+        return fstat(self.w, templates, nthreads=nthreads, _packed=self.packed)
+
+
+def fstat(w, templates=None, *, sft: Optional[np.ndarray] = None, nthreads: Optional[int] = None, _packed=None):
     """2F (FP64), Fa, Fb (complex128) of the listed templates.  `sft` replaces
     the workload's SFT values (e.g. with exactly dequantised 16-bit storage).
     Raises ValueError naming the first template whose window leaves the band."""
     lib = _load()
-    pk = _Packed(w, sft)
+    pk = _packed if _packed is not None else _Packed(w, sft)
     ts, ti, tj = all_templates(w) if templates is None else (np.ascontiguousarray(t, dtype=np.int32) for t in templates)
     n = len(ts)
     twoF = np.empty(n, dtype=np.float64)

@@ -28,8 +28,15 @@ struct fstat_plan {
   size_t geo_bytes = 0;
   void* abcd = nullptr;
   size_t abcd_bytes = 0;
-  int* status_d = nullptr;
-  int* status_h = nullptr;  // pinned
+  fstat::GeoStatus* status_d = nullptr;
+  fstat::GeoStatus* status_h = nullptr;  // pinned
+  double max_abs_tau = 0.0;               // from the last geometry pass
+  // interp kernel: coefficient scratch and per-Dterms polynomial tables
+  void* coef = nullptr;
+  size_t coef_bytes = 0;
+  void* acc = nullptr;
+  size_t acc_bytes = 0;
+  std::map<int, double*> ctab;
   // timing
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   hipStream_t ev_stream = nullptr;
@@ -136,7 +143,10 @@ WuDev make_dev(const fstat_plan* p, const fstat_wu* w, const fstat_out* o) {
   v.twoF = o ? o->twoF : nullptr;
   v.fa = o ? (float2*)o->fa : nullptr;
   v.fb = o ? (float2*)o->fb : nullptr;
-  v.coef = nullptr;
+  v.coef = (float4*)p->coef;
+  v.acc = (float4*)p->acc;
+  auto it = p->ctab.find(w->dterms);
+  v.ctab = it != p->ctab.end() ? it->second : nullptr;
   v.n_sft = w->n_sft;
   v.n_bins = w->n_bins;
   v.k_first = w->k_first;
@@ -154,41 +164,125 @@ WuDev make_dev(const fstat_plan* p, const fstat_wu* w, const fstat_out* o) {
   return v;
 }
 
+int resolved_kernel(const fstat_plan* p) {
+  return p->d.kernel == FSTAT_KERNEL_DIRECT ? fstat::KERNEL_DIRECT : fstat::KERNEL_INTERP;
+}
+
+double host_sinc(double x) { return x == 0.0 ? 1.0 : sin(M_PI * x) / (M_PI * x); }
+
+// Monomial coefficients in u = 2 kappa - 1 of the degree-(kCoef-1) Chebyshev
+// projection of sinc(kappa + m) on kappa in [0, 1], for m = -D .. D-1:
+// Chebyshev coefficients from 64 Chebyshev nodes (discrete cosine sums),
+// then the three-term recurrence T_{j+1} = 2u T_j - T_{j-1} to monomials.
+std::vector<double> sinc_poly_table(int D) {
+  const int N = 64, P = fstat::kCoef;
+  std::vector<double> tab((size_t)2 * D * P, 0.0);
+  std::vector<std::vector<double>> Tm(P, std::vector<double>(P, 0.0));
+  Tm[0][0] = 1.0;
+  if (P > 1) Tm[1][1] = 1.0;
+  for (int j = 1; j + 1 < P; ++j)
+    for (int q = 0; q < P; ++q) Tm[j + 1][q] = (q > 0 ? 2.0 * Tm[j][q - 1] : 0.0) - Tm[j - 1][q];
+  for (int m = -D; m < D; ++m) {
+    std::vector<double> a(P, 0.0);
+    for (int j = 0; j < P; ++j) {
+      double acc = 0.0;
+      for (int k = 0; k < N; ++k) {
+        const double th = M_PI * (k + 0.5) / N;
+        const double kap = 0.5 * (cos(th) + 1.0);
+        acc += host_sinc(kap + m) * cos(j * th);
+      }
+      a[j] = (j == 0 ? 1.0 : 2.0) * acc / N;
+    }
+    double* row = &tab[(size_t)(m + D) * P];
+    for (int j = 0; j < P; ++j)
+      for (int q = 0; q < P; ++q) row[q] += a[j] * Tm[j][q];
+  }
+  return tab;
+}
+
+int ensure_ctab(fstat_plan* p, int D) {
+  if (p->ctab.count(D)) return FSTAT_OK;
+  std::vector<double> tab = sinc_poly_table(D);
+  void* d = nullptr;
+  size_t have = 0;
+  int rc = dev_alloc(p, &d, &have, tab.size() * sizeof(double), "polynomial table");
+  if (rc) return rc;
+  hipError_t e = hipMemcpy(d, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(d);
+    return hip_err(p, e, "polynomial table upload");
+  }
+  p->ctab[D] = (double*)d;
+  return FSTAT_OK;
+}
+
 std::string class_key(const fstat_plan* p, const fstat_wu* w) {
   char b[64];
   snprintf(b, sizeof b, "s%d_d%d_k%d", p->d.storage, w->dterms, p->d.kernel);
   return b;
 }
 
+// LDS slice width (bins) of the interp kernel: 256 frequency templates span
+// 255 df T Tdot bins, the spindowns of a block shift k* by up to
+// |dfdot| (NFD-1) max|tau| T Tdot more; plus slack, rounded to 4.
+// Lanes whose window falls outside the slice read their coefficients from
+// global memory instead, so a narrower slice costs speed, not correctness;
+// the slice is capped so that one work-group uses at most 64 KB of LDS.
+int interp_seg(const fstat_plan* p, const fstat_wu* w, int nfd, int chunk) {
+  const double tdot = 1.001;
+  const double spread = (255.0 * w->df + fabs(w->dfdot) * (nfd - 1) * p->max_abs_tau) * w->t_sft * tdot;
+  const double width = 256.0 + 6.0 + ceil(spread - 255.0 > 0 ? spread - 255.0 : 0.0);
+  const int cap = fstat::interp_max_seg(chunk);
+  int W = width > cap ? cap : (int)width;
+  return W & ~3;
+}
+
 Tile default_tile(const fstat_plan* p, const fstat_wu* w) {
-  (void)p;
-  Tile t{1, 16};
-  if (w->n_f <= 256) t = Tile{1, 16};
-  return t;
+  if (resolved_kernel(p) == fstat::KERNEL_INTERP) {
+    const int nfd = w->n_fd >= 8 ? 8 : (w->n_fd >= 4 ? 4 : (w->n_fd >= 2 ? 2 : 1));
+    return Tile{nfd, nfd >= 4 ? 1 : 2, 0, 64};
+  }
+  return Tile{1, 16, 0, 0};
 }
 
 Tile pick_tile(const fstat_plan* p, const fstat_wu* w) {
   auto it = p->tiles.find(class_key(p, w));
-  return it != p->tiles.end() ? it->second : default_tile(p, w);
+  Tile t = it != p->tiles.end() ? it->second : default_tile(p, w);
+  if (resolved_kernel(p) == fstat::KERNEL_INTERP) t.seg = interp_seg(p, w, t.nf_reg, t.chunk);
+  return t;
 }
 
 int ensure_scratch(fstat_plan* p, const fstat_wu* w) {
   int rc = dev_alloc(p, &p->geo, &p->geo_bytes, (size_t)w->n_sky * w->n_sft * sizeof(double2), "geometry scratch");
   if (rc) return rc;
-  return dev_alloc(p, &p->abcd, &p->abcd_bytes, (size_t)w->n_sky * sizeof(double4), "A,B,C scratch");
+  rc = dev_alloc(p, &p->abcd, &p->abcd_bytes, (size_t)w->n_sky * sizeof(double4), "A,B,C scratch");
+  if (rc) return rc;
+  if (resolved_kernel(p) == fstat::KERNEL_INTERP) {
+    rc = dev_alloc(p, &p->coef, &p->coef_bytes, (size_t)w->n_sft * w->n_bins * fstat::kCoefPairs * sizeof(float4),
+                   "coefficient scratch");
+    if (rc) return rc;
+    rc = dev_alloc(p, &p->acc, &p->acc_bytes, (size_t)w->n_sky * w->n_fd * w->n_f * sizeof(float4),
+                   "accumulator scratch");
+    if (rc) return rc;
+    rc = ensure_ctab(p, w->dterms);
+  }
+  return rc;
 }
 
 // Geometry + band check; waits for the check.  Returns FSTAT_OK or an error.
 int run_geometry(fstat_plan* p, const WuDev& v, hipStream_t st, int idx) {
-  int rc = check_launch(p, fstat::launch_fill_int(p->status_d, 0, 1, st), "status reset");
+  int rc = check_launch(p, fstat::launch_fill_int((int*)p->status_d, 0, sizeof(fstat::GeoStatus) / sizeof(int), st),
+                        "status reset");
   if (rc) return rc;
   rc = check_launch(p, fstat::launch_geometry(v, p->status_d, st), "geometry kernel");
   if (rc) return rc;
-  hipError_t e = hipMemcpyAsync(p->status_h, p->status_d, sizeof(int), hipMemcpyDeviceToHost, st);
+  hipError_t e = hipMemcpyAsync(p->status_h, p->status_d, sizeof(fstat::GeoStatus), hipMemcpyDeviceToHost, st);
   if (e != hipSuccess) return hip_err(p, e, "status copy");
   e = hipStreamSynchronize(st);
   if (e != hipSuccess) return hip_err(p, e, "geometry kernel");
-  const int st_bits = *p->status_h;
+  const int st_bits = p->status_h->flags;
+  unsigned long long tb = p->status_h->max_abs_tau_bits;
+  memcpy(&p->max_abs_tau, &tb, sizeof tb);
   char tag[32] = "";
   if (idx >= 0) snprintf(tag, sizeof tag, "work unit %d: ", idx);
   if (st_bits & 1) return set_err(p, FSTAT_E_BAND, "%sa Dirichlet window [k*-D+1, k*+D] leaves the stored band", tag);
@@ -197,8 +291,13 @@ int run_geometry(fstat_plan* p, const WuDev& v, hipStream_t st, int idx) {
 }
 
 int run_demod(fstat_plan* p, const WuDev& v, const Tile& t, hipStream_t st) {
+  const int kernel = resolved_kernel(p);
+  if (kernel == fstat::KERNEL_INTERP) {
+    int rc = check_launch(p, fstat::launch_coef(v, st), "coefficient kernel");
+    if (rc) return rc;
+  }
   (void)hipEventRecord(p->ev0, st);
-  int rc = check_launch(p, fstat::launch_demod(v, t, p->d.kernel, st), "demodulation kernel");
+  int rc = check_launch(p, fstat::launch_demod(v, t, kernel, st), "demodulation kernel");
   (void)hipEventRecord(p->ev1, st);
   p->ev_stream = st;
   p->timed = (rc == FSTAT_OK);
@@ -240,12 +339,13 @@ int fstat_plan_create(fstat_plan** out, const fstat_desc* d) {
     return FSTAT_E_DEVICE;
   }
   p->cu_count = prop.multiProcessorCount;
-  if (p->d.phase_mode == FSTAT_PHASE_SPLIT_FP32 || p->d.kernel == FSTAT_KERNEL_INTERP) {
+  if (p->d.phase_mode == FSTAT_PHASE_SPLIT_FP32) {
     // not built in this version of the library
     delete p;
     return FSTAT_E_UNSUPPORTED;
   }
-  if (hipMalloc(&p->status_d, 64) != hipSuccess || hipHostMalloc((void**)&p->status_h, 64, hipHostMallocDefault) != hipSuccess ||
+  if (hipMalloc((void**)&p->status_d, sizeof(fstat::GeoStatus)) != hipSuccess ||
+      hipHostMalloc((void**)&p->status_h, sizeof(fstat::GeoStatus), hipHostMallocDefault) != hipSuccess ||
       hipEventCreate(&p->ev0) != hipSuccess || hipEventCreate(&p->ev1) != hipSuccess) {
     (void)hipGetLastError();
     fstat_plan_destroy(p);
@@ -261,6 +361,9 @@ void fstat_plan_destroy(fstat_plan* p) {
   (void)hipDeviceSynchronize();
   if (p->geo) (void)hipFree(p->geo);
   if (p->abcd) (void)hipFree(p->abcd);
+  if (p->coef) (void)hipFree(p->coef);
+  if (p->acc) (void)hipFree(p->acc);
+  for (auto& kv : p->ctab) (void)hipFree(kv.second);
   if (p->status_d) (void)hipFree(p->status_d);
   if (p->status_h) (void)hipHostFree(p->status_h);
   if (p->ev0) (void)hipEventDestroy(p->ev0);
@@ -334,9 +437,9 @@ int fstat_autotune(fstat_plan* p, const fstat_wu* wu, const fstat_out* out, void
   if (cache_path) {
     if (FILE* f = fopen(cache_path, "r")) {
       char k[64];
-      int nf, ch;
-      while (fscanf(f, "%63s %d %d", k, &nf, &ch) == 3)
-        if (key == k) p->tiles[key] = Tile{nf, ch};
+      int nf, ch, sb;
+      while (fscanf(f, "%63s %d %d %d", k, &nf, &ch, &sb) == 4)
+        if (key == k) p->tiles[key] = Tile{nf, ch, 0, sb};
       fclose(f);
       if (p->tiles.count(key)) return FSTAT_OK;
     }
@@ -348,10 +451,19 @@ int fstat_autotune(fstat_plan* p, const fstat_wu* wu, const fstat_out* out, void
   WuDev v = make_dev(p, wu, out);
   rc = run_geometry(p, v, st, -1);
   if (rc) return rc;
-  const Tile cands[] = {{1, 16}, {1, 8}, {2, 8}, {2, 4}, {4, 4}};
+  std::vector<Tile> cands;
+  if (resolved_kernel(p) == fstat::KERNEL_INTERP) {
+    for (int nfd : {8, 4, 2, 1})
+      for (int ch : {1, 2})
+        for (int sb : {32, 64, 128, 0})
+          if ((nfd <= 2 * wu->n_fd || nfd == 1) && (nfd >= 4 || ch == 2)) cands.push_back(Tile{nfd, ch, 0, sb});
+  } else {
+    cands = {Tile{1, 16, 0, 0}, Tile{1, 8, 0, 0}, Tile{2, 8, 0, 0}, Tile{2, 4, 0, 0}, Tile{4, 4, 0, 0}};
+  }
   float best = 1e30f;
   Tile best_t = default_tile(p, wu);
-  for (const Tile& t : cands) {
+  for (Tile t : cands) {
+    if (resolved_kernel(p) == fstat::KERNEL_INTERP) t.seg = interp_seg(p, wu, t.nf_reg, t.chunk);
     float ms_sum = 0.f;
     for (int rep = 0; rep < 2; ++rep) {
       rc = run_demod(p, v, t, st);
@@ -362,6 +474,9 @@ int fstat_autotune(fstat_plan* p, const fstat_wu* wu, const fstat_out* out, void
       (void)hipEventElapsedTime(&ms, p->ev0, p->ev1);
       if (rep == 1) ms_sum += ms;
     }
+    if (getenv("FSTAT_TUNE_VERBOSE"))
+      fprintf(stderr, "[fstat autotune] %s tile nf_reg=%d chunk=%d seg=%d sblock=%d: %.3f ms\n", key.c_str(), t.nf_reg,
+              t.chunk, t.seg, t.sblock, ms_sum);
     if (ms_sum < best) {
       best = ms_sum;
       best_t = t;
@@ -370,7 +485,7 @@ int fstat_autotune(fstat_plan* p, const fstat_wu* wu, const fstat_out* out, void
   p->tiles[key] = best_t;
   if (cache_path) {
     if (FILE* f = fopen(cache_path, "a")) {
-      fprintf(f, "%s %d %d\n", key.c_str(), best_t.nf_reg, best_t.chunk);
+      fprintf(f, "%s %d %d %d\n", key.c_str(), best_t.nf_reg, best_t.chunk, best_t.sblock);
       fclose(f);
     }
   }

@@ -20,7 +20,9 @@ struct WuDev {
   float* twoF;             // [n_sky][n_fd][n_f]
   float2* fa;              // optional, same shape
   float2* fb;              // optional
-  const float4* coef;      // interp kernel: [n_sft][NCOEF/2][n_bins] coefficient pairs
+  float4* coef;            // interp kernel scratch: [n_sft][kCoefPairs][n_bins] coefficient pairs
+  const double* ctab;      // interp kernel: [2D][kCoef] polynomial coefficients of sinc(kappa+m)
+  float4* acc;             // interp kernel scratch: running (Fa, Fb) per template between SFT blocks
   int64_t n_sft, n_bins, k_first, n_sky, n_f, n_fd;
   double t_sft, f0, df, fdot0, dfdot, t_ref;
   int32_t dterms;
@@ -29,11 +31,27 @@ struct WuDev {
 
 // Tile shape of the demodulation kernels.
 struct Tile {
-  int32_t nf_reg;   // frequency templates per thread (1, 2 or 4)
+  int32_t nf_reg;   // direct: frequency templates per thread (1, 2 or 4); interp: spindowns per thread
   int32_t chunk;    // SFTs staged in LDS per pass
+  int32_t seg;      // interp: LDS segment width in bins (0: derived)
+  int32_t sblock;   // interp: SFTs per launch (the SFT loop is split into launches of this many SFTs)
 };
 
 enum Kernel : int32_t { KERNEL_DIRECT = 1, KERNEL_INTERP = 2 };
+
+// Interp kernel: each window weight sinc(kappa + m), kappa in [0, 1), is
+// replaced by a degree-7 polynomial in u = 2 kappa - 1 (Chebyshev projection,
+// max error 4.3e-7 over the interval), so the whole window sum of bin k is a
+// degree-7 polynomial in u with kCoef complex coefficients per bin.
+constexpr int kCoef = 8;
+constexpr int kCoefPairs = kCoef / 2;
+
+// Geometry pass results read back by the host.
+struct GeoStatus {
+  int flags;                  // bit 1: window outside the band; bit 2: AB - C^2 <= 0
+  int pad;
+  unsigned long long max_abs_tau_bits;   // max |tau| over (sky, SFT), as FP64 bits
+};
 
 constexpr int kThreads = 256;          // work-group size of the demodulation kernels
 constexpr int kMaxDterms = 64;
@@ -45,10 +63,13 @@ constexpr int kMaxDterms = 64;
 __host__ __device__ inline int seg_width(int nf, int dterms) { return ((nf + 2 * dterms + 4) + 3) & ~3; }
 
 hipError_t launch_fill_int(int* p, int v, int n, hipStream_t s);
-hipError_t launch_geometry(const WuDev& w, int* status, hipStream_t s);
+hipError_t launch_geometry(const WuDev& w, GeoStatus* status, hipStream_t s);
+hipError_t launch_coef(const WuDev& w, hipStream_t s);
 hipError_t launch_demod(const WuDev& w, const Tile& t, int kernel, hipStream_t s);
+int interp_launches(const WuDev& w, const Tile& t);
 hipError_t launch_bins(const WuDev& w, int64_t n, const int32_t* i_sky, const int32_t* i_fd, const int32_t* i_f,
                        const int32_t* i_sft, int64_t* kstar, double* kappa, double* phi_frac, hipStream_t s);
 size_t demod_lds_bytes(const WuDev& w, const Tile& t, int kernel);
+int interp_max_seg(int chunk);
 
 }  // namespace fstat

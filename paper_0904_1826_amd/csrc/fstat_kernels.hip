@@ -70,19 +70,20 @@ __device__ __forceinline__ double warp_sum(double v) {
 // (A, B, C, AB - C^2), and sets status bit 1 if some window of the template
 // grid leaves the band, bit 2 if AB - C^2 <= 0.  k* is monotone in f and in
 // fdot (every rounding step is monotone), so the grid corners bound it.
-__global__ __launch_bounds__(256) void geometry_kernel(WuDev w, int* status) {
-  __shared__ double red[3][4];
+__global__ __launch_bounds__(256) void geometry_kernel(WuDev w, GeoStatus* status) {
+  __shared__ double red[4][4];
   const double T = w.t_sft;
   const double f_lo = template_f(w, 0), f_hi = template_f(w, w.n_f - 1);
   const double fd_a = template_fd(w, 0), fd_b = template_fd(w, w.n_fd - 1);
   const double band_lo = (double)w.k_first, band_hi = (double)(w.k_first + w.n_bins - 1);
   const int D = w.dterms;
   for (int64_t s = blockIdx.x; s < w.n_sky; s += gridDim.x) {
-    double A = 0.0, B = 0.0, C = 0.0;
+    double A = 0.0, B = 0.0, C = 0.0, tmax = 0.0;
     int bad = 0;
     for (int64_t al = threadIdx.x; al < w.n_sft; al += blockDim.x) {
       double tau, tdot;
       sft_geometry(w, s, al, tau, tdot);
+      tmax = fmax(tmax, fabs(tau));
       w.geo[s * w.n_sft + al] = make_double2(tau, tdot);
       const double a = w.a[s * w.n_sft + al], b = w.b[s * w.n_sft + al];
       A += a * a;
@@ -101,8 +102,9 @@ __global__ __launch_bounds__(256) void geometry_kernel(WuDev w, int* status) {
     A = warp_sum(A);
     B = warp_sum(B);
     C = warp_sum(C);
+    for (int o = 32; o > 0; o >>= 1) tmax = fmax(tmax, __shfl_xor(tmax, o, 64));
     const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
-    if (ln == 0) { red[0][wv] = A; red[1][wv] = B; red[2][wv] = C; }
+    if (ln == 0) { red[0][wv] = A; red[1][wv] = B; red[2][wv] = C; red[3][wv] = tmax; }
     const int any_bad = __syncthreads_or(bad);
     if (threadIdx.x == 0) {
       A = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
@@ -112,7 +114,9 @@ __global__ __launch_bounds__(256) void geometry_kernel(WuDev w, int* status) {
       w.abcd[s] = make_double4(A, B, C, Dd);
       int flags = any_bad ? 1 : 0;
       if (!(Dd > 0.0)) flags |= 2;
-      if (flags) atomicOr(status, flags);
+      if (flags) atomicOr(&status->flags, flags);
+      const double tm = fmax(fmax(red[3][0], red[3][1]), fmax(red[3][2], red[3][3]));
+      atomicMax(&status->max_abs_tau_bits, (unsigned long long)__double_as_longlong(tm));
     }
     __syncthreads();
   }
@@ -209,6 +213,19 @@ struct GlobalWindow {
   __device__ __forceinline__ float2 operator()(int b) const { return load_bin(*w, al, col0 + b); }
 };
 
+// Window sum read straight from global memory, for a lane whose window is
+// outside the LDS slice (the asm statement keeps its loads from being merged
+// with the LDS path into generic loads).
+template <int DT>
+__device__ __forceinline__ float2 dirichlet_sum_global(const WuDev& w, int64_t al, int64_t col, int D, float kap,
+                                                       float om) {
+  col = col < 0 ? 0 : col;                          // memory safety only: the band
+  if (col > w.n_bins - 2 * D) col = w.n_bins - 2 * D;   // check rules this out
+  const float2 r = dirichlet_sum<DT>(GlobalWindow{&w, al, col}, D, kap, om);
+  __asm__ volatile("" ::: "memory");
+  return r;
+}
+
 // --------------------------------------------------------- demodulation
 // One work-group per tile of (sky s, spindown i, kThreads * NF frequencies);
 // thread t owns frequencies j0 + t + kThreads * r, r < NF.  SFTs are taken
@@ -223,12 +240,14 @@ __global__ __launch_bounds__(kThreads) void demod_direct_kernel(WuDev w) {
   __shared__ int64_t lo_col[CH];
   const int D = DT > 0 ? DT : w.dterms;
   const int W = seg_width(kThreads * NF, D);
-  const int64_t n_ft = (w.n_f + kThreads * NF - 1) / (kThreads * NF);
+  // Sky point fastest: work-groups resident at the same time share a
+  // frequency tile, so their SFT slices (offset only by the Doppler shift of
+  // each sky point) overlap and stay in L2.
   int64_t bid = blockIdx.x;
-  const int64_t ft = bid % n_ft;
-  bid /= n_ft;
+  const int64_t s = bid % w.n_sky;
+  bid /= w.n_sky;
   const int64_t i = bid % w.n_fd;
-  const int64_t s = bid / w.n_fd;
+  const int64_t ft = bid / w.n_fd;
   const int tid = threadIdx.x;
   const int64_t j0 = ft * (kThreads * NF);
   const double T = w.t_sft;
@@ -277,7 +296,7 @@ __global__ __launch_bounds__(kThreads) void demod_direct_kernel(WuDev w) {
       const float a = arow[al], b = brow[al];
       const double gf = fd * g.x;                   // fdot * tau
       const double gh = hfd * g.x;                  // (fdot / 2) * tau
-      const int64_t lo = lo_col[c];
+      const int base = (int)(w.k_first + lo_col[c]);   // absolute bin of slice column 0
 #pragma unroll
       for (int r = 0; r < NF; ++r) {
         const double dphi = bin_position(f[r], gf, g.y, T);
@@ -287,15 +306,12 @@ __global__ __launch_bounds__(kThreads) void demod_direct_kernel(WuDev w) {
         const float om = (float)(1.0 - kap64);
         const double phi = g.x * (f[r] + gh);
         const float ph = (float)fract64(phi);
-        const int64_t col = (int64_t)kst - (D - 1) - w.k_first;
-        const int64_t off = col - lo;
+        const int off = kst - (D - 1) - base;     // first window bin within the LDS slice
         float2 S;
         if (off >= 0 && off + 2 * D <= W) {
           S = dirichlet_sum<DT>(LdsWindow{seg + c * W + off}, D, kap, om);
         } else {
-          int64_t cc = col < 0 ? 0 : col;           // memory safety only: the band
-          if (cc > w.n_bins - 2 * D) cc = w.n_bins - 2 * D;   // check rules this out
-          S = dirichlet_sum<DT>(GlobalWindow{&w, al, cc}, D, kap, om);
+          S = dirichlet_sum_global<DT>(w, al, (int64_t)kst - (D - 1) - w.k_first, D, kap, om);
         }
         const uint32_t sg = (uint32_t)kst << 31;   // (-1)^k*
         S.x = __uint_as_float(__float_as_uint(S.x) ^ sg);
@@ -319,6 +335,295 @@ __global__ __launch_bounds__(kThreads) void demod_direct_kernel(WuDev w) {
     const double fa2 = ar * ar + ai * ai, fb2 = br * br + bi * bi, re = ar * br + ai * bi;
     const double two_f = 2.0 * (abcd.y * fa2 + abcd.x * fb2 - 2.0 * abcd.z * re) / abcd.w;
     const int64_t o = (s * w.n_fd + i) * w.n_f + j;
+    w.twoF[o] = (float)two_f;
+    if (w.fa) w.fa[o] = make_float2(far[r], fai[r]);
+    if (w.fb) w.fb[o] = make_float2(fbr[r], fbi[r]);
+  }
+}
+
+
+// ------------------------------------------- interpolated window (INTERP)
+// The window sum of bin k as a function of kappa,
+//   G_k(kappa) = sum_{m=-D}^{D-1} (-1)^(k-m) x[k-m] sinc(kappa + m),
+// is an entire function of kappa; on [0, 1) it is replaced by the polynomial
+// sum_p c[k][p] u^p, u = 2 kappa - 1, whose coefficients
+//   c[k][p] = sum_m (-1)^(k-m) x[k-m] t[m][p]
+// follow from the per-term polynomials t[m][.] of sinc(kappa + m).  This pass
+// computes c for every bin of every SFT (in FP64, stored as FP32 pairs
+// (c_p, c_p+1) per float4); the demodulation kernel then evaluates one
+// polynomial per (template, SFT) pair instead of 2D weighted terms.  Bins
+// whose window would leave the band get zeros (no valid k* selects them).
+__global__ __launch_bounds__(256) void coef_kernel(WuDev w) {
+  __shared__ float2 xs[256 + 2 * kMaxDterms];
+  __shared__ double tab[2 * kMaxDterms * kCoef];
+  const int D = w.dterms;
+  const int64_t n_cc = (w.n_bins + 255) / 256;
+  const int64_t al = blockIdx.x / n_cc;
+  const int64_t c0 = (blockIdx.x % n_cc) * 256;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < 2 * D * kCoef; e += 256) tab[e] = w.ctab[e];
+  for (int e = tid; e < 256 + 2 * D; e += 256) {
+    const int64_t n = c0 - D + e;
+    float2 v = make_float2(0.f, 0.f);
+    if (n >= 0 && n < w.n_bins) {
+      v = load_bin(w, al, n);
+      if ((w.k_first + n) & 1) { v.x = -v.x; v.y = -v.y; }   // (-1)^(absolute bin)
+    }
+    xs[e] = v;
+  }
+  __syncthreads();
+  const int64_t c = c0 + tid;
+  if (c >= w.n_bins) return;
+  double cr[kCoef], ci[kCoef];
+#pragma unroll
+  for (int p = 0; p < kCoef; ++p) cr[p] = ci[p] = 0.0;
+  if (c >= D - 1 && c <= w.n_bins - 1 - D) {
+    for (int m = -D; m < D; ++m) {
+      const float2 x = xs[tid + D - m];                         // bin k - m
+      const double* t = tab + (m + D) * kCoef;
+#pragma unroll
+      for (int p = 0; p < kCoef; ++p) {
+        cr[p] = __builtin_fma((double)x.x, t[p], cr[p]);
+        ci[p] = __builtin_fma((double)x.y, t[p], ci[p]);
+      }
+    }
+  }
+  float4* dst = w.coef + (al * kCoefPairs) * w.n_bins + c;
+#pragma unroll
+  for (int q = 0; q < kCoefPairs; ++q)
+    dst[q * w.n_bins] = make_float4((float)cr[2 * q], (float)ci[2 * q], (float)cr[2 * q + 1], (float)ci[2 * q + 1]);
+}
+
+struct CoefSet {
+  float4 c[kCoefPairs];
+};
+
+// Coefficients of one bin read straight from global memory, for a lane whose
+// bin is outside the LDS slice.  The empty asm statement after the loads
+// keeps the compiler from sinking them into the join with the LDS reads,
+// where both would become generic (flat) loads.
+__device__ __forceinline__ CoefSet load_coef_global(const WuDev& w, int64_t al, int64_t col) {
+  col = col < 0 ? 0 : (col >= w.n_bins ? w.n_bins - 1 : col);   // memory safety only
+  const float4* src = w.coef + al * kCoefPairs * w.n_bins + col;
+  CoefSet r;
+#pragma unroll
+  for (int q = 0; q < kCoefPairs; ++q) r.c[q] = src[q * w.n_bins];
+  __asm__ volatile("" ::: "memory");
+  return r;
+}
+
+// Per-chunk values shared by the work-group: for each staged SFT the first
+// column of its coefficient slice and whether every window of the tile falls
+// inside the slice, and per (SFT, spindown) the FP64 product fdot * tau and
+// the phase factor exp(-2 pi i frac(tau (fdot/2) tau)).
+template <int NFD, int CH>
+struct ChunkMeta {
+  int64_t lo[CH];
+  int fast[CH];
+  double g[CH][NFD];
+  float2 e[CH][NFD];
+};
+
+// k* is monotone in f and in fdot, so the tile's corners bound the bins of
+// every (template, SFT) pair of the tile: [kmin, kmax] in slice columns.
+template <int NFD, int CH>
+__device__ __forceinline__ void chunk_meta(const WuDev& w, const double2* geo, int64_t al0, int nc, int64_t i0,
+                                           int64_t i_last, double f_first, double f_last, int W,
+                                           ChunkMeta<NFD, CH>& m) {
+  const int tid = threadIdx.x;
+  for (int e = tid; e < nc * NFD; e += kThreads) {
+    const int c = e / NFD, r = e % NFD;
+    const double2 g = geo[al0 + c];
+    const int64_t i = (i0 + r < w.n_fd) ? i0 + r : w.n_fd - 1;
+    const double fd = template_fd(w, i);
+    m.g[c][r] = fd * g.x;
+    const float q = (float)fract64(g.x * ((0.5 * fd) * g.x));
+    m.e[c][r] = make_float2(cos_rev(q), -sin_rev(q));
+  }
+  if (tid < nc) {
+    const double2 g = geo[al0 + tid];
+    const double ga = template_fd(w, i0) * g.x, gb = template_fd(w, i_last) * g.x;
+    const double d1 = bin_position(f_first, ga, g.y, w.t_sft), d2 = bin_position(f_first, gb, g.y, w.t_sft);
+    const double d3 = bin_position(f_last, ga, g.y, w.t_sft), d4 = bin_position(f_last, gb, g.y, w.t_sft);
+    const double kmin = floor(d1 < d2 ? d1 : d2) - (double)w.k_first;
+    const double kmax = floor(d3 > d4 ? d3 : d4) - (double)w.k_first;
+    const int64_t max_lo = w.n_bins > W ? w.n_bins - W : 0;
+    int64_t lo = (kmin > 1.0 ? (int64_t)kmin : 1) - 1;              // one bin of slack
+    lo = lo > max_lo ? max_lo : lo;
+    m.lo[tid] = lo;
+    m.fast[tid] = (kmin >= (double)lo && kmax <= (double)(lo + W - 1) && kmax < (double)w.n_bins) ? 1 : 0;
+  }
+}
+
+// Copy the coefficient slices of chunk (al0, nc) into one LDS buffer with
+// direct global-to-LDS loads (global_load_lds_dwordx4): each wave moves runs
+// of 64 consecutive float4, lane l to run start + l, without staging through
+// registers.  The loads complete asynchronously; the caller waits on vmcnt
+// and a barrier before reading the buffer.  Columns beyond the band are not
+// loaded (no valid window reaches them).
+template <int CH>
+__device__ __forceinline__ void stage_coef_async(const WuDev& w, int64_t al0, int nc, const int64_t* lo, int W,
+                                                 float4* buf) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int runs = (W + 63) >> 6;
+  const int total = nc * kCoefPairs * runs;
+  for (int wr = wave; wr < total; wr += kThreads / 64) {
+    const int row = wr / runs, e0 = (wr % runs) << 6;
+    const int c = row / kCoefPairs, q = row % kCoefPairs;
+    const int e = e0 + lane;
+    const int64_t col = lo[c] + e;
+    if (e < W && col < w.n_bins) {
+      const float4* src = w.coef + ((al0 + c) * kCoefPairs + q) * w.n_bins + col;
+      __builtin_amdgcn_global_load_lds((const void*)src,
+                                       (void __attribute__((address_space(3)))*)(buf + row * W + e0), 16, 0, 0);
+    }
+  }
+}
+
+// Degree-7 complex polynomial in u (Horner) times exp(-2 pi i phi), added
+// to Fa, Fb with the weights a, b.
+__device__ __forceinline__ void interp_accumulate(float4 c01, float4 c23, float4 c45, float4 c67, float u, float cf,
+                                                  float sf, float2 eq, float a, float b, float& far, float& fai,
+                                                  float& fbr, float& fbi) {
+  float gr = __builtin_fmaf(c67.z, u, c67.x), gi = __builtin_fmaf(c67.w, u, c67.y);
+  gr = __builtin_fmaf(gr, u, c45.z); gi = __builtin_fmaf(gi, u, c45.w);
+  gr = __builtin_fmaf(gr, u, c45.x); gi = __builtin_fmaf(gi, u, c45.y);
+  gr = __builtin_fmaf(gr, u, c23.z); gi = __builtin_fmaf(gi, u, c23.w);
+  gr = __builtin_fmaf(gr, u, c23.x); gi = __builtin_fmaf(gi, u, c23.y);
+  gr = __builtin_fmaf(gr, u, c01.z); gi = __builtin_fmaf(gi, u, c01.w);
+  gr = __builtin_fmaf(gr, u, c01.x); gi = __builtin_fmaf(gi, u, c01.y);
+  // exp(-2 pi i phi) = exp(-2 pi i frac(tau f)) * exp(-2 pi i frac(tau (fdot/2) tau))
+  const float er = __builtin_fmaf(cf, eq.x, sf * eq.y);
+  const float ei = __builtin_fmaf(cf, eq.y, -sf * eq.x);
+  const float zr = __builtin_fmaf(gr, er, -gi * ei);
+  const float zi = __builtin_fmaf(gr, ei, gi * er);
+  far = __builtin_fmaf(a, zr, far);
+  fai = __builtin_fmaf(a, zi, fai);
+  fbr = __builtin_fmaf(b, zr, fbr);
+  fbi = __builtin_fmaf(b, zi, fbi);
+}
+
+// Demodulation over SFTs [al_begin, al_end) for tiles of (sky s, NFD
+// spindowns, kThreads frequencies), sky point fastest, one tile per
+// work-group.  The host splits the SFT loop into launches of a few dozen
+// SFTs: the work-groups of one launch then share the coefficient slices of a
+// few dozen SFTs (the same frequency tile, offset by each sky point's Doppler
+// shift), which stay in L2; Fa, Fb carry over between launches in `acc`.
+// Within a launch the slices are double-buffered in LDS: the direct
+// global-to-LDS loads of chunk k+1 are in flight while chunk k is evaluated.
+// Each thread owns one frequency at NFD spindowns: per SFT it forms
+// exp(-2 pi i frac(tau f)) once and, per spindown, the canonical FP64 Dphi,
+// k*, kappa, the degree-7 polynomial in u = 2 kappa - 1, the rotation and the
+// a/b accumulation in registers.  A chunk whose windows are not all inside
+// the slice (only possible for slices narrower than the tile's spread) takes
+// the same arithmetic with coefficients read from global memory.
+template <int NFD, int CH>
+__global__ __launch_bounds__(kThreads) void demod_interp_kernel(WuDev w, int W, int64_t al_begin, int64_t al_end) {
+  extern __shared__ float4 cseg[];                 // [2][CH][kCoefPairs][W]
+  __shared__ ChunkMeta<NFD, CH> meta[2];
+  const int tid = threadIdx.x;
+  const int64_t n_fdb = (w.n_fd + NFD - 1) / NFD;
+  const int buf_elems = CH * kCoefPairs * W;
+  int64_t t = blockIdx.x;
+  const int64_t s = t % w.n_sky;
+  t /= w.n_sky;
+  const int64_t ib = t % n_fdb;
+  const int64_t ft = t / n_fdb;
+  const int64_t j0 = ft * kThreads;
+  int64_t j = j0 + tid;
+  const bool jvalid = j < w.n_f;
+  if (!jvalid) j = w.n_f - 1;
+  const int64_t j_last = (j0 + kThreads - 1 < w.n_f - 1) ? j0 + kThreads - 1 : w.n_f - 1;
+  const int64_t i0 = ib * NFD;
+  const int64_t i_last = (i0 + NFD - 1 < w.n_fd - 1) ? i0 + NFD - 1 : w.n_fd - 1;
+  const double T = w.t_sft;
+  const double f = template_f(w, j);
+  const double f_first = template_f(w, j0), f_last = template_f(w, j_last);
+  const double2* geo = w.geo + s * w.n_sft;
+  const float* arow = w.a + s * w.n_sft;
+  const float* brow = w.b + s * w.n_sft;
+
+  float far[NFD], fai[NFD], fbr[NFD], fbi[NFD];
+#pragma unroll
+  for (int r = 0; r < NFD; ++r) {
+    const int64_t i = (i0 + r < w.n_fd) ? i0 + r : w.n_fd - 1;
+    if (al_begin > 0) {
+      const float4 v = w.acc[(s * w.n_fd + i) * w.n_f + j];
+      far[r] = v.x; fai[r] = v.y; fbr[r] = v.z; fbi[r] = v.w;
+    } else {
+      far[r] = fai[r] = fbr[r] = fbi[r] = 0.f;
+    }
+  }
+
+  const int64_t n_chunks = (al_end - al_begin + CH - 1) / CH;
+  {
+    const int nc0 = (int)(al_end - al_begin < CH ? al_end - al_begin : CH);
+    chunk_meta<NFD, CH>(w, geo, al_begin, nc0, i0, i_last, f_first, f_last, W, meta[0]);
+    __syncthreads();
+    stage_coef_async<CH>(w, al_begin, nc0, meta[0].lo, W, cseg);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+  }
+  for (int64_t k = 0; k < n_chunks; ++k) {
+    const int64_t al0 = al_begin + k * CH;
+    const int nc = (int)(al_end - al0 < CH ? al_end - al0 : CH);
+    const int nb = (int)(k & 1);
+    if (k + 1 < n_chunks) {
+      const int64_t al1 = al0 + CH;
+      const int nc1 = (int)(al_end - al1 < CH ? al_end - al1 : CH);
+      chunk_meta<NFD, CH>(w, geo, al1, nc1, i0, i_last, f_first, f_last, W, meta[nb ^ 1]);
+      __syncthreads();
+      stage_coef_async<CH>(w, al1, nc1, meta[nb ^ 1].lo, W, cseg + (nb ^ 1) * buf_elems);
+    }
+    const ChunkMeta<NFD, CH>& m = meta[nb];
+    const float4* bufk = cseg + nb * buf_elems;
+    for (int c = 0; c < nc; ++c) {
+      const int64_t al = al0 + c;
+      const double2 g = geo[al];
+      const float a = arow[al], b = brow[al];
+      const float pf = (float)fract64(g.x * f);                    // frac(tau f)
+      const float cf = cos_rev(pf), sf = sin_rev(pf);
+      const int base = (int)(w.k_first + m.lo[c]);                // absolute bin of slice column 0
+      const float4* seg = bufk + c * kCoefPairs * W;
+      if (__builtin_amdgcn_readfirstlane(m.fast[c])) {
+#pragma unroll
+        for (int r = 0; r < NFD; ++r) {
+          const double dphi = bin_position(f, m.g[c][r], g.y, T);
+          const int off = (int)dphi - base;
+          const float u = __builtin_fmaf(2.f, (float)fract64(dphi), -1.f);
+          interp_accumulate(seg[off], seg[W + off], seg[2 * W + off], seg[3 * W + off], u, cf, sf, m.e[c][r], a, b,
+                            far[r], fai[r], fbr[r], fbi[r]);
+          if (r % 4 == 3) __builtin_amdgcn_sched_barrier(0);   // bounds the coefficient registers in flight
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < NFD; ++r) {
+          const double dphi = bin_position(f, m.g[c][r], g.y, T);
+          const CoefSet cs = load_coef_global(w, al, (int64_t)(int)dphi - w.k_first);
+          const float u = __builtin_fmaf(2.f, (float)fract64(dphi), -1.f);
+          interp_accumulate(cs.c[0], cs.c[1], cs.c[2], cs.c[3], u, cf, sf, m.e[c][r], a, b, far[r], fai[r], fbr[r],
+                            fbi[r]);
+        }
+      }
+    }
+    __builtin_amdgcn_s_waitcnt(0);                  // this thread's loads of chunk k+1 have landed
+    __syncthreads();                                 // ... and everyone's; chunk k consumed
+  }
+  if (!jvalid) return;
+  const bool last = al_end == w.n_sft;
+  const double4 abcd = w.abcd[s];
+#pragma unroll
+  for (int r = 0; r < NFD; ++r) {
+    const int64_t i = i0 + r;
+    if (i >= w.n_fd) continue;
+    const int64_t o = (s * w.n_fd + i) * w.n_f + j;
+    if (!last) {
+      w.acc[o] = make_float4(far[r], fai[r], fbr[r], fbi[r]);
+      continue;
+    }
+    const double ar = far[r], ai = fai[r], br = fbr[r], bi = fbi[r];
+    const double fa2 = ar * ar + ai * ai, fb2 = br * br + bi * bi, re = ar * br + ai * bi;
+    const double two_f = 2.0 * (abcd.y * fa2 + abcd.x * fb2 - 2.0 * abcd.z * re) / abcd.w;
     w.twoF[o] = (float)two_f;
     if (w.fa) w.fa[o] = make_float2(far[r], fai[r]);
     if (w.fb) w.fb[o] = make_float2(fbr[r], fbi[r]);
@@ -360,15 +665,59 @@ hipError_t launch_fill_int(int* p, int v, int n, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_geometry(const WuDev& w, int* status, hipStream_t st) {
+hipError_t launch_geometry(const WuDev& w, GeoStatus* status, hipStream_t st) {
   const int64_t blocks = w.n_sky < 65536 ? w.n_sky : 65536;
   hipLaunchKernelGGL(geometry_kernel, dim3((unsigned)blocks), dim3(256), 0, st, w, status);
   return hipGetLastError();
 }
 
 size_t demod_lds_bytes(const WuDev& w, const Tile& t, int kernel) {
-  (void)kernel;
+  if (kernel == KERNEL_INTERP) return 2 * (size_t)t.chunk * kCoefPairs * t.seg * sizeof(float4);
   return (size_t)t.chunk * seg_width(kThreads * t.nf_reg, w.dterms) * sizeof(float2);
+}
+
+hipError_t launch_coef(const WuDev& w, hipStream_t st) {
+  const int64_t blocks = ((w.n_bins + 255) / 256) * w.n_sft;
+  if (blocks <= 0 || blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL(coef_kernel, dim3((unsigned)blocks), dim3(256), 0, st, w);
+  return hipGetLastError();
+}
+
+int interp_launches(const WuDev& w, const Tile& t) {
+  const int64_t sb = t.sblock > 0 ? t.sblock : w.n_sft;
+  return (int)((w.n_sft + sb - 1) / sb);
+}
+
+template <int NFD, int CH>
+static hipError_t launch_interp_t(const WuDev& w, const Tile& t, hipStream_t st) {
+  const int W = t.seg;
+  const int64_t n_ft = (w.n_f + kThreads - 1) / kThreads;
+  const int64_t n_tiles = n_ft * ((w.n_fd + NFD - 1) / NFD) * w.n_sky;
+  if (n_tiles <= 0 || n_tiles > 0x7fffffffLL || W < 8 || W > interp_max_seg(CH)) return hipErrorInvalidConfiguration;
+  const int64_t sb = t.sblock > 0 ? t.sblock : w.n_sft;
+  if (sb < w.n_sft && !w.acc) return hipErrorInvalidValue;
+  const size_t lds = 2 * (size_t)CH * kCoefPairs * W * sizeof(float4);
+  for (int64_t al = 0; al < w.n_sft; al += sb) {
+    const int64_t end = al + sb < w.n_sft ? al + sb : w.n_sft;
+    hipLaunchKernelGGL((demod_interp_kernel<NFD, CH>), dim3((unsigned)n_tiles), dim3(kThreads), lds, st, w, W, al, end);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// Largest slice width: the double-buffered slices of one work-group stay
+// within 64 KB of LDS.
+int interp_max_seg(int chunk) { return 65536 / (2 * chunk * kCoefPairs * (int)sizeof(float4)); }
+
+static hipError_t launch_interp(const WuDev& w, const Tile& t, hipStream_t st) {
+  if (t.nf_reg == 8 && t.chunk == 1) return launch_interp_t<8, 1>(w, t, st);
+  if (t.nf_reg == 8 && t.chunk == 2) return launch_interp_t<8, 2>(w, t, st);
+  if (t.nf_reg == 4 && t.chunk == 1) return launch_interp_t<4, 1>(w, t, st);
+  if (t.nf_reg == 4 && t.chunk == 2) return launch_interp_t<4, 2>(w, t, st);
+  if (t.nf_reg == 2 && t.chunk == 2) return launch_interp_t<2, 2>(w, t, st);
+  if (t.nf_reg == 1 && t.chunk == 2) return launch_interp_t<1, 2>(w, t, st);
+  return hipErrorInvalidValue;
 }
 
 template <int DT, int NF, int CH>
@@ -392,7 +741,7 @@ static hipError_t launch_direct_d(const WuDev& w, const Tile& t, hipStream_t st)
 }
 
 hipError_t launch_demod(const WuDev& w, const Tile& t, int kernel, hipStream_t st) {
-  (void)kernel;
+  if (kernel == KERNEL_INTERP) return launch_interp(w, t, st);
   switch (w.dterms) {
     case 8: return launch_direct_d<8>(w, t, st);
     case 16: return launch_direct_d<16>(w, t, st);

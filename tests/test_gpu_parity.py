@@ -88,34 +88,40 @@ def test_bins_bit_exact(torch_cuda, oracle_lib):
     assert np.max(np.minimum(d, 1 - d)) < 1e-9
 
 
-def test_parity_config0(torch_cuda, oracle_lib):
+KERNELS = ["direct", "interp"]
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_parity_config0(torch_cuda, oracle_lib, kernel):
     w = synth.make_config(0)
-    _say(f"config0: {w.name} n_sft={w.n_sft} n_bins={w.n_bins} D={w.dterms}")
-    out, _ = _run(torch_cuda, w)
+    _say(f"config0 {kernel}: {w.name} n_sft={w.n_sft} n_bins={w.n_bins} D={w.dterms}")
+    out, _ = _run(torch_cuda, w, kernel=kernel)
     _compare(oracle_lib, w, out)
     # the injected template stands out
     assert out.twoF.cpu().numpy()[0, 0, 128] > 60
 
 
+@pytest.mark.parametrize("kernel", KERNELS)
 @pytest.mark.parametrize("dterms", [1, 3, 8, 16, 33, 64])
-def test_parity_ragged_tiles(torch_cuda, oracle_lib, dterms):
+def test_parity_ragged_tiles(torch_cuda, oracle_lib, dterms, kernel):
     """Several frequency tiles with a ragged tail, an SFT count that is not a
     multiple of the LDS chunk, two detectors, several sky points and spindowns."""
     w = small_workload(100 + dterms, n_det=2, slots=23, keep=0.8, n_sky=3, n_fd=3, n_f=700, dterms=dterms,
                        injections=((1, 2, 333, 15.0),))
-    _say(f"ragged D={dterms}: n_sft={w.n_sft} n_bins={w.n_bins} templates={w.n_templates}")
-    out, _ = _run(torch_cuda, w)
+    _say(f"ragged {kernel} D={dterms}: n_sft={w.n_sft} n_bins={w.n_bins} templates={w.n_templates}")
+    out, _ = _run(torch_cuda, w, kernel=kernel)
     _compare(oracle_lib, w, out)
 
 
+@pytest.mark.parametrize("kernel", KERNELS)
 @pytest.mark.parametrize("storage", ["bf16", "fp16"])
-def test_parity_16bit_storage(torch_cuda, oracle_lib, storage):
+def test_parity_16bit_storage(torch_cuda, oracle_lib, storage, kernel):
     """Arithmetic parity against the oracle run on the exactly dequantised
     stored values (1e-4), and the storage error against complex64 input."""
     w = small_workload(200, n_det=2, slots=30, keep=0.9, n_sky=4, n_fd=2, n_f=600, dterms=8,
                        injections=((0, 1, 300, 20.0),))
-    _say(f"16-bit {storage}: n_sft={w.n_sft} n_bins={w.n_bins}")
-    out, deq = _run(torch_cuda, w, storage)
+    _say(f"16-bit {storage} {kernel}: n_sft={w.n_sft} n_bins={w.n_bins}")
+    out, deq = _run(torch_cuda, w, storage, kernel=kernel)
     _compare(oracle_lib, w, out, sft=deq)
     ref = oracle_lib.fstat(w)
     e = twoF_error(out.twoF.cpu().numpy().ravel(), ref["twoF"])
@@ -123,14 +129,15 @@ def test_parity_16bit_storage(torch_cuda, oracle_lib, storage):
     assert math.sqrt(np.mean(e * e)) < 5e-3
 
 
-def test_parity_config1_sampled(torch_cuda, oracle_lib):
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_parity_config1_sampled(torch_cuda, oracle_lib, kernel):
     """The work-unit-shaped case at full size, in the launch configuration the
     benchmark times; the oracle checks two whole sky points (8 x 3600
     templates each, all 2000 SFTs) and every injected template."""
     torch = torch_cuda
     w = synth.make_config(1)
-    _say(f"config1: n_sft={w.n_sft} n_bins={w.n_bins} templates={w.n_templates}")
-    out, _ = _run(torch, w, fafb=False)
+    _say(f"config1 {kernel}: n_sft={w.n_sft} n_bins={w.n_bins} templates={w.n_templates}")
+    out, _ = _run(torch, w, kernel=kernel, fafb=False)
     sk = [0, 1234]
     s, i, j = oracle_lib.all_templates(w, sk)
     inj = [(x.sky_index, x.fdot_index, x.f_index) for x in w.injections]
@@ -152,17 +159,19 @@ def test_band_error_on_gpu(torch_cuda, oracle_lib):
     lo, hi = int(k.min()) - w.dterms + 1, int(k.max()) + w.dterms
     c0, c1 = lo - w.k_first, hi - w.k_first + 1
     tight = replace(w, sft=np.ascontiguousarray(w.sft[:, c0:c1]), k_first=lo)
-    out, _ = _run(torch_cuda, tight, fafb=False)           # exactly enough bins: accepted
-    _compare(oracle_lib, tight, out)
+    for kernel in KERNELS:
+        out, _ = _run(torch_cuda, tight, kernel=kernel, fafb=False)     # exactly enough bins: accepted
+        _compare(oracle_lib, tight, out)
     cut = replace(w, sft=np.ascontiguousarray(w.sft[:, c0 + 1:c1]), k_first=lo + 1)
     with pytest.raises(P.FstatError) as e:
         _run(torch_cuda, cut, fafb=False)
     assert e.value.code == P.FSTAT_E_BAND
 
 
-def test_edge_single_frequency_two_sfts(torch_cuda, oracle_lib):
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_edge_single_frequency_two_sfts(torch_cuda, oracle_lib, kernel):
     w = small_workload(400, n_det=1, slots=2, keep=1.0, n_sky=1, n_fd=1, n_f=1, injections=())
-    out, _ = _run(torch_cuda, w)
+    out, _ = _run(torch_cuda, w, kernel=kernel)
     _compare(oracle_lib, w, out)
 
 
