@@ -240,7 +240,11 @@ int interp_seg(const fstat_plan* p, const fstat_wu* w, int nfd, int chunk) {
 Tile default_tile(const fstat_plan* p, const fstat_wu* w) {
   if (resolved_kernel(p) == fstat::KERNEL_INTERP) {
     const int nfd = w->n_fd >= 8 ? 8 : (w->n_fd >= 4 ? 4 : (w->n_fd >= 2 ? 2 : 1));
-    return Tile{nfd, nfd >= 4 ? 1 : 2, 0, 64};
+    // measured on the work-unit-shaped case: 8 spindowns per thread with room
+    // for 3 waves per SIMD and one launch over all SFTs is fastest; with fewer
+    // spindowns per thread the staged slices are reused less and splitting the
+    // SFT loop into launches keeps them in L2
+    return Tile{nfd, 3, 0, nfd >= 4 ? 0 : 256};
   }
   return Tile{1, 16, 0, 0};
 }
@@ -248,7 +252,7 @@ Tile default_tile(const fstat_plan* p, const fstat_wu* w) {
 Tile pick_tile(const fstat_plan* p, const fstat_wu* w) {
   auto it = p->tiles.find(class_key(p, w));
   Tile t = it != p->tiles.end() ? it->second : default_tile(p, w);
-  if (resolved_kernel(p) == fstat::KERNEL_INTERP) t.seg = interp_seg(p, w, t.nf_reg, t.chunk);
+  if (resolved_kernel(p) == fstat::KERNEL_INTERP) t.seg = interp_seg(p, w, t.nf_reg, 1);
   return t;
 }
 
@@ -454,16 +458,16 @@ int fstat_autotune(fstat_plan* p, const fstat_wu* wu, const fstat_out* out, void
   std::vector<Tile> cands;
   if (resolved_kernel(p) == fstat::KERNEL_INTERP) {
     for (int nfd : {8, 4, 2, 1})
-      for (int ch : {1, 2})
-        for (int sb : {32, 64, 128, 0})
-          if ((nfd <= 2 * wu->n_fd || nfd == 1) && (nfd >= 4 || ch == 2)) cands.push_back(Tile{nfd, ch, 0, sb});
+      for (int minw : {2, 3})
+        for (int sb : {64, 128, 256, 0})
+          if ((nfd <= 2 * wu->n_fd || nfd == 1) && (nfd >= 4 || minw == 3)) cands.push_back(Tile{nfd, minw, 0, sb});
   } else {
     cands = {Tile{1, 16, 0, 0}, Tile{1, 8, 0, 0}, Tile{2, 8, 0, 0}, Tile{2, 4, 0, 0}, Tile{4, 4, 0, 0}};
   }
   float best = 1e30f;
   Tile best_t = default_tile(p, wu);
   for (Tile t : cands) {
-    if (resolved_kernel(p) == fstat::KERNEL_INTERP) t.seg = interp_seg(p, wu, t.nf_reg, t.chunk);
+    if (resolved_kernel(p) == fstat::KERNEL_INTERP) t.seg = interp_seg(p, wu, t.nf_reg, 1);
     float ms_sum = 0.f;
     for (int rep = 0; rep < 2; ++rep) {
       rc = run_demod(p, v, t, st);

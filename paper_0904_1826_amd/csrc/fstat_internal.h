@@ -45,6 +45,12 @@ enum Kernel : int32_t { KERNEL_DIRECT = 1, KERNEL_INTERP = 2 };
 // degree-7 polynomial in u with kCoef complex coefficients per bin.
 constexpr int kCoef = 8;
 constexpr int kCoefPairs = kCoef / 2;
+// Widest coefficient slice (bins) one work-group stages per SFT: 256
+// frequency templates plus up to 58 bins of Doppler and spindown spread and
+// the slack, in runs of 64; two buffers of it take 40 KB of LDS, so three
+// work-groups fit a CU.
+constexpr int kMaxRuns = 5;
+constexpr int kSegMax = 64 * kMaxRuns;
 
 // Geometry pass results read back by the host.
 struct GeoStatus {

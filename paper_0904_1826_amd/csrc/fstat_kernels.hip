@@ -412,26 +412,35 @@ __device__ __forceinline__ CoefSet load_coef_global(const WuDev& w, int64_t al, 
   return r;
 }
 
-// Per-chunk values shared by the work-group: for each staged SFT the first
-// column of its coefficient slice and whether every window of the tile falls
-// inside the slice, and per (SFT, spindown) the FP64 product fdot * tau and
-// the phase factor exp(-2 pi i frac(tau (fdot/2) tau)).
-template <int NFD, int CH>
-struct ChunkMeta {
-  int64_t lo[CH];
-  int fast[CH];
-  double g[CH][NFD];
-  float2 e[CH][NFD];
+// Values shared by the work-group for a group of S consecutive SFTs: for each
+// SFT the first column of its coefficient slice and whether every window of
+// the tile falls inside the slice, and per (SFT, spindown) the FP64 product
+// fdot * tau and the phase factor exp(-2 pi i frac(tau (fdot/2) tau)).
+template <int NFD, int S>
+struct GroupMeta {
+  double2 geo[S];     // (tau, Tdot) of the sky point
+  float a[S], b[S];
+  int lo[S];
+  int fast[S];
+  double g[S][NFD];
+  float2 e[S][NFD];
 };
 
+// Fills the meta of SFTs [al0, al0 + n) with all threads of the work-group.
 // k* is monotone in f and in fdot, so the tile's corners bound the bins of
 // every (template, SFT) pair of the tile: [kmin, kmax] in slice columns.
-template <int NFD, int CH>
-__device__ __forceinline__ void chunk_meta(const WuDev& w, const double2* geo, int64_t al0, int nc, int64_t i0,
-                                           int64_t i_last, double f_first, double f_last, int W,
-                                           ChunkMeta<NFD, CH>& m) {
+template <int NFD, int S>
+__device__ __forceinline__ void group_meta(const WuDev& w, const double2* geo, const float* arow, const float* brow,
+                                           int64_t al0, int n, int64_t i0, int64_t i_last, double f_first,
+                                           double f_last, int W, GroupMeta<NFD, S>& m) {
   const int tid = threadIdx.x;
-  for (int e = tid; e < nc * NFD; e += kThreads) {
+  const int t3 = tid - (kThreads - 2 * S);       // S threads before the last S copy tau, Tdot, a, b
+  if (t3 >= 0 && t3 < n) {
+    m.geo[t3] = geo[al0 + t3];
+    m.a[t3] = arow[al0 + t3];
+    m.b[t3] = brow[al0 + t3];
+  }
+  for (int e = tid; e < n * NFD; e += kThreads) {
     const int c = e / NFD, r = e % NFD;
     const double2 g = geo[al0 + c];
     const int64_t i = (i0 + r < w.n_fd) ? i0 + r : w.n_fd - 1;
@@ -440,43 +449,62 @@ __device__ __forceinline__ void chunk_meta(const WuDev& w, const double2* geo, i
     const float q = (float)fract64(g.x * ((0.5 * fd) * g.x));
     m.e[c][r] = make_float2(cos_rev(q), -sin_rev(q));
   }
-  if (tid < nc) {
-    const double2 g = geo[al0 + tid];
+  const int t2 = tid - (kThreads - S);           // the last S threads do the slice bounds
+  if (t2 >= 0 && t2 < n) {
+    const double2 g = geo[al0 + t2];
     const double ga = template_fd(w, i0) * g.x, gb = template_fd(w, i_last) * g.x;
     const double d1 = bin_position(f_first, ga, g.y, w.t_sft), d2 = bin_position(f_first, gb, g.y, w.t_sft);
     const double d3 = bin_position(f_last, ga, g.y, w.t_sft), d4 = bin_position(f_last, gb, g.y, w.t_sft);
-    const double kmin = floor(d1 < d2 ? d1 : d2) - (double)w.k_first;
-    const double kmax = floor(d3 > d4 ? d3 : d4) - (double)w.k_first;
-    const int64_t max_lo = w.n_bins > W ? w.n_bins - W : 0;
-    int64_t lo = (kmin > 1.0 ? (int64_t)kmin : 1) - 1;              // one bin of slack
+    // column offsets of the extreme bins; the band is below 2^31 bins
+    const int kmin = (int)(floor(d1 < d2 ? d1 : d2) - (double)w.k_first);
+    const int kmax = (int)(floor(d3 > d4 ? d3 : d4) - (double)w.k_first);
+    const int nb = (int)w.n_bins;
+    const int max_lo = nb > W ? nb - W : 0;
+    int lo = (kmin > 1 ? kmin : 1) - 1;           // one bin of slack
     lo = lo > max_lo ? max_lo : lo;
-    m.lo[tid] = lo;
-    m.fast[tid] = (kmin >= (double)lo && kmax <= (double)(lo + W - 1) && kmax < (double)w.n_bins) ? 1 : 0;
+    m.lo[t2] = lo;
+    m.fast[t2] = (kmin >= lo && kmax <= lo + W - 1 && kmax < nb) ? 1 : 0;
   }
 }
 
-// Copy the coefficient slices of chunk (al0, nc) into one LDS buffer with
-// direct global-to-LDS loads (global_load_lds_dwordx4): each wave moves runs
-// of 64 consecutive float4, lane l to run start + l, without staging through
-// registers.  The loads complete asynchronously; the caller waits on vmcnt
-// and a barrier before reading the buffer.  Columns beyond the band are not
-// loaded (no valid window reaches them).
-template <int CH>
-__device__ __forceinline__ void stage_coef_async(const WuDev& w, int64_t al0, int nc, const int64_t* lo, int W,
-                                                 float4* buf) {
+// Staging of one SFT's coefficient slice through registers: the slice is
+// kCoefPairs rows of kSegMax float4 (columns W .. kSegMax-1 are padding),
+// i.e. kCoefPairs * kMaxRuns runs of 64, and wave w moves runs w, w + 4, ...,
+// kMaxRuns of them, one float4 per lane each.  The loads are issued before
+// the current SFT is evaluated and written to LDS after it, so their latency
+// hides behind the arithmetic; they are unconditional (columns beyond the
+// band are clamped to its last column, never read by a valid window) so that
+// the compiler waits for them only where they are stored.
+typedef float v4f __attribute__((ext_vector_type(4)));   // native vector: stays in registers
+
+struct SlicePrefetch {
+  v4f v[kMaxRuns];
+};
+
+__device__ __forceinline__ SlicePrefetch slice_load(const WuDev& w, int64_t al, int lo) {
+  SlicePrefetch p;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int runs = (W + 63) >> 6;
-  const int total = nc * kCoefPairs * runs;
-  for (int wr = wave; wr < total; wr += kThreads / 64) {
-    const int row = wr / runs, e0 = (wr % runs) << 6;
-    const int c = row / kCoefPairs, q = row % kCoefPairs;
-    const int e = e0 + lane;
-    const int64_t col = lo[c] + e;
-    if (e < W && col < w.n_bins) {
-      const float4* src = w.coef + ((al0 + c) * kCoefPairs + q) * w.n_bins + col;
-      __builtin_amdgcn_global_load_lds((const void*)src,
-                                       (void __attribute__((address_space(3)))*)(buf + row * W + e0), 16, 0, 0);
-    }
+  const int last = (int)w.n_bins - 1;
+  const v4f* base = reinterpret_cast<const v4f*>(w.coef + al * kCoefPairs * w.n_bins);
+#pragma unroll
+  for (int i = 0; i < kMaxRuns; ++i) {
+    const int wr = wave + (kThreads / 64) * i;
+    const int q = wr / kMaxRuns, e = (wr % kMaxRuns) * 64 + lane;
+    int col = lo + e;
+    col = col > last ? last : col;
+    p.v[i] = base[q * w.n_bins + col];
+  }
+  return p;
+}
+
+__device__ __forceinline__ void slice_store(const SlicePrefetch& p, float4* buf_) {
+  v4f* buf = reinterpret_cast<v4f*>(buf_);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+  for (int i = 0; i < kMaxRuns; ++i) {
+    const int wr = wave + (kThreads / 64) * i;
+    const int q = wr / kMaxRuns, e = (wr % kMaxRuns) * 64 + lane;
+    buf[q * kSegMax + e] = p.v[i];
   }
 }
 
@@ -509,21 +537,25 @@ __device__ __forceinline__ void interp_accumulate(float4 c01, float4 c23, float4
 // SFTs: the work-groups of one launch then share the coefficient slices of a
 // few dozen SFTs (the same frequency tile, offset by each sky point's Doppler
 // shift), which stay in L2; Fa, Fb carry over between launches in `acc`.
-// Within a launch the slices are double-buffered in LDS: the direct
-// global-to-LDS loads of chunk k+1 are in flight while chunk k is evaluated.
+// Within a launch the slices (one SFT per chunk) are double-buffered in LDS:
+// the direct global-to-LDS loads of chunk k+1 are in flight while chunk k is
+// evaluated, with one barrier per chunk.  The per-SFT values shared by the
+// work-group are prepared S SFTs at a time by all threads, one group ahead.
 // Each thread owns one frequency at NFD spindowns: per SFT it forms
 // exp(-2 pi i frac(tau f)) once and, per spindown, the canonical FP64 Dphi,
 // k*, kappa, the degree-7 polynomial in u = 2 kappa - 1, the rotation and the
-// a/b accumulation in registers.  A chunk whose windows are not all inside
+// a/b accumulation in registers.  An SFT whose windows are not all inside
 // the slice (only possible for slices narrower than the tile's spread) takes
 // the same arithmetic with coefficients read from global memory.
-template <int NFD, int CH>
-__global__ __launch_bounds__(kThreads) void demod_interp_kernel(WuDev w, int W, int64_t al_begin, int64_t al_end) {
-  extern __shared__ float4 cseg[];                 // [2][CH][kCoefPairs][W]
-  __shared__ ChunkMeta<NFD, CH> meta[2];
+template <int NFD, int S, int MINW>
+__global__ __launch_bounds__(kThreads, MINW) void demod_interp_kernel(WuDev w, int W, int64_t al_begin,
+                                                                     int64_t al_end) {
+  __shared__ float4 cbuf0[kCoefPairs * kSegMax];
+  __shared__ float4 cbuf1[kCoefPairs * kSegMax];
+  __shared__ GroupMeta<NFD, S> meta[2];
   const int tid = threadIdx.x;
   const int64_t n_fdb = (w.n_fd + NFD - 1) / NFD;
-  const int buf_elems = CH * kCoefPairs * W;
+  constexpr int Wp = kSegMax;                      // LDS row stride
   int64_t t = blockIdx.x;
   const int64_t s = t % w.n_sky;
   t /= w.n_sky;
@@ -542,6 +574,8 @@ __global__ __launch_bounds__(kThreads) void demod_interp_kernel(WuDev w, int W, 
   const double2* geo = w.geo + s * w.n_sft;
   const float* arow = w.a + s * w.n_sft;
   const float* brow = w.b + s * w.n_sft;
+  const int n = (int)(al_end - al_begin);
+  const int k_first = (int)w.k_first;
 
   float far[NFD], fai[NFD], fbr[NFD], fbi[NFD];
 #pragma unroll
@@ -555,59 +589,58 @@ __global__ __launch_bounds__(kThreads) void demod_interp_kernel(WuDev w, int W, 
     }
   }
 
-  const int64_t n_chunks = (al_end - al_begin + CH - 1) / CH;
-  {
-    const int nc0 = (int)(al_end - al_begin < CH ? al_end - al_begin : CH);
-    chunk_meta<NFD, CH>(w, geo, al_begin, nc0, i0, i_last, f_first, f_last, W, meta[0]);
-    __syncthreads();
-    stage_coef_async<CH>(w, al_begin, nc0, meta[0].lo, W, cseg);
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
-  }
-  for (int64_t k = 0; k < n_chunks; ++k) {
-    const int64_t al0 = al_begin + k * CH;
-    const int nc = (int)(al_end - al0 < CH ? al_end - al0 : CH);
-    const int nb = (int)(k & 1);
-    if (k + 1 < n_chunks) {
-      const int64_t al1 = al0 + CH;
-      const int nc1 = (int)(al_end - al1 < CH ? al_end - al1 : CH);
-      chunk_meta<NFD, CH>(w, geo, al1, nc1, i0, i_last, f_first, f_last, W, meta[nb ^ 1]);
-      __syncthreads();
-      stage_coef_async<CH>(w, al1, nc1, meta[nb ^ 1].lo, W, cseg + (nb ^ 1) * buf_elems);
+  group_meta<NFD, S>(w, geo, arow, brow, al_begin, n < S ? n : S, i0, i_last, f_first, f_last, W, meta[0]);
+  __syncthreads();
+  slice_store(slice_load(w, al_begin, meta[0].lo[0]), cbuf0);
+  __syncthreads();
+  // One SFT per step; the step is written twice (even SFTs read cbuf0 and
+  // fill cbuf1, odd SFTs the reverse) so that every LDS access has a fixed
+  // buffer.
+  auto step = [&](int k, const float4* seg, float4* next) __attribute__((always_inline)) {
+    const int kk = k % S, gq = (k / S) & 1;
+    if (kk == 0 && k + S < n) {                    // values of the next group, read after >= 1 barrier
+      const int n1 = n - (k + S) < S ? n - (k + S) : S;
+      group_meta<NFD, S>(w, geo, arow, brow, al_begin + k + S, n1, i0, i_last, f_first, f_last, W, meta[gq ^ 1]);
     }
-    const ChunkMeta<NFD, CH>& m = meta[nb];
-    const float4* bufk = cseg + nb * buf_elems;
-    for (int c = 0; c < nc; ++c) {
-      const int64_t al = al0 + c;
-      const double2 g = geo[al];
-      const float a = arow[al], b = brow[al];
-      const float pf = (float)fract64(g.x * f);                    // frac(tau f)
-      const float cf = cos_rev(pf), sf = sin_rev(pf);
-      const int base = (int)(w.k_first + m.lo[c]);                // absolute bin of slice column 0
-      const float4* seg = bufk + c * kCoefPairs * W;
-      if (__builtin_amdgcn_readfirstlane(m.fast[c])) {
+    const bool more = k + 1 < n;
+    // unconditional (the last step reloads its own SFT and discards it), so
+    // that the registers carry no branch-merged values the compiler must wait
+    // for
+    const int k1 = more ? k + 1 : k;
+    const SlicePrefetch pre = slice_load(w, al_begin + k1, meta[(k1 / S) & 1].lo[k1 % S]);
+    const GroupMeta<NFD, S>& m = meta[gq];
+    const int64_t al = al_begin + k;
+    const double2 g = m.geo[kk];
+    const float a = m.a[kk], b = m.b[kk];
+    const float pf = (float)fract64(g.x * f);                      // frac(tau f)
+    const float cf = cos_rev(pf), sf = sin_rev(pf);
+    const int base = k_first + m.lo[kk];                           // absolute bin of slice column 0
+    if (__builtin_amdgcn_readfirstlane(m.fast[kk])) {
 #pragma unroll
-        for (int r = 0; r < NFD; ++r) {
-          const double dphi = bin_position(f, m.g[c][r], g.y, T);
-          const int off = (int)dphi - base;
-          const float u = __builtin_fmaf(2.f, (float)fract64(dphi), -1.f);
-          interp_accumulate(seg[off], seg[W + off], seg[2 * W + off], seg[3 * W + off], u, cf, sf, m.e[c][r], a, b,
-                            far[r], fai[r], fbr[r], fbi[r]);
-          if (r % 4 == 3) __builtin_amdgcn_sched_barrier(0);   // bounds the coefficient registers in flight
-        }
-      } else {
+      for (int r = 0; r < NFD; ++r) {
+        const double dphi = bin_position(f, m.g[kk][r], g.y, T);
+        const int off = (int)dphi - base;
+        const float u = __builtin_fmaf(2.f, (float)fract64(dphi), -1.f);
+        interp_accumulate(seg[off], seg[Wp + off], seg[2 * Wp + off], seg[3 * Wp + off], u, cf, sf, m.e[kk][r], a,
+                          b, far[r], fai[r], fbr[r], fbi[r]);
+        if (r % 4 == 3) __builtin_amdgcn_sched_barrier(0);     // bounds the coefficient registers in flight
+      }
+    } else {
 #pragma unroll
-        for (int r = 0; r < NFD; ++r) {
-          const double dphi = bin_position(f, m.g[c][r], g.y, T);
-          const CoefSet cs = load_coef_global(w, al, (int64_t)(int)dphi - w.k_first);
-          const float u = __builtin_fmaf(2.f, (float)fract64(dphi), -1.f);
-          interp_accumulate(cs.c[0], cs.c[1], cs.c[2], cs.c[3], u, cf, sf, m.e[c][r], a, b, far[r], fai[r], fbr[r],
-                            fbi[r]);
-        }
+      for (int r = 0; r < NFD; ++r) {
+        const double dphi = bin_position(f, m.g[kk][r], g.y, T);
+        const CoefSet cs = load_coef_global(w, al, (int64_t)(int)dphi - w.k_first);
+        const float u = __builtin_fmaf(2.f, (float)fract64(dphi), -1.f);
+        interp_accumulate(cs.c[0], cs.c[1], cs.c[2], cs.c[3], u, cf, sf, m.e[kk][r], a, b, far[r], fai[r], fbr[r],
+                          fbi[r]);
       }
     }
-    __builtin_amdgcn_s_waitcnt(0);                  // this thread's loads of chunk k+1 have landed
-    __syncthreads();                                 // ... and everyone's; chunk k consumed
+    if (more) slice_store(pre, next);               // the other buffer was consumed before the last barrier
+    __syncthreads();
+  };
+  for (int k = 0; k < n; k += 2) {
+    step(k, cbuf0, cbuf1);
+    if (k + 1 < n) step(k + 1, cbuf1, cbuf0);
   }
   if (!jvalid) return;
   const bool last = al_end == w.n_sft;
@@ -672,7 +705,7 @@ hipError_t launch_geometry(const WuDev& w, GeoStatus* status, hipStream_t st) {
 }
 
 size_t demod_lds_bytes(const WuDev& w, const Tile& t, int kernel) {
-  if (kernel == KERNEL_INTERP) return 2 * (size_t)t.chunk * kCoefPairs * t.seg * sizeof(float4);
+  if (kernel == KERNEL_INTERP) return 2 * (size_t)kCoefPairs * kSegMax * sizeof(float4);
   return (size_t)t.chunk * seg_width(kThreads * t.nf_reg, w.dterms) * sizeof(float2);
 }
 
@@ -688,36 +721,38 @@ int interp_launches(const WuDev& w, const Tile& t) {
   return (int)((w.n_sft + sb - 1) / sb);
 }
 
-template <int NFD, int CH>
+template <int NFD, int S, int MINW>
 static hipError_t launch_interp_t(const WuDev& w, const Tile& t, hipStream_t st) {
   const int W = t.seg;
   const int64_t n_ft = (w.n_f + kThreads - 1) / kThreads;
   const int64_t n_tiles = n_ft * ((w.n_fd + NFD - 1) / NFD) * w.n_sky;
-  if (n_tiles <= 0 || n_tiles > 0x7fffffffLL || W < 8 || W > interp_max_seg(CH)) return hipErrorInvalidConfiguration;
+  if (n_tiles <= 0 || n_tiles > 0x7fffffffLL || W < 8 || W > kSegMax) return hipErrorInvalidConfiguration;
   const int64_t sb = t.sblock > 0 ? t.sblock : w.n_sft;
   if (sb < w.n_sft && !w.acc) return hipErrorInvalidValue;
-  const size_t lds = 2 * (size_t)CH * kCoefPairs * W * sizeof(float4);
+  const size_t lds = 0;
   for (int64_t al = 0; al < w.n_sft; al += sb) {
     const int64_t end = al + sb < w.n_sft ? al + sb : w.n_sft;
-    hipLaunchKernelGGL((demod_interp_kernel<NFD, CH>), dim3((unsigned)n_tiles), dim3(kThreads), lds, st, w, W, al, end);
+    hipLaunchKernelGGL((demod_interp_kernel<NFD, S, MINW>), dim3((unsigned)n_tiles), dim3(kThreads), lds, st, w, W, al,
+                       end);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
 }
 
-// Largest slice width: the double-buffered slices of one work-group stay
-// within 64 KB of LDS.
-int interp_max_seg(int chunk) { return 65536 / (2 * chunk * kCoefPairs * (int)sizeof(float4)); }
+int interp_max_seg(int chunk) { return chunk > 0 ? kSegMax : kSegMax; }
 
+// Tile.chunk is the minimum number of waves per SIMD the compiler must leave
+// room for (2 or 3): it trades registers for occupancy.
 static hipError_t launch_interp(const WuDev& w, const Tile& t, hipStream_t st) {
-  if (t.nf_reg == 8 && t.chunk == 1) return launch_interp_t<8, 1>(w, t, st);
-  if (t.nf_reg == 8 && t.chunk == 2) return launch_interp_t<8, 2>(w, t, st);
-  if (t.nf_reg == 4 && t.chunk == 1) return launch_interp_t<4, 1>(w, t, st);
-  if (t.nf_reg == 4 && t.chunk == 2) return launch_interp_t<4, 2>(w, t, st);
-  if (t.nf_reg == 2 && t.chunk == 2) return launch_interp_t<2, 2>(w, t, st);
-  if (t.nf_reg == 1 && t.chunk == 2) return launch_interp_t<1, 2>(w, t, st);
-  return hipErrorInvalidValue;
+  const bool w3 = t.chunk >= 3;
+  switch (t.nf_reg) {
+    case 8: return w3 ? launch_interp_t<8, 16, 3>(w, t, st) : launch_interp_t<8, 16, 2>(w, t, st);
+    case 4: return w3 ? launch_interp_t<4, 16, 3>(w, t, st) : launch_interp_t<4, 16, 2>(w, t, st);
+    case 2: return launch_interp_t<2, 16, 3>(w, t, st);
+    case 1: return launch_interp_t<1, 16, 3>(w, t, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 template <int DT, int NF, int CH>
