@@ -24,7 +24,7 @@
  * above (no fused multiply-add), so k* is reproducible bit for bit; the window
  * sums and Fa, Fb are accumulated in FP32.  The data arrays follow the
  * "data arrays plus offset arrays" layout the paper's GPU port adopted
- * (Section 6): flat contiguous arrays, ragged detector blocks addressed by
+ * (Section 7): flat contiguous arrays, ragged detector blocks addressed by
  * offsets.
  *
  * Memory: every array pointer in fstat_wu / fstat_out is a DEVICE pointer on

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <algorithm>
 #include <map>
 #include <string>
 #include <vector>
@@ -43,6 +44,20 @@ struct fstat_plan {
   bool timed = false;
   // tile choices per class key
   std::map<std::string, Tile> tiles;
+  // batched form: scratch arena, per-work-unit statuses, work-unit tables,
+  // tile counter, capture stream and instantiated graphs
+  void* arena = nullptr;
+  size_t arena_bytes = 0;
+  fstat::GeoStatus* bstat_d = nullptr;
+  fstat::GeoStatus* bstat_h = nullptr;
+  size_t bstat_cap = 0;
+  fstat::BatchEntry* ents_d = nullptr;
+  fstat::BatchEntry* ents_h = nullptr;
+  size_t ents_cap = 0;
+  unsigned long long* counter = nullptr;
+  hipStream_t cap_stream = nullptr;
+  int batch_grid = 0;
+  std::map<std::vector<int64_t>, hipGraphExec_t> graphs;
   // fault injection (host-side forcing of error paths)
   long fail_malloc_at = -1, fail_launch_at = -1;
   long n_malloc = 0, n_launch = 0;
@@ -228,13 +243,17 @@ std::string class_key(const fstat_plan* p, const fstat_wu* w) {
 // Lanes whose window falls outside the slice read their coefficients from
 // global memory instead, so a narrower slice costs speed, not correctness;
 // the slice is capped so that one work-group uses at most 64 KB of LDS.
-int interp_seg(const fstat_plan* p, const fstat_wu* w, int nfd, int chunk) {
+int interp_seg_tau(const fstat_wu* w, int nfd, int chunk, double max_abs_tau) {
   const double tdot = 1.001;
-  const double spread = (255.0 * w->df + fabs(w->dfdot) * (nfd - 1) * p->max_abs_tau) * w->t_sft * tdot;
+  const double spread = (255.0 * w->df + fabs(w->dfdot) * (nfd - 1) * max_abs_tau) * w->t_sft * tdot;
   const double width = 256.0 + 6.0 + ceil(spread - 255.0 > 0 ? spread - 255.0 : 0.0);
   const int cap = fstat::interp_max_seg(chunk);
   int W = width > cap ? cap : (int)width;
   return W & ~3;
+}
+
+int interp_seg(const fstat_plan* p, const fstat_wu* w, int nfd, int chunk) {
+  return interp_seg_tau(w, nfd, chunk, p->max_abs_tau);
 }
 
 Tile default_tile(const fstat_plan* p, const fstat_wu* w) {
@@ -246,7 +265,7 @@ Tile default_tile(const fstat_plan* p, const fstat_wu* w) {
     // SFT loop into launches keeps them in L2
     return Tile{nfd, 3, 0, nfd >= 4 ? 0 : 256};
   }
-  return Tile{1, 16, 0, 0};
+  return Tile{4, 4, 0, 0};   // fastest direct tile on the work-unit-shaped case
 }
 
 Tile pick_tile(const fstat_plan* p, const fstat_wu* w) {
@@ -308,6 +327,201 @@ int run_demod(fstat_plan* p, const WuDev& v, const Tile& t, hipStream_t st) {
   return rc;
 }
 
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct WuScratch {
+  size_t geo, abcd, coef, total;
+};
+
+WuScratch wu_scratch(const fstat_wu* w) {
+  WuScratch r;
+  r.geo = align256((size_t)w->n_sky * w->n_sft * sizeof(double2));
+  r.abcd = align256((size_t)w->n_sky * sizeof(double4));
+  r.coef = align256((size_t)w->n_sft * w->n_bins * fstat::kCoefPairs * sizeof(float4));
+  r.total = r.geo + r.abcd + r.coef;
+  return r;
+}
+
+template <class T>
+int ensure_pinned_pair(fstat_plan* p, T** dev, T** host, size_t* cap, size_t need, const char* what) {
+  if (*cap >= need) return FSTAT_OK;
+  (void)hipDeviceSynchronize();                    // earlier batches may still read the old table
+  for (auto& kv : p->graphs) (void)hipGraphExecDestroy(kv.second);
+  p->graphs.clear();
+  if (*dev) (void)hipFree(*dev);
+  if (*host) (void)hipHostFree(*host);
+  *dev = nullptr;
+  *host = nullptr;
+  *cap = 0;
+  if (++p->n_malloc == p->fail_malloc_at) return set_err(p, FSTAT_E_NOMEM, "%s: injected allocation failure", what);
+  if (hipMalloc((void**)dev, need * sizeof(T)) != hipSuccess ||
+      hipHostMalloc((void**)host, need * sizeof(T), hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    return set_err(p, FSTAT_E_NOMEM, "%s: allocation of %zu entries failed", what, need);
+  }
+  *cap = need;
+  return FSTAT_OK;
+}
+
+// Geometry and band check of work units [k0, k1) into their status slots,
+// with the geometry written to `geo_base` (one work unit at a time).
+int batch_check(fstat_plan* p, const fstat_wu* wus, const fstat_out* outs, int k0, int k1, char* geo_base,
+                const std::vector<size_t>& offs, hipStream_t st) {
+  for (int k = k0; k < k1; ++k) {
+    WuDev v = make_dev(p, &wus[k], &outs[k]);
+    const WuScratch sc = wu_scratch(&wus[k]);
+    v.geo = (double2*)(geo_base + offs[k]);
+    v.abcd = (double4*)(geo_base + offs[k] + sc.geo);
+    int rc = check_launch(p, fstat::launch_fill_int((int*)(p->bstat_d + k), 0, sizeof(fstat::GeoStatus) / sizeof(int), st),
+                          "status reset");
+    if (rc) return rc;
+    rc = check_launch(p, fstat::launch_geometry(v, p->bstat_d + k, st), "geometry kernel");
+    if (rc) return rc;
+  }
+  hipError_t e = hipMemcpyAsync(p->bstat_h + k0, p->bstat_d + k0, (size_t)(k1 - k0) * sizeof(fstat::GeoStatus),
+                                hipMemcpyDeviceToHost, st);
+  if (e != hipSuccess) return hip_err(p, e, "status copy");
+  e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_err(p, e, "geometry kernel");
+  for (int k = k0; k < k1; ++k) {
+    const int f = p->bstat_h[k].flags;
+    if (f & 1) return set_err(p, FSTAT_E_BAND, "work unit %d: a Dirichlet window [k*-D+1, k*+D] leaves the stored band", k);
+    if (f & 2) return set_err(p, FSTAT_E_ARG, "work unit %d: antenna-pattern matrix is singular (A B - C^2 <= 0)", k);
+  }
+  return FSTAT_OK;
+}
+
+double status_tau(const fstat::GeoStatus& g) {
+  double t;
+  memcpy(&t, &g.max_abs_tau_bits, sizeof t);
+  return t;
+}
+
+// Batched interp path: work units are grouped so that one group's scratch
+// (geometry, A,B,C, coefficients) fits the budget; per group the geometry is
+// computed and checked, the work-unit table is uploaded, and the coefficient
+// pass plus the persistent demodulation kernel run as one captured graph.
+int batch_interp(fstat_plan* p, const fstat_wu* wus, int n, const fstat_out* outs, hipStream_t st) {
+  std::vector<size_t> offs(n);
+  std::vector<std::pair<int, int>> groups;
+  double budget_gb = 64.0;
+  if (const char* e = getenv("FSTAT_BATCH_SCRATCH_GB")) budget_gb = atof(e) > 0 ? atof(e) : budget_gb;
+  const size_t budget = (size_t)(budget_gb * 1073741824.0);
+  size_t cur = 0, biggest = 0;
+  int g0 = 0;
+  for (int k = 0; k < n; ++k) {
+    const size_t need = wu_scratch(&wus[k]).total;
+    if (cur > 0 && cur + need > budget) {
+      groups.push_back({g0, k});
+      g0 = k;
+      cur = 0;
+    }
+    offs[k] = cur;
+    cur += need;
+    biggest = cur > biggest ? cur : biggest;
+  }
+  groups.push_back({g0, n});
+  int rc = dev_alloc(p, &p->arena, &p->arena_bytes, biggest, "batch scratch");
+  if (rc) return rc;
+  rc = ensure_pinned_pair(p, &p->bstat_d, &p->bstat_h, &p->bstat_cap, (size_t)n, "batch status");
+  if (rc) return rc;
+  rc = ensure_pinned_pair(p, &p->ents_d, &p->ents_h, &p->ents_cap, (size_t)n, "work-unit table");
+  if (rc) return rc;
+  for (int k = 0; k < n; ++k) {
+    rc = ensure_ctab(p, wus[k].dterms);
+    if (rc) return rc;
+  }
+  if (!p->counter) {
+    size_t have = 0;
+    rc = dev_alloc(p, (void**)&p->counter, &have, 64, "tile counter");
+    if (rc) return rc;
+  }
+  if (!p->batch_grid) p->batch_grid = fstat::interp_batch_grid();
+  // every work unit is checked before anything is demodulated
+  if (groups.size() > 1) {
+    for (auto& g : groups) {
+      for (int k = g.first; k < g.second; ++k) {
+        rc = batch_check(p, wus, outs, k, k + 1, (char*)p->arena, std::vector<size_t>(n, 0), st);
+        if (rc) return rc;
+      }
+    }
+  }
+  bool first = true;
+  for (auto& g : groups) {
+    rc = batch_check(p, wus, outs, g.first, g.second, (char*)p->arena, offs, st);
+    if (rc) return rc;
+    // table of the group, most SFTs first
+    std::vector<int> order;
+    for (int k = g.first; k < g.second; ++k) order.push_back(k);
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return wus[x].n_sft > wus[y].n_sft; });
+    fstat::BatchEntry* eh = p->ents_h + g.first;
+    int64_t tiles = 0, blocks = 0;
+    for (size_t q = 0; q < order.size(); ++q) {
+      const int k = order[q];
+      fstat::BatchEntry& e = eh[q];
+      WuDev v = make_dev(p, &wus[k], &outs[k]);
+      const WuScratch sc = wu_scratch(&wus[k]);
+      char* base = (char*)p->arena + offs[k];
+      v.geo = (double2*)base;
+      v.abcd = (double4*)(base + sc.geo);
+      v.coef = (float4*)(base + sc.geo + sc.abcd);
+      v.acc = nullptr;
+      e.w = v;
+      e.nfd = wus[k].n_fd >= 8 ? 8 : 4;
+      e.seg = interp_seg_tau(&wus[k], e.nfd, 1, status_tau(p->bstat_h[k]));
+      e.n_tiles = fstat::interp_tiles(v, e.nfd);
+      e.tile_begin = tiles;
+      e.coef_begin = blocks;
+      tiles += e.n_tiles;
+      blocks += fstat::coef_blocks(v);
+    }
+    const int m = (int)order.size();
+    fstat::BatchEntry* ed = p->ents_d + g.first;
+    hipError_t e = hipMemcpyAsync(ed, eh, (size_t)m * sizeof(fstat::BatchEntry), hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return hip_err(p, e, "work-unit table upload");
+    if (first) {
+      (void)hipEventRecord(p->ev0, st);
+      first = false;
+    }
+    if (p->d.flags & FSTAT_FLAG_NO_GRAPH) {
+      rc = check_launch(p, fstat::launch_coef_batch(ed, m, blocks, st), "coefficient kernel");
+      if (rc) return rc;
+      rc = check_launch(p, fstat::launch_interp_batch(ed, m, tiles, p->counter, p->batch_grid, st), "batch kernel");
+      if (rc) return rc;
+      continue;
+    }
+    const std::vector<int64_t> sig = {(int64_t)(intptr_t)ed, m, blocks, tiles, p->batch_grid};
+    auto it = p->graphs.find(sig);
+    if (it == p->graphs.end()) {
+      if (!p->cap_stream) {
+        if (hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess)
+          return set_err(p, FSTAT_E_DEVICE, "capture stream creation failed");
+      }
+      e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal);
+      if (e != hipSuccess) return hip_err(p, e, "graph capture");
+      hipError_t e1 = fstat::launch_coef_batch(ed, m, blocks, p->cap_stream);
+      hipError_t e2 = fstat::launch_interp_batch(ed, m, tiles, p->counter, p->batch_grid, p->cap_stream);
+      hipGraph_t graph = nullptr;
+      e = hipStreamEndCapture(p->cap_stream, &graph);
+      if (e1 != hipSuccess || e2 != hipSuccess || e != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return hip_err(p, e1 != hipSuccess ? e1 : (e2 != hipSuccess ? e2 : e), "graph capture");
+      }
+      hipGraphExec_t exec = nullptr;
+      e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (e != hipSuccess) return hip_err(p, e, "graph instantiation");
+      it = p->graphs.emplace(sig, exec).first;
+    }
+    if (++p->n_launch == p->fail_launch_at) return set_err(p, FSTAT_E_DEVICE, "graph launch: injected launch failure");
+    e = hipGraphLaunch(it->second, st);
+    if (e != hipSuccess) return hip_err(p, e, "graph launch");
+  }
+  (void)hipEventRecord(p->ev1, st);
+  p->timed = true;
+  return FSTAT_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -365,6 +579,14 @@ void fstat_plan_destroy(fstat_plan* p) {
   (void)hipDeviceSynchronize();
   if (p->geo) (void)hipFree(p->geo);
   if (p->abcd) (void)hipFree(p->abcd);
+  for (auto& kv : p->graphs) (void)hipGraphExecDestroy(kv.second);
+  if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+  if (p->arena) (void)hipFree(p->arena);
+  if (p->bstat_d) (void)hipFree(p->bstat_d);
+  if (p->bstat_h) (void)hipHostFree(p->bstat_h);
+  if (p->ents_d) (void)hipFree(p->ents_d);
+  if (p->ents_h) (void)hipHostFree(p->ents_h);
+  if (p->counter) (void)hipFree(p->counter);
   if (p->coef) (void)hipFree(p->coef);
   if (p->acc) (void)hipFree(p->acc);
   for (auto& kv : p->ctab) (void)hipFree(kv.second);
@@ -403,6 +625,9 @@ int fstat_batch_compute(fstat_plan* p, const fstat_wu* wus, int32_t n_wu, const 
   }
   if (hipSetDevice(p->device) != hipSuccess) return set_err(p, FSTAT_E_DEVICE, "hipSetDevice failed");
   hipStream_t st = (hipStream_t)stream;
+  if (n_wu == 0) return FSTAT_OK;
+  if (resolved_kernel(p) == fstat::KERNEL_INTERP) return batch_interp(p, wus, n_wu, outs, st);
+  // direct kernel: one work unit after the other
   for (int k = 0; k < n_wu; ++k) {
     int rc = ensure_scratch(p, &wus[k]);
     if (rc) return rc;

@@ -52,6 +52,18 @@ constexpr int kCoefPairs = kCoef / 2;
 constexpr int kMaxRuns = 5;
 constexpr int kSegMax = 64 * kMaxRuns;
 
+// One work unit of a batched launch: its device view, its slice width, its
+// spindowns per thread (4 or 8) and the index of its first tile in the
+// concatenated tile list.
+struct BatchEntry {
+  WuDev w;
+  int32_t seg;
+  int32_t nfd;
+  int64_t tile_begin;   // first tile in the concatenated tile list
+  int64_t n_tiles;
+  int64_t coef_begin;   // first block of the batched coefficient pass
+};
+
 // Geometry pass results read back by the host.
 struct GeoStatus {
   int flags;                  // bit 1: window outside the band; bit 2: AB - C^2 <= 0
@@ -73,6 +85,12 @@ hipError_t launch_geometry(const WuDev& w, GeoStatus* status, hipStream_t s);
 hipError_t launch_coef(const WuDev& w, hipStream_t s);
 hipError_t launch_demod(const WuDev& w, const Tile& t, int kernel, hipStream_t s);
 int interp_launches(const WuDev& w, const Tile& t);
+int64_t interp_tiles(const WuDev& w, int nfd);
+int64_t coef_blocks(const WuDev& w);
+hipError_t launch_coef_batch(const BatchEntry* ents_dev, int n_ent, int64_t total_blocks, hipStream_t s);
+hipError_t launch_interp_batch(const BatchEntry* ents_dev, int n_ent, int64_t total_tiles,
+                               unsigned long long* counter, int grid, hipStream_t s);
+int interp_batch_grid();
 hipError_t launch_bins(const WuDev& w, int64_t n, const int32_t* i_sky, const int32_t* i_fd, const int32_t* i_f,
                        const int32_t* i_sft, int64_t* kstar, double* kappa, double* phi_frac, hipStream_t s);
 size_t demod_lds_bytes(const WuDev& w, const Tile& t, int kernel);

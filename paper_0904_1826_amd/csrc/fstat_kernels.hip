@@ -353,13 +353,11 @@ __global__ __launch_bounds__(kThreads) void demod_direct_kernel(WuDev w) {
 // (c_p, c_p+1) per float4); the demodulation kernel then evaluates one
 // polynomial per (template, SFT) pair instead of 2D weighted terms.  Bins
 // whose window would leave the band get zeros (no valid k* selects them).
-__global__ __launch_bounds__(256) void coef_kernel(WuDev w) {
-  __shared__ float2 xs[256 + 2 * kMaxDterms];
-  __shared__ double tab[2 * kMaxDterms * kCoef];
+__device__ __forceinline__ void coef_block(const WuDev& w, int64_t block, float2* xs, double* tab) {
   const int D = w.dterms;
   const int64_t n_cc = (w.n_bins + 255) / 256;
-  const int64_t al = blockIdx.x / n_cc;
-  const int64_t c0 = (blockIdx.x % n_cc) * 256;
+  const int64_t al = block / n_cc;
+  const int64_t c0 = (block % n_cc) * 256;
   const int tid = threadIdx.x;
   for (int e = tid; e < 2 * D * kCoef; e += 256) tab[e] = w.ctab[e];
   for (int e = tid; e < 256 + 2 * D; e += 256) {
@@ -392,6 +390,27 @@ __global__ __launch_bounds__(256) void coef_kernel(WuDev w) {
 #pragma unroll
   for (int q = 0; q < kCoefPairs; ++q)
     dst[q * w.n_bins] = make_float4((float)cr[2 * q], (float)ci[2 * q], (float)cr[2 * q + 1], (float)ci[2 * q + 1]);
+}
+
+__global__ __launch_bounds__(256) void coef_kernel(WuDev w) {
+  __shared__ float2 xs[256 + 2 * kMaxDterms];
+  __shared__ double tab[2 * kMaxDterms * kCoef];
+  coef_block(w, blockIdx.x, xs, tab);
+}
+
+// The coefficient pass of many work units in one launch; block b belongs to
+// the last entry whose coef_begin <= b.
+__global__ __launch_bounds__(256) void coef_batch_kernel(const BatchEntry* __restrict__ ents, int n_ent) {
+  __shared__ float2 xs[256 + 2 * kMaxDterms];
+  __shared__ double tab[2 * kMaxDterms * kCoef];
+  const int64_t b = blockIdx.x;
+  int lo = 0, hi = n_ent - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (ents[mid].coef_begin <= b) lo = mid; else hi = mid - 1;
+  }
+  const WuDev w = ents[lo].w;
+  coef_block(w, b - ents[lo].coef_begin, xs, tab);
 }
 
 struct CoefSet {
@@ -547,16 +566,13 @@ __device__ __forceinline__ void interp_accumulate(float4 c01, float4 c23, float4
 // a/b accumulation in registers.  An SFT whose windows are not all inside
 // the slice (only possible for slices narrower than the tile's spread) takes
 // the same arithmetic with coefficients read from global memory.
-template <int NFD, int S, int MINW>
-__global__ __launch_bounds__(kThreads, MINW) void demod_interp_kernel(WuDev w, int W, int64_t al_begin,
-                                                                     int64_t al_end) {
-  __shared__ float4 cbuf0[kCoefPairs * kSegMax];
-  __shared__ float4 cbuf1[kCoefPairs * kSegMax];
-  __shared__ GroupMeta<NFD, S> meta[2];
+template <int NFD, int S>
+__device__ __forceinline__ void interp_tile(const WuDev& w, int W, int64_t tile, int64_t al_begin, int64_t al_end,
+                                            float4* cbuf0, float4* cbuf1, GroupMeta<NFD, S>* meta) {
   const int tid = threadIdx.x;
   const int64_t n_fdb = (w.n_fd + NFD - 1) / NFD;
   constexpr int Wp = kSegMax;                      // LDS row stride
-  int64_t t = blockIdx.x;
+  int64_t t = tile;
   const int64_t s = t % w.n_sky;
   t /= w.n_sky;
   const int64_t ib = t % n_fdb;
@@ -663,6 +679,55 @@ __global__ __launch_bounds__(kThreads, MINW) void demod_interp_kernel(WuDev w, i
   }
 }
 
+// One tile per work-group (see interp_tile).
+template <int NFD, int S, int MINW>
+__global__ __launch_bounds__(kThreads, MINW) void demod_interp_kernel(WuDev w, int W, int64_t al_begin,
+                                                                     int64_t al_end) {
+  __shared__ float4 cbuf0[kCoefPairs * kSegMax];
+  __shared__ float4 cbuf1[kCoefPairs * kSegMax];
+  __shared__ GroupMeta<NFD, S> meta[2];
+  interp_tile<NFD, S>(w, W, blockIdx.x, al_begin, al_end, cbuf0, cbuf1, meta);
+}
+
+// Many work units in one persistent launch: the grid holds as many
+// work-groups as fit on the device at once; each takes the next tile of the
+// concatenated tile list from a device counter until none is left (every
+// work-group reaches that exit).  Entries are ordered by cost (SFT count)
+// descending, so the long tiles start first and the tail is short.  Tiles of
+// one work unit are sky point fastest, as in the single-unit kernel, so the
+// work-groups running at once share coefficient slices in L2.  Dterms may
+// differ between work units: the window is folded into the coefficients.
+__global__ __launch_bounds__(kThreads, 2) void demod_interp_batch_kernel(const BatchEntry* __restrict__ ents,
+                                                                         int n_ent, int64_t total_tiles,
+                                                                         unsigned long long* counter) {
+  __shared__ float4 cbuf0[kCoefPairs * kSegMax];
+  __shared__ float4 cbuf1[kCoefPairs * kSegMax];
+  __shared__ GroupMeta<8, 16> meta8[2];
+  __shared__ GroupMeta<4, 16> meta4[2];
+  __shared__ unsigned long long next;
+  for (;;) {
+    if (threadIdx.x == 0) next = atomicAdd(counter, 1ull);
+    __syncthreads();
+    const int64_t tile = (int64_t)next;
+    __syncthreads();                                 // all have read `next` before it is replaced
+    if (tile >= total_tiles) break;
+    int lo = 0, hi = n_ent - 1;                      // last entry with tile_begin <= tile
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (ents[mid].tile_begin <= tile) lo = mid; else hi = mid - 1;
+    }
+    lo = __builtin_amdgcn_readfirstlane(lo);
+    const WuDev w = ents[lo].w;
+    const int W = ents[lo].seg;
+    const int64_t local = tile - ents[lo].tile_begin;
+    if (ents[lo].nfd == 8)
+      interp_tile<8, 16>(w, W, local, 0, w.n_sft, cbuf0, cbuf1, meta8);
+    else
+      interp_tile<4, 16>(w, W, local, 0, w.n_sft, cbuf0, cbuf1, meta4);
+    __syncthreads();                                 // LDS free for the next tile
+  }
+}
+
 // ------------------------------------------------------------ bin probe
 __global__ void bins_kernel(WuDev w, int64_t n, const int32_t* i_sky, const int32_t* i_fd, const int32_t* i_f,
                             const int32_t* i_sft, int64_t* kstar, double* kappa, double* phi_frac) {
@@ -713,6 +778,39 @@ hipError_t launch_coef(const WuDev& w, hipStream_t st) {
   const int64_t blocks = ((w.n_bins + 255) / 256) * w.n_sft;
   if (blocks <= 0 || blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
   hipLaunchKernelGGL(coef_kernel, dim3((unsigned)blocks), dim3(256), 0, st, w);
+  return hipGetLastError();
+}
+
+int64_t coef_blocks(const WuDev& w) { return ((w.n_bins + 255) / 256) * w.n_sft; }
+
+hipError_t launch_coef_batch(const BatchEntry* ents_dev, int n_ent, int64_t total_blocks, hipStream_t st) {
+  if (n_ent <= 0 || total_blocks <= 0) return hipSuccess;
+  if (total_blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL(coef_batch_kernel, dim3((unsigned)total_blocks), dim3(256), 0, st, ents_dev, n_ent);
+  return hipGetLastError();
+}
+
+int64_t interp_tiles(const WuDev& w, int nfd) {
+  return ((w.n_f + kThreads - 1) / kThreads) * ((w.n_fd + nfd - 1) / nfd) * w.n_sky;
+}
+
+int interp_batch_grid() {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    cus = 256;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, demod_interp_batch_kernel, kThreads, 0) != hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  return per_cu * cus;
+}
+
+hipError_t launch_interp_batch(const BatchEntry* ents_dev, int n_ent, int64_t total_tiles,
+                               unsigned long long* counter, int grid, hipStream_t st) {
+  if (n_ent <= 0 || total_tiles <= 0) return hipSuccess;
+  hipError_t e = launch_fill_int((int*)counter, 0, 2, st);   // kernel, not memset: safe under capture
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(demod_interp_batch_kernel, dim3((unsigned)grid), dim3(kThreads), 0, st, ents_dev, n_ent,
+                     total_tiles, counter);
   return hipGetLastError();
 }
 

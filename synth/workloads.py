@@ -303,3 +303,39 @@ def make_config(idx: int, *, seed: Optional[int] = None, **over):
     name = over.pop("name", None) or CONFIG_NAMES[idx] + ("" if not over else "-custom")
     p.pop("name", None)
     return make_workload(name, seed=seed, **p)
+
+
+BATCH_NAMES = {
+    3: "batch-64wu-200to2000sft-900to7200bins",
+}
+
+
+def make_batch(idx: int = 3, *, seed: Optional[int] = None, n_wu: Optional[int] = None, scale: float = 1.0,
+               noise: bool = True):
+    """Many work units with uneven shapes.  Recipe 3: 64 work units, each with
+    U{200..2000} SFTs split over 2 detectors (all slots kept, jitter 60 s),
+    a band of U{900..7200} template bins starting at U[50, 1500] Hz,
+    U{500..4000} sky points x U{4..16} spindowns in [-1e-9, 0], Dterms 8 or
+    16, one injected signal.  `scale` < 1 shrinks SFT counts, bands and sky
+    points proportionally (for tests); `n_wu` truncates the list."""
+    if idx != 3:
+        raise ValueError(f"no batch recipe {idx}")
+    seed = 1000 + idx if seed is None else seed
+    rng = np.random.Generator(np.random.PCG64(seed))
+    total = 64 if n_wu is None else n_wu
+    wus = []
+    for u in range(total):
+        n_sft = max(4, int(round(rng.integers(200, 2001) * scale)))
+        band = max(64, int(round(rng.integers(900, 7201) * scale)))
+        f0 = float(rng.uniform(50.0, 1500.0))
+        f0 = round(f0 * 1800.0) / 1800.0
+        n_sky = max(1, int(round(rng.integers(500, 4001) * scale)))
+        n_fd = int(rng.integers(4, 17))
+        dterms = int(rng.choice([8, 16]))
+        inj = [(int(rng.integers(0, n_sky)), int(rng.integers(0, n_fd)), int(rng.integers(band // 4, 3 * band // 4)),
+                float(rng.uniform(10.0, 20.0)))]
+        w = make_workload(f"{BATCH_NAMES[idx]}-{u}", seed=seed * 1000 + u, n_det=2, slots_per_det=(n_sft + 1) // 2,
+                          keep_frac=1.0, jitter=60.0, t_sft=1800.0, f0=f0, n_f=band, n_sky=n_sky, n_fd=n_fd,
+                          fdot_lo=-1.0e-9, fdot_hi=0.0, dterms=dterms, injections=inj, noise=noise)
+        wus.append(w)
+    return wus

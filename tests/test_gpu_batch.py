@@ -1,0 +1,153 @@
+"""Batched form: many work units with uneven SFT counts, bands, grids and
+Dterms in one persistent launch (replayed from a captured hipGraph), checked
+against single-work-unit calls and against the FP64 oracle."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from synth.device import to_device, alloc_output
+from tests._helpers import small_workload, replace, twoF_error
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _plan_for(ws, **kw):
+    import paper_0904_1826_amd as P
+    return P.Plan(max_sft=max(w.n_sft for w in ws), max_bins=max(w.n_bins for w in ws),
+                  max_sky=max(w.n_sky for w in ws), max_fd=max(w.n_fd for w in ws), max_f=max(w.n_f for w in ws),
+                  max_dterms=max(max(w.dterms for w in ws), 16), **kw)
+
+
+def _batch(torch, ws, storage="c64", **kw):
+    devs = [to_device(w, storage) for w in ws]
+    outs = [alloc_output(w) for w in ws]
+    with _plan_for(ws, storage=storage, **kw) as p:
+        p.batch_compute([d[0] for d in devs], outs)
+        torch.cuda.synchronize()
+    return outs, devs
+
+
+def test_batch_matches_single_and_oracle(torch_cuda, oracle_lib):
+    torch = torch_cuda
+    ws = synth.make_batch(3, n_wu=6, scale=0.1)
+    _say("batch shapes:", [(w.n_sft, w.n_bins, w.n_sky, w.n_fd, w.n_f, w.dterms) for w in ws])
+    outs, devs = _batch(torch, ws)
+    for k, w in enumerate(ws):
+        single = alloc_output(w)
+        with _plan_for([w]) as p:
+            p.compute(devs[k][0], single)
+            torch.cuda.synchronize()
+        a = outs[k].twoF.cpu().numpy()
+        b = single.twoF.cpu().numpy()
+        assert np.array_equal(a, b), (k, np.max(np.abs(a - b)))
+        s, i, j = oracle_lib.all_templates(w, [0, w.n_sky - 1])
+        ref = oracle_lib.fstat(w, (s, i, j))["twoF"]
+        e = twoF_error(a[s, i, j], ref)
+        _say(f"  wu {k}: D={w.dterms} n_fd={w.n_fd} max_e={e.max():.2e}")
+        assert e.max() <= 1e-4
+
+
+def test_batch_graph_replay_follows_new_contents(torch_cuda, oracle_lib):
+    """The second call replays the captured graph; the work-unit table lives in
+    device memory, so new data (and new buffers) of the same shapes are used."""
+    torch = torch_cuda
+    ws = synth.make_batch(3, n_wu=4, scale=0.06, seed=77)
+    devs = [to_device(w)[0] for w in ws]
+    outs = [alloc_output(w) for w in ws]
+    with _plan_for(ws) as p:
+        p.batch_compute(devs, outs)
+        torch.cuda.synchronize()
+        first = [o.twoF.clone() for o in outs]
+        p.batch_compute(devs, outs)                  # replay, same inputs
+        torch.cuda.synchronize()
+        for a, b in zip(first, outs):
+            assert torch.equal(a, b.twoF)
+        for d in devs:
+            d.sft.mul_(2.0)                            # 2F scales by 4 exactly (powers of two)
+        outs2 = [alloc_output(w) for w in ws]          # new output buffers
+        p.batch_compute(devs, outs2)
+        torch.cuda.synchronize()
+        for a, b in zip(first, outs2):
+            assert torch.allclose(b.twoF, 4.0 * a, rtol=1e-6, atol=1e-5)
+        for d in devs:
+            d.sft.mul_(0.5)
+        # different shapes: a new graph
+        ws2 = ws[:3]
+        outs3 = [alloc_output(w) for w in ws2]
+        p.batch_compute(devs[:3], outs3)
+        torch.cuda.synchronize()
+        for a, b in zip(first[:3], outs3):
+            assert torch.equal(a, b.twoF)
+
+
+def test_batch_without_graph_is_identical(torch_cuda):
+    import paper_0904_1826_amd as P
+    torch = torch_cuda
+    ws = synth.make_batch(3, n_wu=3, scale=0.05, seed=5)
+    a, _ = _batch(torch, ws)
+    b, _ = _batch(torch, ws, flags=P.FSTAT_FLAG_NO_GRAPH)
+    for x, y in zip(a, b):
+        assert torch.equal(x.twoF, y.twoF)
+
+
+def test_batch_band_error_names_the_work_unit(torch_cuda, oracle_lib):
+    import paper_0904_1826_amd as P
+    torch = torch_cuda
+    ws = synth.make_batch(3, n_wu=3, scale=0.05, seed=9)
+    w = ws[1]
+    s, i, j = oracle_lib.all_templates(w)
+    k, _, _, _ = oracle_lib.bins(w, (s, i, j))
+    lo = int(k.min()) - w.dterms + 2                   # one bin short at the bottom
+    c0 = lo - w.k_first
+    ws[1] = replace(w, sft=np.ascontiguousarray(w.sft[:, c0:]), k_first=lo)
+    outs = [alloc_output(x) for x in ws]
+    for o in outs:
+        o.twoF.fill_(-7.0)
+    with _plan_for(ws) as p:
+        with pytest.raises(P.FstatError) as e:
+            p.batch_compute([to_device(x)[0] for x in ws], outs)
+        assert e.value.code == P.FSTAT_E_BAND
+        assert "work unit 1" in str(e.value)
+    torch.cuda.synchronize()
+    for o in outs:                                    # nothing was demodulated
+        assert bool((o.twoF == -7.0).all())
+
+
+def test_batch_groups_under_a_small_scratch_budget(torch_cuda, monkeypatch):
+    """With a tiny scratch budget every work unit forms its own group (its own
+    table slice and graph); results are unchanged."""
+    torch = torch_cuda
+    ws = synth.make_batch(3, n_wu=4, scale=0.05, seed=11)
+    a, _ = _batch(torch, ws)
+    monkeypatch.setenv("FSTAT_BATCH_SCRATCH_GB", "0.000001")
+    b, _ = _batch(torch, ws)
+    for x, y in zip(a, b):
+        assert torch.equal(x.twoF, y.twoF)
+
+
+@pytest.mark.parametrize("storage", ["bf16", "fp16"])
+def test_batch_16bit_storage(torch_cuda, oracle_lib, storage):
+    torch = torch_cuda
+    ws = synth.make_batch(3, n_wu=3, scale=0.06, seed=13)
+    outs, devs = _batch(torch, ws, storage=storage)
+    for k, w in enumerate(ws):
+        s, i, j = oracle_lib.all_templates(w, [0])
+        ref = oracle_lib.fstat(w, (s, i, j), sft=devs[k][1])["twoF"]
+        e = twoF_error(outs[k].twoF.cpu().numpy()[s, i, j], ref)
+        assert e.max() <= 1e-4, (k, e.max())
