@@ -176,6 +176,7 @@ WuDev make_dev(const fstat_plan* p, const fstat_wu* w, const fstat_out* o) {
   v.t_ref = w->t_ref;
   v.dterms = w->dterms;
   v.storage = p->d.storage;
+  v.phase_mode = p->d.phase_mode;
   return v;
 }
 
@@ -557,8 +558,8 @@ int fstat_plan_create(fstat_plan** out, const fstat_desc* d) {
     return FSTAT_E_DEVICE;
   }
   p->cu_count = prop.multiProcessorCount;
-  if (p->d.phase_mode == FSTAT_PHASE_SPLIT_FP32) {
-    // not built in this version of the library
+  if (p->d.phase_mode == FSTAT_PHASE_SPLIT_FP32 && p->d.kernel == FSTAT_KERNEL_DIRECT) {
+    // the split phase form is built into the interpolated kernel only
     delete p;
     return FSTAT_E_UNSUPPORTED;
   }

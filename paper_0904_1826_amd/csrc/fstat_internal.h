@@ -27,6 +27,7 @@ struct WuDev {
   double t_sft, f0, df, fdot0, dfdot, t_ref;
   int32_t dterms;
   int32_t storage;
+  int32_t phase_mode;      // 0: frac(phi) in FP64; 1: in double-FP32 (split) products
 };
 
 // Tile shape of the demodulation kernels.

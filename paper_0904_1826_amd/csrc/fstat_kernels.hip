@@ -37,6 +37,31 @@ __device__ __forceinline__ double bin_position(double f, double g, double tdot, 
 
 __device__ __forceinline__ double fract64(double x) { return __builtin_amdgcn_fract(x); }
 
+// FP64 value as an unevaluated sum hi + lo of two FP32 (48 significant bits).
+__device__ __forceinline__ float2 split64(double x) {
+  const float hi = (float)x;
+  return make_float2(hi, (float)(x - (double)hi));
+}
+
+__device__ __forceinline__ float frac32(float x) { return x - floorf(x); }
+
+// frac(a * b) for a = a.x + a.y, b = b.x + b.y in FP32 arithmetic only: each
+// partial product is split into its rounded value and its exact rounding
+// error (Dekker's product with a fused multiply-add), the fractional part of
+// every term is taken exactly, and only the small remainders are summed.
+// Resolution: that of the 48-bit operands (about 5e-5 cycles for a
+// 1.2e7 s baseline at 1.5 kHz) plus a few FP32 roundings of values below 4.
+__device__ __forceinline__ float frac_split_product(float2 a, float2 b) {
+  const float p = a.x * b.x, pe = __builtin_fmaf(a.x, b.x, -p);
+  const float q = a.x * b.y, qe = __builtin_fmaf(a.x, b.y, -q);
+  const float r = a.y * b.x, re = __builtin_fmaf(a.y, b.x, -r);
+  const float t = a.y * b.y;
+  float acc = frac32(p) + frac32(pe);
+  acc += frac32(q) + frac32(r);
+  acc += (qe + re) + t;
+  return frac32(acc);
+}
+
 // sin(2 pi x) and cos(2 pi x) for x in revolutions (hardware transcendental
 // units; |x| < 256).
 __device__ __forceinline__ float sin_rev(float x) { return __builtin_amdgcn_sinf(x); }
@@ -438,6 +463,7 @@ __device__ __forceinline__ CoefSet load_coef_global(const WuDev& w, int64_t al, 
 template <int NFD, int S>
 struct GroupMeta {
   double2 geo[S];     // (tau, Tdot) of the sky point
+  float2 tsplit[S];   // tau as hi + lo FP32 (split phase mode)
   float a[S], b[S];
   int lo[S];
   int fast[S];
@@ -456,6 +482,7 @@ __device__ __forceinline__ void group_meta(const WuDev& w, const double2* geo, c
   const int t3 = tid - (kThreads - 2 * S);       // S threads before the last S copy tau, Tdot, a, b
   if (t3 >= 0 && t3 < n) {
     m.geo[t3] = geo[al0 + t3];
+    m.tsplit[t3] = split64(geo[al0 + t3].x);
     m.a[t3] = arow[al0 + t3];
     m.b[t3] = brow[al0 + t3];
   }
@@ -465,7 +492,8 @@ __device__ __forceinline__ void group_meta(const WuDev& w, const double2* geo, c
     const int64_t i = (i0 + r < w.n_fd) ? i0 + r : w.n_fd - 1;
     const double fd = template_fd(w, i);
     m.g[c][r] = fd * g.x;
-    const float q = (float)fract64(g.x * ((0.5 * fd) * g.x));
+    const double h = (0.5 * fd) * g.x;                 // (fdot / 2) tau
+    const float q = w.phase_mode ? frac_split_product(split64(g.x), split64(h)) : (float)fract64(g.x * h);
     m.e[c][r] = make_float2(cos_rev(q), -sin_rev(q));
   }
   const int t2 = tid - (kThreads - S);           // the last S threads do the slice bounds
@@ -586,6 +614,8 @@ __device__ __forceinline__ void interp_tile(const WuDev& w, int W, int64_t tile,
   const int64_t i_last = (i0 + NFD - 1 < w.n_fd - 1) ? i0 + NFD - 1 : w.n_fd - 1;
   const double T = w.t_sft;
   const double f = template_f(w, j);
+  const float2 fsplit = split64(f);
+  const bool split_phase = w.phase_mode != 0;
   const double f_first = template_f(w, j0), f_last = template_f(w, j_last);
   const double2* geo = w.geo + s * w.n_sft;
   const float* arow = w.a + s * w.n_sft;
@@ -628,7 +658,8 @@ __device__ __forceinline__ void interp_tile(const WuDev& w, int W, int64_t tile,
     const int64_t al = al_begin + k;
     const double2 g = m.geo[kk];
     const float a = m.a[kk], b = m.b[kk];
-    const float pf = (float)fract64(g.x * f);                      // frac(tau f)
+    const float pf = split_phase ? frac_split_product(m.tsplit[kk], fsplit)   // frac(tau f)
+                                 : (float)fract64(g.x * f);
     const float cf = cos_rev(pf), sf = sin_rev(pf);
     const int base = k_first + m.lo[kk];                           // absolute bin of slice column 0
     if (__builtin_amdgcn_readfirstlane(m.fast[kk])) {
@@ -746,7 +777,13 @@ __global__ void bins_kernel(WuDev w, int64_t n, const int32_t* i_sky, const int3
   const double dphi = bin_position(f, fd * tau, tdot, w.t_sft);
   kstar[t] = (int64_t)dphi;
   kappa[t] = fract64(dphi);
-  phi_frac[t] = fract64(tau * (f + (0.5 * fd) * tau));
+  if (w.phase_mode) {       // the demodulation kernel's split form: frac(tau f) + frac(tau (fdot/2) tau)
+    const float a = frac_split_product(split64(tau), split64(f));
+    const float b = frac_split_product(split64(tau), split64((0.5 * fd) * tau));
+    phi_frac[t] = (double)frac32(a + b);
+  } else {
+    phi_frac[t] = fract64(tau * (f + (0.5 * fd) * tau));
+  }
 }
 
 // Small fill kernel used instead of hipMemsetAsync, so that the same code is
