@@ -135,7 +135,7 @@ def fstat(w, templates=None, *, sft: Optional[np.ndarray] = None, nthreads: Opti
 def bins(w, templates):
     """k* (int64), kappa, frac(phi), Dphi of every (template, SFT), [n_tmpl, n_sft]."""
     lib = _load()
-    pk = _Packed(w, None if w.sft.size else np.zeros((w.n_sft, 1)))
+    pk = _Packed(w, np.zeros((w.n_sft, 1), dtype=np.complex128))   # bins do not read SFT values
     ts, ti, tj = (np.ascontiguousarray(t, dtype=np.int32) for t in templates)
     n, m = len(ts), w.n_sft
     k = np.empty((n, m), dtype=np.int64)

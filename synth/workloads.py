@@ -132,7 +132,7 @@ class Injection:
 class Workload:
     """One work unit: an SFT band of every detector plus a template grid."""
     name: str
-    sft: np.ndarray            # complex64 [n_sft, n_bins]
+    sft: Optional[np.ndarray]  # complex64 [n_sft, n_bins], or None when drawn on the device
     k_first: int               # absolute bin index of column 0
     t_sft: float
     t_start: np.ndarray        # float64 [n_sft]
@@ -151,14 +151,15 @@ class Workload:
     t_ref: float
     dterms: int
     injections: List[Injection] = dataclasses.field(default_factory=list)
+    shape: Optional[tuple] = None  # (n_sft, n_bins) when `sft` is None (drawn on the device)
 
     @property
     def n_sft(self):
-        return self.sft.shape[0]
+        return self.sft.shape[0] if self.sft is not None else self.shape[0]
 
     @property
     def n_bins(self):
-        return self.sft.shape[1]
+        return self.sft.shape[1] if self.sft is not None else self.shape[1]
 
     @property
     def n_sky(self):
@@ -212,14 +213,16 @@ def _inject(w: Workload, inj: Injection, sft: np.ndarray, rng_unused=None):
     nb = w.n_bins
     j = np.arange(nb, dtype=np.int64)
     het = ((w.k_first % nb) * j) % nb                       # exact k_first*j mod nb
-    for alpha in range(w.n_sft):
-        tj = w.t_start[alpha] + j * (w.t_sft / nb)
+    chunk = max(1, (1 << 22) // nb)                          # SFTs per vectorised block
+    for a0 in range(0, w.n_sft, chunk):
+        a1 = min(w.n_sft, a0 + chunk)
+        tj = w.t_start[a0:a1, None] + j[None, :] * (w.t_sft / nb)
         r, _ = orbit(tj)
         tau = (tj - w.t_ref) + r @ n
         cyc = f * tau + 0.5 * fd * tau * tau
-        cyc = cyc - np.floor(cyc) - het / nb
-        x = s[alpha] * np.exp(2j * np.pi * cyc)
-        sft[alpha] += (np.fft.fft(x) / nb).astype(np.complex64)
+        cyc = cyc - np.floor(cyc) - het[None, :] / nb
+        x = s[a0:a1, None] * np.exp(2j * np.pi * cyc)
+        sft[a0:a1] += (np.fft.fft(x, axis=1) / nb).astype(np.complex64)
 
 
 CONFIG_NAMES = {
@@ -263,14 +266,17 @@ def make_workload(name, *, seed, n_det, slots_per_det, keep_frac, jitter, t_sft,
                                   rmax, vmax, t_sft, dterms)
     n_bins = k_last - k_first + 1
     n_sft = len(t_start)
-    if noise:
+    if noise == "device":
+        sft = None              # shapes only: the noise is drawn on the GPU (synth.device)
+    elif noise:
         z = rng.standard_normal((n_sft, n_bins, 2), dtype=np.float32) * np.float32(math.sqrt(0.5))
         sft = z.view(np.complex64).reshape(n_sft, n_bins).copy()
     else:
         sft = np.zeros((n_sft, n_bins), dtype=np.complex64)
     w = Workload(name=name, sft=sft, k_first=k_first, t_sft=t_sft, t_start=t_start, pos=pos, vel=vel,
                  det_offset=np.asarray(det_offset, dtype=np.int32), a=a, b=b, sky=sky, f0=f0, df=df,
-                 n_f=n_f, fdot0=fdot_lo, dfdot=dfdot, n_fd=n_fd, t_ref=t_ref, dterms=dterms)
+                 n_f=n_f, fdot0=fdot_lo, dfdot=dfdot, n_fd=n_fd, t_ref=t_ref, dterms=dterms,
+                 shape=(n_sft, n_bins))
     for inj in injections:
         if isinstance(inj, dict):
             inj = Injection(**inj)
@@ -307,23 +313,30 @@ def make_config(idx: int, *, seed: Optional[int] = None, **over):
 
 BATCH_NAMES = {
     3: "batch-64wu-200to2000sft-900to7200bins",
+    4: "large-256wu-2x1000to4000sft-14400bins-bf16",
 }
 
 
+def _make_workload_kw(kw):
+    return make_workload(**kw)
+
+
 def make_batch(idx: int = 3, *, seed: Optional[int] = None, n_wu: Optional[int] = None, scale: float = 1.0,
-               noise: bool = True):
+               noise: bool = True, workers: int = 1):
     """Many work units with uneven shapes.  Recipe 3: 64 work units, each with
     U{200..2000} SFTs split over 2 detectors (all slots kept, jitter 60 s),
     a band of U{900..7200} template bins starting at U[50, 1500] Hz,
     U{500..4000} sky points x U{4..16} spindowns in [-1e-9, 0], Dterms 8 or
     16, one injected signal.  `scale` < 1 shrinks SFT counts, bands and sky
     points proportionally (for tests); `n_wu` truncates the list."""
+    if idx == 4:
+        return _make_large_batch(seed=seed, n_wu=n_wu, scale=scale, workers=workers)
     if idx != 3:
         raise ValueError(f"no batch recipe {idx}")
     seed = 1000 + idx if seed is None else seed
     rng = np.random.Generator(np.random.PCG64(seed))
     total = 64 if n_wu is None else n_wu
-    wus = []
+    kws = []
     for u in range(total):
         n_sft = max(4, int(round(rng.integers(200, 2001) * scale)))
         band = max(64, int(round(rng.integers(900, 7201) * scale)))
@@ -334,8 +347,40 @@ def make_batch(idx: int = 3, *, seed: Optional[int] = None, n_wu: Optional[int] 
         dterms = int(rng.choice([8, 16]))
         inj = [(int(rng.integers(0, n_sky)), int(rng.integers(0, n_fd)), int(rng.integers(band // 4, 3 * band // 4)),
                 float(rng.uniform(10.0, 20.0)))]
-        w = make_workload(f"{BATCH_NAMES[idx]}-{u}", seed=seed * 1000 + u, n_det=2, slots_per_det=(n_sft + 1) // 2,
-                          keep_frac=1.0, jitter=60.0, t_sft=1800.0, f0=f0, n_f=band, n_sky=n_sky, n_fd=n_fd,
-                          fdot_lo=-1.0e-9, fdot_hi=0.0, dterms=dterms, injections=inj, noise=noise)
-        wus.append(w)
-    return wus
+        kws.append(dict(name=f"{BATCH_NAMES[idx]}-{u}", seed=seed * 1000 + u, n_det=2,
+                        slots_per_det=(n_sft + 1) // 2, keep_frac=1.0, jitter=60.0, t_sft=1800.0, f0=f0, n_f=band,
+                        n_sky=n_sky, n_fd=n_fd, fdot_lo=-1.0e-9, fdot_hi=0.0, dterms=dterms, injections=inj,
+                        noise=noise))
+    if workers > 1 and total > 1:
+        from concurrent.futures import ProcessPoolExecutor
+        with ProcessPoolExecutor(max_workers=min(workers, total)) as ex:
+            return list(ex.map(_make_workload_kw, kws))
+    return [make_workload(**kw) for kw in kws]
+
+
+def _make_large_batch(*, seed=None, n_wu=None, scale=1.0, workers=1):
+    """Recipe 4 (shapes and geometry; the SFT noise is drawn on the device by
+    synth.device.draw_noise_16bit): 256 work units, 2 detectors with
+    U{1000..4000} SFTs each (all slots kept, jitter 60 s), 14400 template bins
+    from U[50, 1500] Hz, 10000 sky points of one Fibonacci grid split evenly
+    over the work units (39 or 40 each) x 32 spindowns in [-1e-9, 0],
+    Dterms 16, no injection.  `scale` < 1 shrinks SFT counts and bands."""
+    seed = 1004 if seed is None else seed
+    rng = np.random.Generator(np.random.PCG64(seed))
+    total = 256 if n_wu is None else n_wu
+    grid = sky_grid(10000)
+    splits = np.array_split(np.arange(10000), 256)
+    kws = []
+    for u in range(total):
+        per_det = max(2, int(round(rng.integers(1000, 4001) * scale)))
+        band = max(64, int(round(14400 * scale)))
+        f0 = round(float(rng.uniform(50.0, 1500.0)) * 1800.0) / 1800.0
+        kws.append(dict(name=f"{BATCH_NAMES[4]}-{u}", seed=seed * 1000 + u, n_det=2, slots_per_det=per_det,
+                        keep_frac=1.0, jitter=60.0, t_sft=1800.0, f0=f0, n_f=band, n_sky=len(splits[u]), n_fd=32,
+                        fdot_lo=-1.0e-9, fdot_hi=0.0, dterms=16, injections=(), noise="device",
+                        sky_override=grid[splits[u]]))
+    if workers > 1 and total > 1:
+        from concurrent.futures import ProcessPoolExecutor
+        with ProcessPoolExecutor(max_workers=min(workers, total)) as ex:
+            return list(ex.map(_make_workload_kw, kws))
+    return [make_workload(**kw) for kw in kws]
