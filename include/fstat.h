@@ -161,7 +161,11 @@ int fstat_bins(fstat_plan* p, const fstat_wu* wu, int64_t n, const int32_t* i_sk
 /* Measure the candidate tile shapes on this work unit (timed on `stream`,
  * outputs overwritten) and keep the fastest for work units of its class
  * (storage, Dterms, kernel).  `cache_path` (may be NULL) names a text file
- * that stores results across processes; it is read first and updated. */
+ * that stores results across processes; it is read first and updated.  One
+ * line per class: "<class> <nf_reg> <chunk> <sblock> <threads>" (spindowns
+ * or frequencies per thread, waves per SIMD (interp) or SFTs per LDS chunk
+ * (direct), SFTs per launch with 0 = all, work-group size of the interp
+ * kernel); lines naming a tile the library does not implement are ignored. */
 int fstat_autotune(fstat_plan* p, const fstat_wu* wu, const fstat_out* out, void* stream,
                    const char* cache_path);
 

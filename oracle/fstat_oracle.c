@@ -4,8 +4,9 @@
  * Only the tests, the smoke check and the benchmark's CPU-baseline leg use
  * this file.  It shares no code with the GPU library: it is written from the
  * mathematics of the SFT-domain F-statistic, in plain loops, in IEEE binary64
- * with round-to-nearest and no fused multiply-add (build with
- * -ffp-contract=off and without -ffast-math).
+ * with round-to-nearest; the one fused multiply-add is the explicit fma() in
+ * Dphi, nothing else may be contracted (build with -ffp-contract=off and
+ * without -ffast-math).
  *
  * What it computes follows the F-statistic loop nest of the paper (Listing 1,
  * Section 2): an independent loop over the frequencies of a band, a sum over
@@ -15,7 +16,9 @@
  *
  *   tau_a   = (t_a + T/2 - t_ref) + r_a . n          (arrival-time offset)
  *   Tdot_a  = 1 + v_a . n                            (Doppler factor)
- *   Dphi_a  = ((f + fdot * tau_a) * Tdot_a) * T      (instantaneous frequency in bins)
+ *   P_a     = Tdot_a * T,  q_a = (fdot * tau_a) * P_a
+ *   Dphi_a  = fma(f, P_a, q_a)                       (instantaneous frequency in bins,
+ *                                                     (f + fdot tau_a) Tdot_a T)
  *   k*_a    = floor(Dphi_a),  kappa_a = Dphi_a - k*_a
  *   phi_a   = tau_a * (f + (fdot/2) * tau_a)         (phase at the SFT midpoint, cycles)
  *   z_a     = exp(-2 pi i frac(phi_a)) *
@@ -103,7 +106,9 @@ static void bin_and_phase(const oracle_wu* w, int s, int ifd, int jf, int al, in
   double fd = w->fdot0 + (double)ifd * w->dfdot;
   double tau, tdot;
   sft_geometry(w, s, al, &tau, &tdot);
-  double dphi = ((f + fd * tau) * tdot) * w->t_sft;
+  double P = tdot * w->t_sft;
+  double q = (fd * tau) * P;
+  double dphi = fma(f, P, q);     /* f P + q, rounded once */
   double k = floor(dphi);
   *kstar = (int64_t)k;
   *kappa = dphi - k;

@@ -140,6 +140,8 @@ int validate_wu(fstat_plan* p, const fstat_wu* w, const fstat_out* o, int idx) {
   if (w->k_first < 0 || w->k_first + w->n_bins > 0x7fffffffLL)
     return set_err(p, FSTAT_E_BAND, "%sband outside [0, 2^31)", tag);
   if (w->n_sky * w->n_fd * w->n_f > ((int64_t)1 << 40)) return set_err(p, FSTAT_E_SIZE, "%stoo many templates", tag);
+  // the interp kernel addresses one SFT's coefficients with 32-bit offsets
+  if (w->n_bins > ((int64_t)1 << 25)) return set_err(p, FSTAT_E_SIZE, "%sband wider than 2^25 bins", tag);
   return FSTAT_OK;
 }
 
@@ -180,16 +182,24 @@ WuDev make_dev(const fstat_plan* p, const fstat_wu* w, const fstat_out* o) {
   return v;
 }
 
+// Coefficient scratch of one work unit: [n_sft][kCoefPairs][n_bins] float4,
+// plus kSegMax float4 of padding that the slice staging of the last SFT may
+// read (into columns it never uses).
+size_t coef_bytes(const fstat_wu* w) {
+  return ((size_t)w->n_sft * w->n_bins * fstat::kCoefPairs + fstat::kSegMax) * sizeof(float4);
+}
+
 int resolved_kernel(const fstat_plan* p) {
   return p->d.kernel == FSTAT_KERNEL_DIRECT ? fstat::KERNEL_DIRECT : fstat::KERNEL_INTERP;
 }
 
 double host_sinc(double x) { return x == 0.0 ? 1.0 : sin(M_PI * x) / (M_PI * x); }
 
-// Monomial coefficients in u = 2 kappa - 1 of the degree-(kCoef-1) Chebyshev
+// Monomial coefficients in kappa of the degree-(kCoef-1) Chebyshev
 // projection of sinc(kappa + m) on kappa in [0, 1], for m = -D .. D-1:
-// Chebyshev coefficients from 64 Chebyshev nodes (discrete cosine sums),
-// then the three-term recurrence T_{j+1} = 2u T_j - T_{j-1} to monomials.
+// Chebyshev coefficients from 64 Chebyshev nodes (discrete cosine sums), the
+// three-term recurrence T_{j+1} = 2u T_j - T_{j-1} to monomials of
+// u = 2 kappa - 1, then the binomial expansion of (2 kappa - 1)^q.
 std::vector<double> sinc_poly_table(int D) {
   const int N = 64, P = fstat::kCoef;
   std::vector<double> tab((size_t)2 * D * P, 0.0);
@@ -209,9 +219,17 @@ std::vector<double> sinc_poly_table(int D) {
       }
       a[j] = (j == 0 ? 1.0 : 2.0) * acc / N;
     }
-    double* row = &tab[(size_t)(m + D) * P];
+    std::vector<double> cu(P, 0.0);
     for (int j = 0; j < P; ++j)
-      for (int q = 0; q < P; ++q) row[q] += a[j] * Tm[j][q];
+      for (int q = 0; q < P; ++q) cu[q] += a[j] * Tm[j][q];
+    double* row = &tab[(size_t)(m + D) * P];
+    for (int q = 0; q < P; ++q) {     // cu[q] (2 kappa - 1)^q = cu[q] sum_r C(q,r) 2^r kappa^r (-1)^(q-r)
+      double binom = 1.0;
+      for (int r = 0; r <= q; ++r) {
+        row[r] += cu[q] * binom * ldexp(1.0, r) * (((q - r) & 1) ? -1.0 : 1.0);
+        binom = binom * (q - r) / (r + 1);
+      }
+    }
   }
   return tab;
 }
@@ -238,23 +256,24 @@ std::string class_key(const fstat_plan* p, const fstat_wu* w) {
   return b;
 }
 
-// LDS slice width (bins) of the interp kernel: 256 frequency templates span
-// 255 df T Tdot bins, the spindowns of a block shift k* by up to
-// |dfdot| (NFD-1) max|tau| T Tdot more; plus slack, rounded to 4.
+// LDS slice width (bins) of the interp kernel: the NT frequency templates of
+// a work-group span (NT-1) df T Tdot bins, the spindowns of a block shift k*
+// by up to |dfdot| (NFD-1) max|tau| T Tdot more; plus slack, rounded to 4.
 // Lanes whose window falls outside the slice read their coefficients from
 // global memory instead, so a narrower slice costs speed, not correctness;
-// the slice is capped so that one work-group uses at most 64 KB of LDS.
-int interp_seg_tau(const fstat_wu* w, int nfd, int chunk, double max_abs_tau) {
+// the slice is capped at 5 NT / 4 bins (40 KB of LDS for 256 threads).
+int interp_seg_tau(const fstat_wu* w, int nfd, int threads, double max_abs_tau) {
   const double tdot = 1.001;
-  const double spread = (255.0 * w->df + fabs(w->dfdot) * (nfd - 1) * max_abs_tau) * w->t_sft * tdot;
-  const double width = 256.0 + 6.0 + ceil(spread - 255.0 > 0 ? spread - 255.0 : 0.0);
-  const int cap = fstat::interp_max_seg(chunk);
+  const double nt = threads;
+  const double spread = ((nt - 1.0) * w->df + fabs(w->dfdot) * (nfd - 1) * max_abs_tau) * w->t_sft * tdot;
+  const double width = nt + 6.0 + ceil(spread - (nt - 1.0) > 0 ? spread - (nt - 1.0) : 0.0);
+  const int cap = fstat::interp_max_seg(threads);
   int W = width > cap ? cap : (int)width;
   return W & ~3;
 }
 
-int interp_seg(const fstat_plan* p, const fstat_wu* w, int nfd, int chunk) {
-  return interp_seg_tau(w, nfd, chunk, p->max_abs_tau);
+int interp_seg(const fstat_plan* p, const fstat_wu* w, int nfd, int threads) {
+  return interp_seg_tau(w, nfd, threads, p->max_abs_tau);
 }
 
 Tile default_tile(const fstat_plan* p, const fstat_wu* w) {
@@ -264,15 +283,15 @@ Tile default_tile(const fstat_plan* p, const fstat_wu* w) {
     // for 3 waves per SIMD and one launch over all SFTs is fastest; with fewer
     // spindowns per thread the staged slices are reused less and splitting the
     // SFT loop into launches keeps them in L2
-    return Tile{nfd, 3, 0, nfd >= 4 ? 0 : 256};
+    return Tile{nfd, 3, 0, nfd >= 4 ? 0 : 256, fstat::kThreads};
   }
-  return Tile{4, 4, 0, 0};   // fastest direct tile on the work-unit-shaped case
+  return Tile{4, 4, 0, 0, 0};   // fastest direct tile on the work-unit-shaped case
 }
 
 Tile pick_tile(const fstat_plan* p, const fstat_wu* w) {
   auto it = p->tiles.find(class_key(p, w));
   Tile t = it != p->tiles.end() ? it->second : default_tile(p, w);
-  if (resolved_kernel(p) == fstat::KERNEL_INTERP) t.seg = interp_seg(p, w, t.nf_reg, 1);
+  if (resolved_kernel(p) == fstat::KERNEL_INTERP) t.seg = interp_seg(p, w, t.nf_reg, t.threads);
   return t;
 }
 
@@ -282,8 +301,7 @@ int ensure_scratch(fstat_plan* p, const fstat_wu* w) {
   rc = dev_alloc(p, &p->abcd, &p->abcd_bytes, (size_t)w->n_sky * sizeof(double4), "A,B,C scratch");
   if (rc) return rc;
   if (resolved_kernel(p) == fstat::KERNEL_INTERP) {
-    rc = dev_alloc(p, &p->coef, &p->coef_bytes, (size_t)w->n_sft * w->n_bins * fstat::kCoefPairs * sizeof(float4),
-                   "coefficient scratch");
+    rc = dev_alloc(p, &p->coef, &p->coef_bytes, coef_bytes(w), "coefficient scratch");
     if (rc) return rc;
     rc = dev_alloc(p, &p->acc, &p->acc_bytes, (size_t)w->n_sky * w->n_fd * w->n_f * sizeof(float4),
                    "accumulator scratch");
@@ -338,7 +356,7 @@ WuScratch wu_scratch(const fstat_wu* w) {
   WuScratch r;
   r.geo = align256((size_t)w->n_sky * w->n_sft * sizeof(double2));
   r.abcd = align256((size_t)w->n_sky * sizeof(double4));
-  r.coef = align256((size_t)w->n_sft * w->n_bins * fstat::kCoefPairs * sizeof(float4));
+  r.coef = align256(coef_bytes(w));
   r.total = r.geo + r.abcd + r.coef;
   return r;
 }
@@ -469,7 +487,7 @@ int batch_interp(fstat_plan* p, const fstat_wu* wus, int n, const fstat_out* out
       v.acc = nullptr;
       e.w = v;
       e.nfd = wus[k].n_fd >= 8 ? 8 : 4;
-      e.seg = interp_seg_tau(&wus[k], e.nfd, 1, status_tau(p->bstat_h[k]));
+      e.seg = interp_seg_tau(&wus[k], e.nfd, fstat::kThreads, status_tau(p->bstat_h[k]));
       e.n_tiles = fstat::interp_tiles(v, e.nfd);
       e.tile_begin = tiles;
       e.coef_begin = blocks;
@@ -658,6 +676,17 @@ int fstat_bins(fstat_plan* p, const fstat_wu* wu, int64_t n, const int32_t* i_sk
                       "bins kernel");
 }
 
+// A tile the launchers implement (cache entries are checked against it).
+static bool valid_tile(const fstat_plan* p, const Tile& t) {
+  if (t.sblock < 0) return false;
+  if (resolved_kernel(p) == fstat::KERNEL_INTERP) {
+    const bool nf_ok = t.nf_reg == 8 || t.nf_reg == 4 || t.nf_reg == 2 || t.nf_reg == 1;
+    return nf_ok && (t.chunk == 2 || t.chunk == 3) && (t.threads == 256 || (t.threads == 64 && t.nf_reg >= 4));
+  }
+  return (t.nf_reg == 1 && (t.chunk == 16 || t.chunk == 8)) || (t.nf_reg == 2 && (t.chunk == 8 || t.chunk == 4)) ||
+         (t.nf_reg == 4 && t.chunk == 4);
+}
+
 int fstat_autotune(fstat_plan* p, const fstat_wu* wu, const fstat_out* out, void* stream, const char* cache_path) {
   if (!p) return FSTAT_E_ARG;
   p->err.clear();
@@ -667,9 +696,11 @@ int fstat_autotune(fstat_plan* p, const fstat_wu* wu, const fstat_out* out, void
   if (cache_path) {
     if (FILE* f = fopen(cache_path, "r")) {
       char k[64];
-      int nf, ch, sb;
-      while (fscanf(f, "%63s %d %d %d", k, &nf, &ch, &sb) == 4)
-        if (key == k) p->tiles[key] = Tile{nf, ch, 0, sb};
+      int nf, ch, sb, nt;
+      while (fscanf(f, "%63s %d %d %d %d", k, &nf, &ch, &sb, &nt) == 5) {
+        const Tile t{nf, ch, 0, sb, nt};
+        if (key == k && valid_tile(p, t)) p->tiles[key] = t;
+      }
       fclose(f);
       if (p->tiles.count(key)) return FSTAT_OK;
     }
@@ -683,17 +714,19 @@ int fstat_autotune(fstat_plan* p, const fstat_wu* wu, const fstat_out* out, void
   if (rc) return rc;
   std::vector<Tile> cands;
   if (resolved_kernel(p) == fstat::KERNEL_INTERP) {
-    for (int nfd : {8, 4, 2, 1})
-      for (int minw : {2, 3})
-        for (int sb : {64, 128, 256, 0})
-          if ((nfd <= 2 * wu->n_fd || nfd == 1) && (nfd >= 4 || minw == 3)) cands.push_back(Tile{nfd, minw, 0, sb});
+    for (int nt : {256, 64})
+      for (int nfd : {8, 4, 2, 1})
+        for (int minw : {2, 3})
+          for (int sb : {64, 256, 0})
+            if ((nfd <= 2 * wu->n_fd || nfd == 1) && (nfd == 8 || minw == 3) && (nt == 256 || nfd >= 4))
+              cands.push_back(Tile{nfd, minw, 0, sb, nt});
   } else {
-    cands = {Tile{1, 16, 0, 0}, Tile{1, 8, 0, 0}, Tile{2, 8, 0, 0}, Tile{2, 4, 0, 0}, Tile{4, 4, 0, 0}};
+    cands = {Tile{1, 16, 0, 0, 0}, Tile{1, 8, 0, 0, 0}, Tile{2, 8, 0, 0, 0}, Tile{2, 4, 0, 0, 0}, Tile{4, 4, 0, 0, 0}};
   }
   float best = 1e30f;
   Tile best_t = default_tile(p, wu);
   for (Tile t : cands) {
-    if (resolved_kernel(p) == fstat::KERNEL_INTERP) t.seg = interp_seg(p, wu, t.nf_reg, 1);
+    if (resolved_kernel(p) == fstat::KERNEL_INTERP) t.seg = interp_seg(p, wu, t.nf_reg, t.threads);
     float ms_sum = 0.f;
     for (int rep = 0; rep < 2; ++rep) {
       rc = run_demod(p, v, t, st);
@@ -705,8 +738,8 @@ int fstat_autotune(fstat_plan* p, const fstat_wu* wu, const fstat_out* out, void
       if (rep == 1) ms_sum += ms;
     }
     if (getenv("FSTAT_TUNE_VERBOSE"))
-      fprintf(stderr, "[fstat autotune] %s tile nf_reg=%d chunk=%d seg=%d sblock=%d: %.3f ms\n", key.c_str(), t.nf_reg,
-              t.chunk, t.seg, t.sblock, ms_sum);
+      fprintf(stderr, "[fstat autotune] %s tile nf_reg=%d chunk=%d seg=%d sblock=%d threads=%d: %.3f ms\n", key.c_str(),
+              t.nf_reg, t.chunk, t.seg, t.sblock, t.threads, ms_sum);
     if (ms_sum < best) {
       best = ms_sum;
       best_t = t;
@@ -715,7 +748,7 @@ int fstat_autotune(fstat_plan* p, const fstat_wu* wu, const fstat_out* out, void
   p->tiles[key] = best_t;
   if (cache_path) {
     if (FILE* f = fopen(cache_path, "a")) {
-      fprintf(f, "%s %d %d %d\n", key.c_str(), best_t.nf_reg, best_t.chunk, best_t.sblock);
+      fprintf(f, "%s %d %d %d %d\n", key.c_str(), best_t.nf_reg, best_t.chunk, best_t.sblock, best_t.threads);
       fclose(f);
     }
   }

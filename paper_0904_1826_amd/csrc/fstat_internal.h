@@ -15,7 +15,7 @@ struct WuDev {
   const double* sky;       // [n_sky][3]
   const float* a;          // [n_sky][n_sft]
   const float* b;          // [n_sky][n_sft]
-  double2* geo;            // scratch [n_sky][n_sft]: (tau, Tdot)
+  double2* geo;            // scratch [n_sky][n_sft]: (tau, Tdot T)
   double4* abcd;           // scratch [n_sky]: (A, B, C, AB - C^2)
   float* twoF;             // [n_sky][n_fd][n_f]
   float2* fa;              // optional, same shape
@@ -36,22 +36,25 @@ struct Tile {
   int32_t chunk;    // SFTs staged in LDS per pass
   int32_t seg;      // interp: LDS segment width in bins (0: derived)
   int32_t sblock;   // interp: SFTs per launch (the SFT loop is split into launches of this many SFTs)
+  int32_t threads;  // interp: work-group size, 64 or 256
 };
 
 enum Kernel : int32_t { KERNEL_DIRECT = 1, KERNEL_INTERP = 2 };
 
 // Interp kernel: each window weight sinc(kappa + m), kappa in [0, 1), is
-// replaced by a degree-7 polynomial in u = 2 kappa - 1 (Chebyshev projection,
-// max error 4.3e-7 over the interval), so the whole window sum of bin k is a
-// degree-7 polynomial in u with kCoef complex coefficients per bin.
+// replaced by a degree-7 polynomial in kappa (Chebyshev projection, max error
+// 4.3e-7 over the interval, written in monomials of kappa), so the whole
+// window sum of bin k is a degree-7 polynomial in kappa with kCoef complex
+// coefficients per bin.
 constexpr int kCoef = 8;
 constexpr int kCoefPairs = kCoef / 2;
-// Widest coefficient slice (bins) one work-group stages per SFT: 256
-// frequency templates plus up to 58 bins of Doppler and spindown spread and
-// the slack, in runs of 64; two buffers of it take 40 KB of LDS, so three
-// work-groups fit a CU.
+// Widest coefficient slice (bins) a work-group of NT threads stages per SFT:
+// NT frequency templates plus NT/4 - 6 bins of Doppler and spindown spread
+// (58 for 256 threads, 10 for 64) and the slack.  Two buffers of it take
+// 40 KB of LDS for 256 threads, so three work-groups fit a CU.
 constexpr int kMaxRuns = 5;
-constexpr int kSegMax = 64 * kMaxRuns;
+__host__ __device__ constexpr int seg_cap(int nt) { return nt + nt / 4; }
+constexpr int kSegMax = seg_cap(256);
 
 // One work unit of a batched launch: its device view, its slice width, its
 // spindowns per thread (4 or 8) and the index of its first tile in the
@@ -95,6 +98,6 @@ int interp_batch_grid();
 hipError_t launch_bins(const WuDev& w, int64_t n, const int32_t* i_sky, const int32_t* i_fd, const int32_t* i_f,
                        const int32_t* i_sft, int64_t* kstar, double* kappa, double* phi_frac, hipStream_t s);
 size_t demod_lds_bytes(const WuDev& w, const Tile& t, int kernel);
-int interp_max_seg(int chunk);
+int interp_max_seg(int threads);
 
 }  // namespace fstat

@@ -2,7 +2,7 @@
 //
 // Steps, in the order of the per-SFT body of the F-statistic loop nest
 // (Listing 1, Section 2) read as the Dirichlet demodulation:
-//   geometry   per (sky, SFT): tau, Tdot; per sky: A, B, C; band check
+//   geometry   per (sky, SFT): tau, Tdot T; per sky: A, B, C; band check
 //   demod      per (template, SFT): FP64 bin index k*, offset kappa, phase;
 //              2D-bin window gathered from an LDS-staged slice of the SFT;
 //              FP32 Dirichlet sum; phase rotation; a/b weighting; the sum over
@@ -11,6 +11,8 @@
 // rounded operation by operation in the order written, which makes k* and
 // kappa identical bit for bit to any other IEEE binary64 evaluation of the
 // same formula.  FP32 fused multiply-adds are written explicitly.
+#include <type_traits>
+
 #include "fstat_internal.h"
 
 namespace fstat {
@@ -30,10 +32,12 @@ __device__ __forceinline__ void sft_geometry(const WuDev& w, int64_t s, int64_t 
 __device__ __forceinline__ double template_f(const WuDev& w, int64_t j) { return w.f0 + (double)j * w.df; }
 __device__ __forceinline__ double template_fd(const WuDev& w, int64_t i) { return w.fdot0 + (double)i * w.dfdot; }
 
-// Instantaneous frequency in SFT bins, given g = fdot * tau.
-__device__ __forceinline__ double bin_position(double f, double g, double tdot, double t_sft) {
-  return ((f + g) * tdot) * t_sft;
-}
+// Instantaneous frequency in SFT bins, (f + fdot tau) Tdot T, evaluated as
+// f P + q with one rounding (fused multiply-add), where P = Tdot T and
+// q = (fdot tau) P are rounded products formed once per SFT (and spindown).
+__device__ __forceinline__ double bin_scale(double tdot, double t_sft) { return tdot * t_sft; }
+__device__ __forceinline__ double bin_offset(double fd, double tau, double p) { return (fd * tau) * p; }
+__device__ __forceinline__ double bin_position(double f, double q, double p) { return __builtin_fma(f, p, q); }
 
 __device__ __forceinline__ double fract64(double x) { return __builtin_amdgcn_fract(x); }
 
@@ -109,14 +113,15 @@ __global__ __launch_bounds__(256) void geometry_kernel(WuDev w, GeoStatus* statu
       double tau, tdot;
       sft_geometry(w, s, al, tau, tdot);
       tmax = fmax(tmax, fabs(tau));
-      w.geo[s * w.n_sft + al] = make_double2(tau, tdot);
+      const double P = bin_scale(tdot, T);
+      w.geo[s * w.n_sft + al] = make_double2(tau, P);
       const double a = w.a[s * w.n_sft + al], b = w.b[s * w.n_sft + al];
       A += a * a;
       B += b * b;
       C += a * b;
-      const double g_a = fd_a * tau, g_b = fd_b * tau;
-      const double d1 = bin_position(f_lo, g_a, tdot, T), d2 = bin_position(f_lo, g_b, tdot, T);
-      const double d3 = bin_position(f_hi, g_a, tdot, T), d4 = bin_position(f_hi, g_b, tdot, T);
+      const double q_a = bin_offset(fd_a, tau, P), q_b = bin_offset(fd_b, tau, P);
+      const double d1 = bin_position(f_lo, q_a, P), d2 = bin_position(f_lo, q_b, P);
+      const double d3 = bin_position(f_hi, q_a, P), d4 = bin_position(f_hi, q_b, P);
       const double kmin = floor(d1 < d2 ? (d1 < d3 ? (d1 < d4 ? d1 : d4) : (d3 < d4 ? d3 : d4))
                                         : (d2 < d3 ? (d2 < d4 ? d2 : d4) : (d3 < d4 ? d3 : d4)));
       const double kmax = floor(d1 > d2 ? (d1 > d3 ? (d1 > d4 ? d1 : d4) : (d3 > d4 ? d3 : d4))
@@ -300,7 +305,7 @@ __global__ __launch_bounds__(kThreads) void demod_direct_kernel(WuDev w) {
     __syncthreads();                                // previous chunk consumed
     if (tid < nc) {
       const double2 g = geo[al0 + tid];
-      const double d = bin_position(f_first, fd * g.x, g.y, T);
+      const double d = bin_position(f_first, bin_offset(fd, g.x, g.y), g.y);
       int64_t lo = (int64_t)floor(d) - (D - 1) - w.k_first - 1;   // one bin of slack
       lo = lo < 0 ? 0 : (lo > max_lo ? max_lo : lo);
       lo_col[tid] = lo;
@@ -319,12 +324,12 @@ __global__ __launch_bounds__(kThreads) void demod_direct_kernel(WuDev w) {
       const int64_t al = al0 + c;
       const double2 g = geo[al];
       const float a = arow[al], b = brow[al];
-      const double gf = fd * g.x;                   // fdot * tau
+      const double gf = bin_offset(fd, g.x, g.y);   // (fdot tau) Tdot T
       const double gh = hfd * g.x;                  // (fdot / 2) * tau
       const int base = (int)(w.k_first + lo_col[c]);   // absolute bin of slice column 0
 #pragma unroll
       for (int r = 0; r < NF; ++r) {
-        const double dphi = bin_position(f[r], gf, g.y, T);
+        const double dphi = bin_position(f[r], gf, g.y);
         const int kst = (int)dphi;                  // floor: dphi > 0
         const double kap64 = fract64(dphi);         // dphi - k*, exact
         const float kap = (float)kap64;
@@ -371,7 +376,7 @@ __global__ __launch_bounds__(kThreads) void demod_direct_kernel(WuDev w) {
 // The window sum of bin k as a function of kappa,
 //   G_k(kappa) = sum_{m=-D}^{D-1} (-1)^(k-m) x[k-m] sinc(kappa + m),
 // is an entire function of kappa; on [0, 1) it is replaced by the polynomial
-// sum_p c[k][p] u^p, u = 2 kappa - 1, whose coefficients
+// sum_p c[k][p] kappa^p, whose coefficients
 //   c[k][p] = sum_m (-1)^(k-m) x[k-m] t[m][p]
 // follow from the per-term polynomials t[m][.] of sinc(kappa + m).  This pass
 // computes c for every bin of every SFT (in FP64, stored as FP32 pairs
@@ -462,7 +467,7 @@ __device__ __forceinline__ CoefSet load_coef_global(const WuDev& w, int64_t al, 
 // fdot * tau and the phase factor exp(-2 pi i frac(tau (fdot/2) tau)).
 template <int NFD, int S>
 struct GroupMeta {
-  double2 geo[S];     // (tau, Tdot) of the sky point
+  double2 geo[S];     // (tau, Tdot T) of the sky point
   float2 tsplit[S];   // tau as hi + lo FP32 (split phase mode)
   float a[S], b[S];
   int lo[S];
@@ -474,34 +479,34 @@ struct GroupMeta {
 // Fills the meta of SFTs [al0, al0 + n) with all threads of the work-group.
 // k* is monotone in f and in fdot, so the tile's corners bound the bins of
 // every (template, SFT) pair of the tile: [kmin, kmax] in slice columns.
-template <int NFD, int S>
+template <int NFD, int S, int NT>
 __device__ __forceinline__ void group_meta(const WuDev& w, const double2* geo, const float* arow, const float* brow,
                                            int64_t al0, int n, int64_t i0, int64_t i_last, double f_first,
                                            double f_last, int W, GroupMeta<NFD, S>& m) {
   const int tid = threadIdx.x;
-  const int t3 = tid - (kThreads - 2 * S);       // S threads before the last S copy tau, Tdot, a, b
+  const int t3 = tid - (NT - 2 * S);             // S threads before the last S copy tau, Tdot T, a, b
   if (t3 >= 0 && t3 < n) {
     m.geo[t3] = geo[al0 + t3];
     m.tsplit[t3] = split64(geo[al0 + t3].x);
     m.a[t3] = arow[al0 + t3];
     m.b[t3] = brow[al0 + t3];
   }
-  for (int e = tid; e < n * NFD; e += kThreads) {
+  for (int e = tid; e < n * NFD; e += NT) {
     const int c = e / NFD, r = e % NFD;
     const double2 g = geo[al0 + c];
     const int64_t i = (i0 + r < w.n_fd) ? i0 + r : w.n_fd - 1;
     const double fd = template_fd(w, i);
-    m.g[c][r] = fd * g.x;
+    m.g[c][r] = bin_offset(fd, g.x, g.y);
     const double h = (0.5 * fd) * g.x;                 // (fdot / 2) tau
     const float q = w.phase_mode ? frac_split_product(split64(g.x), split64(h)) : (float)fract64(g.x * h);
     m.e[c][r] = make_float2(cos_rev(q), -sin_rev(q));
   }
-  const int t2 = tid - (kThreads - S);           // the last S threads do the slice bounds
+  const int t2 = tid - (NT - S);                 // the last S threads do the slice bounds
   if (t2 >= 0 && t2 < n) {
     const double2 g = geo[al0 + t2];
-    const double ga = template_fd(w, i0) * g.x, gb = template_fd(w, i_last) * g.x;
-    const double d1 = bin_position(f_first, ga, g.y, w.t_sft), d2 = bin_position(f_first, gb, g.y, w.t_sft);
-    const double d3 = bin_position(f_last, ga, g.y, w.t_sft), d4 = bin_position(f_last, gb, g.y, w.t_sft);
+    const double ga = bin_offset(template_fd(w, i0), g.x, g.y), gb = bin_offset(template_fd(w, i_last), g.x, g.y);
+    const double d1 = bin_position(f_first, ga, g.y), d2 = bin_position(f_first, gb, g.y);
+    const double d3 = bin_position(f_last, ga, g.y), d4 = bin_position(f_last, gb, g.y);
     // column offsets of the extreme bins; the band is below 2^31 bins
     const int kmin = (int)(floor(d1 < d2 ? d1 : d2) - (double)w.k_first);
     const int kmax = (int)(floor(d3 > d4 ? d3 : d4) - (double)w.k_first);
@@ -515,48 +520,69 @@ __device__ __forceinline__ void group_meta(const WuDev& w, const double2* geo, c
 }
 
 // Staging of one SFT's coefficient slice through registers: the slice is
-// kCoefPairs rows of kSegMax float4 (columns W .. kSegMax-1 are padding),
-// i.e. kCoefPairs * kMaxRuns runs of 64, and wave w moves runs w, w + 4, ...,
-// kMaxRuns of them, one float4 per lane each.  The loads are issued before
-// the current SFT is evaluated and written to LDS after it, so their latency
-// hides behind the arithmetic; they are unconditional (columns beyond the
-// band are clamped to its last column, never read by a valid window) so that
-// the compiler waits for them only where they are stored.
+// kCoefPairs rows of seg_cap(NT) = 5 NT / 4 float4 starting at column lo
+// (columns W .. cap-1 are padding), 5 NT float4 in all, and thread t moves
+// elements t, t + NT, ..., five of them (row = index / cap, column =
+// index % cap).  The byte offset of each element from the slice start is the
+// same for every SFT, so the loads take a scalar base and a fixed per-thread
+// offset.  Reads past the band's last column land in the next row, or, for
+// the last SFT, in the kSegMax float4 of padding the coefficient buffer
+// carries, and fill only padding columns.  The loads are issued before the
+// current SFT is evaluated and written to LDS after it, so their latency
+// hides behind the arithmetic.
 typedef float v4f __attribute__((ext_vector_type(4)));   // native vector: stays in registers
+
+// LDS (address space 3) pointers as 32-bit byte addresses.
+typedef const __attribute__((address_space(3))) v4f* LdsPtr;
+__device__ __forceinline__ uint32_t lds_address(const float4* p) {
+  return (uint32_t)(uintptr_t)(LdsPtr)(const v4f*)p;
+}
+__device__ __forceinline__ LdsPtr lds_pointer(uint32_t a) { return (LdsPtr)(uintptr_t)a; }
+__device__ __forceinline__ float4 lds_load(LdsPtr p, int i) {
+  const v4f v = p[i];
+  return make_float4(v.x, v.y, v.z, v.w);
+}
 
 struct SlicePrefetch {
   v4f v[kMaxRuns];
 };
 
-__device__ __forceinline__ SlicePrefetch slice_load(const WuDev& w, int64_t al, int lo) {
-  SlicePrefetch p;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int last = (int)w.n_bins - 1;
-  const v4f* base = reinterpret_cast<const v4f*>(w.coef + al * kCoefPairs * w.n_bins);
+template <int NT>
+struct SliceOffsets {
+  uint32_t o[kMaxRuns];   // bytes from the slice start
+};
+
+template <int NT>
+__device__ __forceinline__ SliceOffsets<NT> slice_offsets(const WuDev& w) {
+  constexpr int cap = seg_cap(NT);
+  SliceOffsets<NT> so;
 #pragma unroll
   for (int i = 0; i < kMaxRuns; ++i) {
-    const int wr = wave + (kThreads / 64) * i;
-    const int q = wr / kMaxRuns, e = (wr % kMaxRuns) * 64 + lane;
-    int col = lo + e;
-    col = col > last ? last : col;
-    p.v[i] = base[q * w.n_bins + col];
+    const int e = (int)threadIdx.x + NT * i;
+    so.o[i] = (uint32_t)(((e / cap) * w.n_bins + e % cap) * (int64_t)sizeof(float4));
   }
+  return so;
+}
+
+template <int NT>
+__device__ __forceinline__ SlicePrefetch slice_load(const WuDev& w, const SliceOffsets<NT>& so, int64_t al, int lo) {
+  SlicePrefetch p;
+  const int lo_u = __builtin_amdgcn_readfirstlane(lo);   // uniform: keeps the base in scalar registers
+  const char* base = reinterpret_cast<const char*>(w.coef + (al * kCoefPairs * w.n_bins + lo_u));
+#pragma unroll
+  for (int i = 0; i < kMaxRuns; ++i) p.v[i] = *reinterpret_cast<const v4f*>(base + so.o[i]);
   return p;
 }
 
+template <int NT>
 __device__ __forceinline__ void slice_store(const SlicePrefetch& p, float4* buf_) {
   v4f* buf = reinterpret_cast<v4f*>(buf_);
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
 #pragma unroll
-  for (int i = 0; i < kMaxRuns; ++i) {
-    const int wr = wave + (kThreads / 64) * i;
-    const int q = wr / kMaxRuns, e = (wr % kMaxRuns) * 64 + lane;
-    buf[q * kSegMax + e] = p.v[i];
-  }
+  for (int i = 0; i < kMaxRuns; ++i) buf[(int)threadIdx.x + NT * i] = p.v[i];
 }
 
-// Degree-7 complex polynomial in u (Horner) times exp(-2 pi i phi), added
-// to Fa, Fb with the weights a, b.
+// Degree-7 complex polynomial in u = kappa (Horner) times exp(-2 pi i phi),
+// added to Fa, Fb with the weights a, b.
 __device__ __forceinline__ void interp_accumulate(float4 c01, float4 c23, float4 c45, float4 c67, float u, float cf,
                                                   float sf, float2 eq, float a, float b, float& far, float& fai,
                                                   float& fbr, float& fbi) {
@@ -579,40 +605,39 @@ __device__ __forceinline__ void interp_accumulate(float4 c01, float4 c23, float4
 }
 
 // Demodulation over SFTs [al_begin, al_end) for tiles of (sky s, NFD
-// spindowns, kThreads frequencies), sky point fastest, one tile per
-// work-group.  The host splits the SFT loop into launches of a few dozen
-// SFTs: the work-groups of one launch then share the coefficient slices of a
-// few dozen SFTs (the same frequency tile, offset by each sky point's Doppler
-// shift), which stay in L2; Fa, Fb carry over between launches in `acc`.
-// Within a launch the slices (one SFT per chunk) are double-buffered in LDS:
-// the direct global-to-LDS loads of chunk k+1 are in flight while chunk k is
-// evaluated, with one barrier per chunk.  The per-SFT values shared by the
+// spindowns, NT frequencies), sky point fastest, one tile per work-group.
+// The host may split the SFT loop into launches of a few dozen SFTs: the
+// work-groups of one launch then share the coefficient slices of a few dozen
+// SFTs (the same frequency tile, offset by each sky point's Doppler shift),
+// which stay in L2; Fa, Fb carry over between launches in `acc`.  Within a
+// launch the slices (one SFT each) are double-buffered in LDS: the loads of
+// SFT k+1 are in flight in registers while SFT k is evaluated, with one
+// barrier per SFT.  The per-SFT values shared by the
 // work-group are prepared S SFTs at a time by all threads, one group ahead.
 // Each thread owns one frequency at NFD spindowns: per SFT it forms
 // exp(-2 pi i frac(tau f)) once and, per spindown, the canonical FP64 Dphi,
-// k*, kappa, the degree-7 polynomial in u = 2 kappa - 1, the rotation and the
+// k*, kappa, the degree-7 polynomial in kappa, the rotation and the
 // a/b accumulation in registers.  An SFT whose windows are not all inside
 // the slice (only possible for slices narrower than the tile's spread) takes
 // the same arithmetic with coefficients read from global memory.
-template <int NFD, int S>
+template <int NFD, int S, int G, int NT>
 __device__ __forceinline__ void interp_tile(const WuDev& w, int W, int64_t tile, int64_t al_begin, int64_t al_end,
                                             float4* cbuf0, float4* cbuf1, GroupMeta<NFD, S>* meta) {
   const int tid = threadIdx.x;
   const int64_t n_fdb = (w.n_fd + NFD - 1) / NFD;
-  constexpr int Wp = kSegMax;                      // LDS row stride
+  constexpr int Wp = seg_cap(NT);                  // LDS row stride
   int64_t t = tile;
   const int64_t s = t % w.n_sky;
   t /= w.n_sky;
   const int64_t ib = t % n_fdb;
   const int64_t ft = t / n_fdb;
-  const int64_t j0 = ft * kThreads;
+  const int64_t j0 = ft * NT;
   int64_t j = j0 + tid;
   const bool jvalid = j < w.n_f;
   if (!jvalid) j = w.n_f - 1;
-  const int64_t j_last = (j0 + kThreads - 1 < w.n_f - 1) ? j0 + kThreads - 1 : w.n_f - 1;
+  const int64_t j_last = (j0 + NT - 1 < w.n_f - 1) ? j0 + NT - 1 : w.n_f - 1;
   const int64_t i0 = ib * NFD;
   const int64_t i_last = (i0 + NFD - 1 < w.n_fd - 1) ? i0 + NFD - 1 : w.n_fd - 1;
-  const double T = w.t_sft;
   const double f = template_f(w, j);
   const float2 fsplit = split64(f);
   const bool split_phase = w.phase_mode != 0;
@@ -635,59 +660,80 @@ __device__ __forceinline__ void interp_tile(const WuDev& w, int W, int64_t tile,
     }
   }
 
-  group_meta<NFD, S>(w, geo, arow, brow, al_begin, n < S ? n : S, i0, i_last, f_first, f_last, W, meta[0]);
+  const SliceOffsets<NT> so = slice_offsets<NT>(w);
+  // waves whose frequencies all lie beyond the band's last template only
+  // help stage slices
+  const bool wave_live = __builtin_amdgcn_readfirstlane((int)(j0 + (tid & ~63) < w.n_f));
+  group_meta<NFD, S, NT>(w, geo, arow, brow, al_begin, n < S ? n : S, i0, i_last, f_first, f_last, W, meta[0]);
   __syncthreads();
-  slice_store(slice_load(w, al_begin, meta[0].lo[0]), cbuf0);
+  slice_store<NT>(slice_load<NT>(w, so, al_begin, meta[0].lo[0]), cbuf0);
   __syncthreads();
   // One SFT per step; the step is written twice (even SFTs read cbuf0 and
   // fill cbuf1, odd SFTs the reverse) so that every LDS access has a fixed
   // buffer.
-  auto step = [&](int k, const float4* seg, float4* next) __attribute__((always_inline)) {
+  // A wave whose frequencies are all beyond the last template runs the same
+  // steps without the evaluation; the loop is written once per case so that
+  // the accumulators are not merged across the two at every SFT.
+  auto step = [&](int k, const float4* seg, float4* next, auto live) __attribute__((always_inline)) {
     const int kk = k % S, gq = (k / S) & 1;
     if (kk == 0 && k + S < n) {                    // values of the next group, read after >= 1 barrier
       const int n1 = n - (k + S) < S ? n - (k + S) : S;
-      group_meta<NFD, S>(w, geo, arow, brow, al_begin + k + S, n1, i0, i_last, f_first, f_last, W, meta[gq ^ 1]);
+      group_meta<NFD, S, NT>(w, geo, arow, brow, al_begin + k + S, n1, i0, i_last, f_first, f_last, W, meta[gq ^ 1]);
     }
     const bool more = k + 1 < n;
     // unconditional (the last step reloads its own SFT and discards it), so
     // that the registers carry no branch-merged values the compiler must wait
     // for
     const int k1 = more ? k + 1 : k;
-    const SlicePrefetch pre = slice_load(w, al_begin + k1, meta[(k1 / S) & 1].lo[k1 % S]);
+    const SlicePrefetch pre = slice_load<NT>(w, so, al_begin + k1, meta[(k1 / S) & 1].lo[k1 % S]);
     const GroupMeta<NFD, S>& m = meta[gq];
     const int64_t al = al_begin + k;
+    if constexpr (decltype(live)::value) {
     const double2 g = m.geo[kk];
     const float a = m.a[kk], b = m.b[kk];
     const float pf = split_phase ? frac_split_product(m.tsplit[kk], fsplit)   // frac(tau f)
                                  : (float)fract64(g.x * f);
     const float cf = cos_rev(pf), sf = sin_rev(pf);
-    const int base = k_first + m.lo[kk];                           // absolute bin of slice column 0
+    // LDS byte address of bin k in row 0 of the slice: 16 k + (seg - 16 (k_first + lo)),
+    // in 32-bit modular arithmetic
+    // (uniform; kept opaque in a scalar register so that the compiler forms one
+    // shift-and-add per pair rather than folding the sign into a subtraction)
+    uint32_t boff = __builtin_amdgcn_readfirstlane(lds_address(seg) - 16u * (uint32_t)(k_first + m.lo[kk]));
+    __asm__ volatile("" : "+s"(boff));
     if (__builtin_amdgcn_readfirstlane(m.fast[kk])) {
 #pragma unroll
       for (int r = 0; r < NFD; ++r) {
-        const double dphi = bin_position(f, m.g[kk][r], g.y, T);
-        const int off = (int)dphi - base;
-        const float u = __builtin_fmaf(2.f, (float)fract64(dphi), -1.f);
-        interp_accumulate(seg[off], seg[Wp + off], seg[2 * Wp + off], seg[3 * Wp + off], u, cf, sf, m.e[kk][r], a,
-                          b, far[r], fai[r], fbr[r], fbi[r]);
-        if (r % 4 == 3) __builtin_amdgcn_sched_barrier(0);     // bounds the coefficient registers in flight
+        const double dphi = bin_position(f, m.g[kk][r], g.y);
+        const LdsPtr c = lds_pointer(((uint32_t)(int)dphi << 4) + boff);
+        const float u = (float)fract64(dphi);   // kappa
+        interp_accumulate(lds_load(c, 0), lds_load(c, Wp), lds_load(c, 2 * Wp), lds_load(c, 3 * Wp), u, cf, sf,
+                          m.e[kk][r], a, b, far[r], fai[r], fbr[r], fbi[r]);
+        if (r % G == G - 1) __builtin_amdgcn_sched_barrier(0);   // bounds the coefficient registers in flight
       }
     } else {
 #pragma unroll
       for (int r = 0; r < NFD; ++r) {
-        const double dphi = bin_position(f, m.g[kk][r], g.y, T);
+        const double dphi = bin_position(f, m.g[kk][r], g.y);
         const CoefSet cs = load_coef_global(w, al, (int64_t)(int)dphi - w.k_first);
-        const float u = __builtin_fmaf(2.f, (float)fract64(dphi), -1.f);
+        const float u = (float)fract64(dphi);   // kappa
         interp_accumulate(cs.c[0], cs.c[1], cs.c[2], cs.c[3], u, cf, sf, m.e[kk][r], a, b, far[r], fai[r], fbr[r],
                           fbi[r]);
       }
     }
-    if (more) slice_store(pre, next);               // the other buffer was consumed before the last barrier
+    }
+    if (more) slice_store<NT>(pre, next);           // the other buffer was consumed before the last barrier
     __syncthreads();
   };
-  for (int k = 0; k < n; k += 2) {
-    step(k, cbuf0, cbuf1);
-    if (k + 1 < n) step(k + 1, cbuf1, cbuf0);
+  if (wave_live) {
+    for (int k = 0; k < n; k += 2) {
+      step(k, cbuf0, cbuf1, std::true_type{});
+      if (k + 1 < n) step(k + 1, cbuf1, cbuf0, std::true_type{});
+    }
+  } else {
+    for (int k = 0; k < n; k += 2) {
+      step(k, cbuf0, cbuf1, std::false_type{});
+      if (k + 1 < n) step(k + 1, cbuf1, cbuf0, std::false_type{});
+    }
   }
   if (!jvalid) return;
   const bool last = al_end == w.n_sft;
@@ -711,13 +757,12 @@ __device__ __forceinline__ void interp_tile(const WuDev& w, int W, int64_t tile,
 }
 
 // One tile per work-group (see interp_tile).
-template <int NFD, int S, int MINW>
-__global__ __launch_bounds__(kThreads, MINW) void demod_interp_kernel(WuDev w, int W, int64_t al_begin,
-                                                                     int64_t al_end) {
-  __shared__ float4 cbuf0[kCoefPairs * kSegMax];
-  __shared__ float4 cbuf1[kCoefPairs * kSegMax];
+template <int NFD, int S, int MINW, int G, int NT>
+__global__ __launch_bounds__(NT, MINW) void demod_interp_kernel(WuDev w, int W, int64_t al_begin, int64_t al_end) {
   __shared__ GroupMeta<NFD, S> meta[2];
-  interp_tile<NFD, S>(w, W, blockIdx.x, al_begin, al_end, cbuf0, cbuf1, meta);
+  __shared__ float4 cbuf0[kCoefPairs * seg_cap(NT)];
+  __shared__ float4 cbuf1[kCoefPairs * seg_cap(NT)];
+  interp_tile<NFD, S, G, NT>(w, W, blockIdx.x, al_begin, al_end, cbuf0, cbuf1, meta);
 }
 
 // Many work units in one persistent launch: the grid holds as many
@@ -752,9 +797,9 @@ __global__ __launch_bounds__(kThreads, 2) void demod_interp_batch_kernel(const B
     const int W = ents[lo].seg;
     const int64_t local = tile - ents[lo].tile_begin;
     if (ents[lo].nfd == 8)
-      interp_tile<8, 16>(w, W, local, 0, w.n_sft, cbuf0, cbuf1, meta8);
+      interp_tile<8, 16, 4, kThreads>(w, W, local, 0, w.n_sft, cbuf0, cbuf1, meta8);
     else
-      interp_tile<4, 16>(w, W, local, 0, w.n_sft, cbuf0, cbuf1, meta4);
+      interp_tile<4, 16, 4, kThreads>(w, W, local, 0, w.n_sft, cbuf0, cbuf1, meta4);
     __syncthreads();                                 // LDS free for the next tile
   }
 }
@@ -774,7 +819,8 @@ __global__ void bins_kernel(WuDev w, int64_t n, const int32_t* i_sky, const int3
   sft_geometry(w, s, al, tau, tdot);
   const double fd = template_fd(w, i);
   const double f = template_f(w, j);
-  const double dphi = bin_position(f, fd * tau, tdot, w.t_sft);
+  const double P = bin_scale(tdot, w.t_sft);
+  const double dphi = bin_position(f, bin_offset(fd, tau, P), P);
   kstar[t] = (int64_t)dphi;
   kappa[t] = fract64(dphi);
   if (w.phase_mode) {       // the demodulation kernel's split form: frac(tau f) + frac(tau (fdot/2) tau)
@@ -807,7 +853,7 @@ hipError_t launch_geometry(const WuDev& w, GeoStatus* status, hipStream_t st) {
 }
 
 size_t demod_lds_bytes(const WuDev& w, const Tile& t, int kernel) {
-  if (kernel == KERNEL_INTERP) return 2 * (size_t)kCoefPairs * kSegMax * sizeof(float4);
+  if (kernel == KERNEL_INTERP) return 2 * (size_t)kCoefPairs * seg_cap(t.threads == 64 ? 64 : kThreads) * sizeof(float4);
   return (size_t)t.chunk * seg_width(kThreads * t.nf_reg, w.dterms) * sizeof(float2);
 }
 
@@ -856,36 +902,46 @@ int interp_launches(const WuDev& w, const Tile& t) {
   return (int)((w.n_sft + sb - 1) / sb);
 }
 
-template <int NFD, int S, int MINW>
+template <int NFD, int S, int MINW, int G, int NT>
 static hipError_t launch_interp_t(const WuDev& w, const Tile& t, hipStream_t st) {
   const int W = t.seg;
-  const int64_t n_ft = (w.n_f + kThreads - 1) / kThreads;
+  const int64_t n_ft = (w.n_f + NT - 1) / NT;
   const int64_t n_tiles = n_ft * ((w.n_fd + NFD - 1) / NFD) * w.n_sky;
-  if (n_tiles <= 0 || n_tiles > 0x7fffffffLL || W < 8 || W > kSegMax) return hipErrorInvalidConfiguration;
+  if (n_tiles <= 0 || n_tiles > 0x7fffffffLL || W < 8 || W > seg_cap(NT)) return hipErrorInvalidConfiguration;
   const int64_t sb = t.sblock > 0 ? t.sblock : w.n_sft;
   if (sb < w.n_sft && !w.acc) return hipErrorInvalidValue;
-  const size_t lds = 0;
   for (int64_t al = 0; al < w.n_sft; al += sb) {
     const int64_t end = al + sb < w.n_sft ? al + sb : w.n_sft;
-    hipLaunchKernelGGL((demod_interp_kernel<NFD, S, MINW>), dim3((unsigned)n_tiles), dim3(kThreads), lds, st, w, W, al,
-                       end);
+    hipLaunchKernelGGL((demod_interp_kernel<NFD, S, MINW, G, NT>), dim3((unsigned)n_tiles), dim3(NT), 0, st, w, W,
+                       al, end);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
 }
 
-int interp_max_seg(int chunk) { return chunk > 0 ? kSegMax : kSegMax; }
+int interp_max_seg(int threads) { return seg_cap(threads == 64 ? 64 : kThreads); }
 
-// Tile.chunk is the minimum number of waves per SIMD the compiler must leave
-// room for (2 or 3): it trades registers for occupancy.
+// Tile: nf_reg = spindowns per thread, chunk = minimum waves per SIMD the
+// compiler must leave room for (2 or 3), threads = work-group size (64: one
+// wave per work-group, no barrier between waves; 256: four waves share one
+// staged slice).
 static hipError_t launch_interp(const WuDev& w, const Tile& t, hipStream_t st) {
   const bool w3 = t.chunk >= 3;
+  if (t.threads == 64) {
+    switch (t.nf_reg) {
+      case 8: return w3 ? launch_interp_t<8, 16, 3, 4, 64>(w, t, st) : launch_interp_t<8, 16, 2, 4, 64>(w, t, st);
+      case 4: return launch_interp_t<4, 16, 3, 4, 64>(w, t, st);
+      case 2: return launch_interp_t<2, 16, 3, 4, 64>(w, t, st);
+      case 1: return launch_interp_t<1, 16, 3, 4, 64>(w, t, st);
+      default: return hipErrorInvalidValue;
+    }
+  }
   switch (t.nf_reg) {
-    case 8: return w3 ? launch_interp_t<8, 16, 3>(w, t, st) : launch_interp_t<8, 16, 2>(w, t, st);
-    case 4: return w3 ? launch_interp_t<4, 16, 3>(w, t, st) : launch_interp_t<4, 16, 2>(w, t, st);
-    case 2: return launch_interp_t<2, 16, 3>(w, t, st);
-    case 1: return launch_interp_t<1, 16, 3>(w, t, st);
+    case 8: return w3 ? launch_interp_t<8, 16, 3, 4, kThreads>(w, t, st) : launch_interp_t<8, 16, 2, 4, kThreads>(w, t, st);
+    case 4: return w3 ? launch_interp_t<4, 16, 3, 4, kThreads>(w, t, st) : launch_interp_t<4, 16, 2, 4, kThreads>(w, t, st);
+    case 2: return launch_interp_t<2, 16, 3, 4, kThreads>(w, t, st);
+    case 1: return launch_interp_t<1, 16, 3, 4, kThreads>(w, t, st);
     default: return hipErrorInvalidValue;
   }
 }

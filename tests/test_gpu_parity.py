@@ -113,6 +113,31 @@ def test_parity_ragged_tiles(torch_cuda, oracle_lib, dterms, kernel):
     _compare(oracle_lib, w, out)
 
 
+INTERP_TILES = [(8, 3, 0, 256), (8, 2, 0, 256), (8, 3, 7, 256), (4, 3, 0, 256), (4, 2, 7, 256), (2, 3, 0, 256),
+                (1, 3, 7, 256), (8, 3, 0, 64), (8, 2, 7, 64), (4, 3, 0, 64)]
+
+
+@pytest.mark.parametrize("tile", INTERP_TILES, ids=lambda t: "nf%d_w%d_sb%d_t%d" % t)
+def test_interp_tile_variants(torch_cuda, oracle_lib, tile, tmp_path):
+    """Every interp tile shape (spindowns per thread, waves per SIMD, SFTs
+    per launch, work-group size), forced through the tile cache, on ragged
+    frequency, spindown and SFT counts; a wide spindown range makes some
+    windows fall outside the staged slice (global-memory path)."""
+    torch = torch_cuda
+    w = small_workload(300, n_det=2, slots=23, keep=0.85, n_sky=3, n_fd=9, n_f=700, dterms=8,
+                       fdot_lo=-2.4e-6, injections=((1, 5, 333, 15.0),))
+    cache = tmp_path / "tiles.txt"
+    cache.write_text("s0_d8_k2 %d %d %d %d\n" % tile)
+    _say(f"tile {tile}: n_sft={w.n_sft} n_bins={w.n_bins} templates={w.n_templates}")
+    wu, _ = to_device(w)
+    out = alloc_output(w)
+    with _plan(w, kernel="interp", max_dterms=8) as p:
+        p.autotune(wu, out, cache_path=str(cache))
+        p.compute(wu, out)
+        torch.cuda.synchronize()
+    _compare(oracle_lib, w, out)
+
+
 @pytest.mark.parametrize("kernel", KERNELS)
 @pytest.mark.parametrize("storage", ["bf16", "fp16"])
 def test_parity_16bit_storage(torch_cuda, oracle_lib, storage, kernel):

@@ -177,9 +177,17 @@ def _py_bins(w, s, i, j, al):
     tdot = 1.0 + vn
     f = float(w.f0) + float(j) * float(w.df)
     fd = float(w.fdot0) + float(i) * float(w.dfdot)
-    dphi = ((f + fd * tau) * tdot) * T
+    P = tdot * T
+    q = (fd * tau) * P
+    dphi = _fma(f, P, q)
     k = math.floor(dphi)
     return k, dphi - k, tau, f, fd
+
+
+def _fma(a, b, c):
+    """a * b + c rounded once: exact rational sum, then Python's correctly
+    rounded integer division."""
+    return float(Fraction(a) * Fraction(b) + Fraction(c))
 
 
 def test_bin_index_bit_exact_vs_python(oracle_lib):
