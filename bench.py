@@ -23,13 +23,17 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X (gfx950): 256 CUs at 2.4 GHz.  FP32 VALU issues 128 lane-ops per CU
-# per clock (157.3 TFLOP/s counting an FMA as two flops), FP64 64 (78.6
-# TFLOP/s), transcendental ops (sin, cos, rcp) 32.  One "slot" is one FP32
-# lane-op: an FP64 op costs 2 slots, a transcendental 4.
-N_CU, CLK, FP32_LANES = 256, 2.4e9, 128
-PEAK_SLOTS = N_CU * FP32_LANES * CLK          # 7.86e13 slot/s
+# MI355X (gfx950): 256 CUs at 2.4 GHz, 4 SIMDs of 16 lanes per CU: one wave64
+# VALU instruction per SIMD every 4 clocks, i.e. 64 lane-ops per CU per clock
+# = 3.93e13 lane-ops/s for every unpacked FP32 or FP64 operation (FP64 FMA
+# is full rate: 78.6 TFLOP/s counting two flops; FP32 reaches 157.3 TFLOP/s
+# only with packed dual-FP32 instructions, which this library does not use).
+# Measured on the chip: FP32 and FP64 FMA issue at that rate, v_sin/v_cos
+# take two issue slots.  One "slot" is one lane-op at full rate.
+N_CU, CLK, LANES = 256, 2.4e9, 64
+PEAK_SLOTS = N_CU * LANES * CLK               # 3.93e13 slot/s
 HBM_PEAK = 8.0e12
+METRIC = "templates\u00b7SFTs/s for 2F (plain vs mixed-precision) at 2F rel err \u22641e-4; % roofline"
 
 
 def slots_per_pair(kernel: str, dterms: int, nfd: int = 8) -> float:
@@ -37,15 +41,17 @@ def slots_per_pair(kernel: str, dterms: int, nfd: int = 8) -> float:
     formulation (instruction count of the arithmetic the method needs; no
     addressing, staging or loop control)."""
     if kernel == "direct":
-        # FP64 bin index + phase 12 ops (24), near weights 19, far terms
-        # (2D-2) x 6, two fraction folds 12, near terms 8, sign 3,
-        # exp(-2 pi i phi) 12, Fa/Fb 4
-        return 12 * dterms + 70
+        # FP64 Dphi (fma), k*, kappa, 1 - kappa and phase: 10; sign 3;
+        # central weights 12 (sin and two reciprocals at 2 slots) and their
+        # terms 6; far terms (2D-2) x 6; fraction folds 8; sin/cos of the
+        # phase 4; rotation 4; Fa/Fb 4
+        return 12 * dterms + 39
     if kernel == "interp":
-        # FP64 Dphi 3 ops + k* + kappa + conversion (13 with u), degree-7
+        # FP64 Dphi (one fma), k*, kappa and its conversion 4, degree-7
         # complex Horner 14, phase factor product 4 + rotation 4, Fa/Fb 4;
-        # frac(tau f) and its sin/cos (14) shared by the nfd spindowns of a thread
-        return 39 + 14.0 / nfd
+        # frac(tau f) and its sin/cos (3 + 2 x 2) shared by the nfd spindowns
+        # of a thread
+        return 30 + 7.0 / nfd
     raise ValueError(kernel)
 
 
@@ -182,7 +188,7 @@ def main():
     slots = slots_per_pair(kernel, w.dterms) * pairs
     achieved = slots / (r["kernel_ms"] * 1e-3)
     line = {
-        "metric": "templates*SFTs/s for 2F",
+        "metric": METRIC,
         "value": r["value"],
         "unit": "templates*SFTs/s",
         "n_gpus": 1,
