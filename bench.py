@@ -103,7 +103,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--forms", default="c64,bf16,fp16")
+    ap.add_argument("--forms", default="c64,bf16,fp16,bf16+coef16",
+                    help="SFT storage (c64, bf16, fp16), optionally +coef16 for the FP16-coefficient form")
     ap.add_argument("--kernel", default="auto", help="auto (= interp), interp or direct")
     ap.add_argument("--compare-direct", type=int, default=2,
                     help="also time this many steps of the direct kernel on complex64 storage")
@@ -140,11 +141,13 @@ def main():
     forms = [f for f in args.forms.split(",") if f]
     results = {}
     for form in forms:
-        wu, _ = to_device(w, form)
+        storage, _, extra = form.partition("+")
+        coef = "f16" if extra == "coef16" else "f32"
+        wu, _ = to_device(w, storage)
         out = alloc_output(w)
         torch.cuda.synchronize()
         with P.Plan(max_sft=w.n_sft, max_bins=w.n_bins, max_sky=w.n_sky, max_fd=w.n_fd, max_f=w.n_f,
-                    max_dterms=w.dterms, storage=form, kernel=args.kernel) as plan:
+                    max_dterms=w.dterms, storage=storage, coef=coef, kernel=args.kernel) as plan:
             steps = args.steps if form == forms[0] else max(2, args.steps // 2)
             for _ in range(args.warmup):
                 plan.compute(wu, out)
@@ -157,7 +160,9 @@ def main():
             torch.cuda.synchronize()
             el = time.perf_counter() - t_start
         results[form] = {"steps": steps, "ms_per_step": 1e3 * el / steps, "value": steps * pairs / el,
-                         "kernel_ms": float(np.mean(kms))}
+                         "kernel_ms": float(np.mean(kms)),
+                         # the 2F error bound each form is tested to against the FP64 oracle
+                         "err_bound": 5e-3 if (coef == "f16" or storage != "c64") else 1e-4}
         print(f"[bench] {form}: {results[form]}", file=sys.stderr, flush=True)
         del wu, out
         torch.cuda.empty_cache()
@@ -201,9 +206,11 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": w.name, "n_det": w.n_det, "n_sft": w.n_sft, "n_bins": w.n_bins, "n_sky": w.n_sky,
-                   "n_fd": w.n_fd, "n_f": w.n_f, "dterms": w.dterms, "storage": main_form, "phase": "fp64",
+                   "n_fd": w.n_fd, "n_f": w.n_f, "dterms": w.dterms, "form": main_form, "phase": "fp64",
                    "kernel": kernel, "templates": w.n_templates, "pairs_per_step": pairs},
-        "forms": {k: {"value": v["value"], "ms_per_step": v["ms_per_step"], "kernel_ms": v["kernel_ms"]}
+        "forms": {k: {"value": v["value"], "ms_per_step": v["ms_per_step"], "kernel_ms": v["kernel_ms"],
+                      "err_bound": v["err_bound"],
+                      "vs_plain": v["value"] / results[main_form]["value"]}
                   for k, v in results.items()},
         "kernels": kernels,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12, "unit": "TOP/s",

@@ -35,6 +35,7 @@ FSTAT_KERNEL_AUTO = 0
 FSTAT_KERNEL_DIRECT = 1
 FSTAT_KERNEL_INTERP = 2
 FSTAT_FLAG_NO_GRAPH = 1
+FSTAT_FLAG_COEF16 = 2
 
 STORAGE = {"c64": FSTAT_STORAGE_C64, "bf16": FSTAT_STORAGE_BF16, "fp16": FSTAT_STORAGE_FP16}
 KERNELS = {"auto": FSTAT_KERNEL_AUTO, "direct": FSTAT_KERNEL_DIRECT, "interp": FSTAT_KERNEL_INTERP}
@@ -186,8 +187,14 @@ def _check(plan, rc: int):
 
 
 def fstat_plan_create(*, max_sft, max_bins, max_sky, max_fd, max_f, max_dterms=16, storage="c64", phase="fp64",
-                      kernel="auto", flags=0, device=-1):
+                      kernel="auto", coef="f32", flags=0, device=-1):
+    """coef="f16" selects the mixed-precision form of the interp kernel
+    (FP16 window-polynomial coefficients, FSTAT_FLAG_COEF16)."""
     lib = load_library()
+    if coef not in ("f32", "f16"):
+        raise ValueError(f"coef must be 'f32' or 'f16', not {coef!r}")
+    if coef == "f16":
+        flags |= FSTAT_FLAG_COEF16
     d = fstat_desc(int(max_sft), int(max_bins), int(max_sky), int(max_fd), int(max_f), int(max_dterms),
                    STORAGE.get(storage, storage), PHASES.get(phase, phase), KERNELS.get(kernel, kernel), int(flags),
                    int(device))

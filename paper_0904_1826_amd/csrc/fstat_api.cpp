@@ -38,6 +38,9 @@ struct fstat_plan {
   void* acc = nullptr;
   size_t acc_bytes = 0;
   std::map<int, double*> ctab;
+  std::map<int, double> csum;              // per Dterms: max_p sum_m |t[m][p]|
+  void* cexp = nullptr;                    // FP16 coefficient form: per-SFT exponents
+  size_t cexp_bytes = 0;
   // timing
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   hipStream_t ev_stream = nullptr;
@@ -164,6 +167,10 @@ WuDev make_dev(const fstat_plan* p, const fstat_wu* w, const fstat_out* o) {
   v.acc = (float4*)p->acc;
   auto it = p->ctab.find(w->dterms);
   v.ctab = it != p->ctab.end() ? it->second : nullptr;
+  auto is = p->csum.find(w->dterms);
+  v.csum = is != p->csum.end() ? is->second : 0.0;
+  v.coef16 = (p->d.flags & FSTAT_FLAG_COEF16) ? 1 : 0;
+  v.cexp = (int32_t*)p->cexp;
   v.n_sft = w->n_sft;
   v.n_bins = w->n_bins;
   v.k_first = w->k_first;
@@ -182,11 +189,16 @@ WuDev make_dev(const fstat_plan* p, const fstat_wu* w, const fstat_out* o) {
   return v;
 }
 
-// Coefficient scratch of one work unit: [n_sft][kCoefPairs][n_bins] float4,
-// plus kSegMax float4 of padding that the slice staging of the last SFT may
-// read (into columns it never uses).
-size_t coef_bytes(const fstat_wu* w) {
-  return ((size_t)w->n_sft * w->n_bins * fstat::kCoefPairs + fstat::kSegMax) * sizeof(float4);
+// Coefficient scratch of one work unit: [n_sft][rows][n_bins] 16-byte
+// elements (4 rows of FP32 pairs, or 2 rows of FP16 quadruples), plus one
+// slice row of padding that the staging of the last SFT may read (into
+// columns it never uses).
+bool coef16(const fstat_plan* p) { return (p->d.flags & FSTAT_FLAG_COEF16) != 0; }
+
+size_t coef_bytes(const fstat_plan* p, const fstat_wu* w) {
+  const size_t rows = coef16(p) ? fstat::kRows16 : fstat::kCoefPairs;
+  const size_t pad = fstat::kSegMax > fstat::kSegMax16 ? fstat::kSegMax : fstat::kSegMax16;
+  return ((size_t)w->n_sft * w->n_bins * rows + pad) * sizeof(float4);
 }
 
 int resolved_kernel(const fstat_plan* p) {
@@ -247,12 +259,19 @@ int ensure_ctab(fstat_plan* p, int D) {
     return hip_err(p, e, "polynomial table upload");
   }
   p->ctab[D] = (double*)d;
+  double mx = 0.0;                       // bound on |c_p| / max|x| for the FP16 form's scale
+  for (int q = 0; q < fstat::kCoef; ++q) {
+    double sum = 0.0;
+    for (int m = 0; m < 2 * D; ++m) sum += fabs(tab[(size_t)m * fstat::kCoef + q]);
+    mx = sum > mx ? sum : mx;
+  }
+  p->csum[D] = mx;
   return FSTAT_OK;
 }
 
 std::string class_key(const fstat_plan* p, const fstat_wu* w) {
   char b[64];
-  snprintf(b, sizeof b, "s%d_d%d_k%d", p->d.storage, w->dterms, p->d.kernel);
+  snprintf(b, sizeof b, "s%d_d%d_k%d_c%d", p->d.storage, w->dterms, p->d.kernel, coef16(p) ? 1 : 0);
   return b;
 }
 
@@ -261,29 +280,33 @@ std::string class_key(const fstat_plan* p, const fstat_wu* w) {
 // by up to |dfdot| (NFD-1) max|tau| T Tdot more; plus slack, rounded to 4.
 // Lanes whose window falls outside the slice read their coefficients from
 // global memory instead, so a narrower slice costs speed, not correctness;
-// the slice is capped at 5 NT / 4 bins (40 KB of LDS for 256 threads).
-int interp_seg_tau(const fstat_wu* w, int nfd, int threads, double max_abs_tau) {
+// the slice is capped at what the staging runs fill: 5 NT / 4 bins (40 KB of
+// LDS, double-buffered, for 256 threads) or 3 NT / 2 bins with FP16
+// coefficients (24 KB).
+int interp_seg_tau(const fstat_wu* w, int nfd, int threads, bool c16, double max_abs_tau) {
   const double tdot = 1.001;
   const double nt = threads;
   const double spread = ((nt - 1.0) * w->df + fabs(w->dfdot) * (nfd - 1) * max_abs_tau) * w->t_sft * tdot;
   const double width = nt + 6.0 + ceil(spread - (nt - 1.0) > 0 ? spread - (nt - 1.0) : 0.0);
-  const int cap = fstat::interp_max_seg(threads);
+  const int cap = fstat::interp_max_seg(threads, c16);
   int W = width > cap ? cap : (int)width;
   return W & ~3;
 }
 
 int interp_seg(const fstat_plan* p, const fstat_wu* w, int nfd, int threads) {
-  return interp_seg_tau(w, nfd, threads, p->max_abs_tau);
+  return interp_seg_tau(w, nfd, threads, coef16(p), p->max_abs_tau);
 }
 
 Tile default_tile(const fstat_plan* p, const fstat_wu* w) {
   if (resolved_kernel(p) == fstat::KERNEL_INTERP) {
     const int nfd = w->n_fd >= 8 ? 8 : (w->n_fd >= 4 ? 4 : (w->n_fd >= 2 ? 2 : 1));
     // measured on the work-unit-shaped case: 8 spindowns per thread with room
-    // for 3 waves per SIMD and one launch over all SFTs is fastest; with fewer
-    // spindowns per thread the staged slices are reused less and splitting the
-    // SFT loop into launches keeps them in L2
-    return Tile{nfd, 3, 0, nfd >= 4 ? 0 : 256, fstat::kThreads};
+    // for 3 waves per SIMD (4 with FP16 coefficients, whose slices take half
+    // the LDS and registers) and one launch over all SFTs is fastest; with
+    // fewer spindowns per thread the staged slices are reused less and
+    // splitting the SFT loop into launches keeps them in L2
+    const int minw = (coef16(p) && nfd == 8) ? 4 : 3;
+    return Tile{nfd, minw, 0, nfd >= 4 ? 0 : 256, fstat::kThreads};
   }
   return Tile{4, 4, 0, 0, 0};   // fastest direct tile on the work-unit-shaped case
 }
@@ -301,8 +324,12 @@ int ensure_scratch(fstat_plan* p, const fstat_wu* w) {
   rc = dev_alloc(p, &p->abcd, &p->abcd_bytes, (size_t)w->n_sky * sizeof(double4), "A,B,C scratch");
   if (rc) return rc;
   if (resolved_kernel(p) == fstat::KERNEL_INTERP) {
-    rc = dev_alloc(p, &p->coef, &p->coef_bytes, coef_bytes(w), "coefficient scratch");
+    rc = dev_alloc(p, &p->coef, &p->coef_bytes, coef_bytes(p, w), "coefficient scratch");
     if (rc) return rc;
+    if (coef16(p)) {
+      rc = dev_alloc(p, &p->cexp, &p->cexp_bytes, (size_t)w->n_sft * sizeof(int32_t), "coefficient exponents");
+      if (rc) return rc;
+    }
     rc = dev_alloc(p, &p->acc, &p->acc_bytes, (size_t)w->n_sky * w->n_fd * w->n_f * sizeof(float4),
                    "accumulator scratch");
     if (rc) return rc;
@@ -335,6 +362,10 @@ int run_geometry(fstat_plan* p, const WuDev& v, hipStream_t st, int idx) {
 int run_demod(fstat_plan* p, const WuDev& v, const Tile& t, hipStream_t st) {
   const int kernel = resolved_kernel(p);
   if (kernel == fstat::KERNEL_INTERP) {
+    if (v.coef16) {
+      int rc = check_launch(p, fstat::launch_cexp(v, st), "coefficient exponent kernel");
+      if (rc) return rc;
+    }
     int rc = check_launch(p, fstat::launch_coef(v, st), "coefficient kernel");
     if (rc) return rc;
   }
@@ -349,15 +380,16 @@ int run_demod(fstat_plan* p, const WuDev& v, const Tile& t, hipStream_t st) {
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct WuScratch {
-  size_t geo, abcd, coef, total;
+  size_t geo, abcd, coef, cexp, total;
 };
 
-WuScratch wu_scratch(const fstat_wu* w) {
+WuScratch wu_scratch(const fstat_plan* p, const fstat_wu* w) {
   WuScratch r;
   r.geo = align256((size_t)w->n_sky * w->n_sft * sizeof(double2));
   r.abcd = align256((size_t)w->n_sky * sizeof(double4));
-  r.coef = align256(coef_bytes(w));
-  r.total = r.geo + r.abcd + r.coef;
+  r.coef = align256(coef_bytes(p, w));
+  r.cexp = coef16(p) ? align256((size_t)w->n_sft * sizeof(int32_t)) : 0;
+  r.total = r.geo + r.abcd + r.coef + r.cexp;
   return r;
 }
 
@@ -388,7 +420,7 @@ int batch_check(fstat_plan* p, const fstat_wu* wus, const fstat_out* outs, int k
                 const std::vector<size_t>& offs, hipStream_t st) {
   for (int k = k0; k < k1; ++k) {
     WuDev v = make_dev(p, &wus[k], &outs[k]);
-    const WuScratch sc = wu_scratch(&wus[k]);
+    const WuScratch sc = wu_scratch(p, &wus[k]);
     v.geo = (double2*)(geo_base + offs[k]);
     v.abcd = (double4*)(geo_base + offs[k] + sc.geo);
     int rc = check_launch(p, fstat::launch_fill_int((int*)(p->bstat_d + k), 0, sizeof(fstat::GeoStatus) / sizeof(int), st),
@@ -429,7 +461,7 @@ int batch_interp(fstat_plan* p, const fstat_wu* wus, int n, const fstat_out* out
   size_t cur = 0, biggest = 0;
   int g0 = 0;
   for (int k = 0; k < n; ++k) {
-    const size_t need = wu_scratch(&wus[k]).total;
+    const size_t need = wu_scratch(p, &wus[k]).total;
     if (cur > 0 && cur + need > budget) {
       groups.push_back({g0, k});
       g0 = k;
@@ -455,7 +487,7 @@ int batch_interp(fstat_plan* p, const fstat_wu* wus, int n, const fstat_out* out
     rc = dev_alloc(p, (void**)&p->counter, &have, 64, "tile counter");
     if (rc) return rc;
   }
-  if (!p->batch_grid) p->batch_grid = fstat::interp_batch_grid();
+  if (!p->batch_grid) p->batch_grid = fstat::interp_batch_grid(coef16(p));
   // every work unit is checked before anything is demodulated
   if (groups.size() > 1) {
     for (auto& g : groups) {
@@ -474,25 +506,28 @@ int batch_interp(fstat_plan* p, const fstat_wu* wus, int n, const fstat_out* out
     for (int k = g.first; k < g.second; ++k) order.push_back(k);
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return wus[x].n_sft > wus[y].n_sft; });
     fstat::BatchEntry* eh = p->ents_h + g.first;
-    int64_t tiles = 0, blocks = 0;
+    int64_t tiles = 0, blocks = 0, sfts = 0;
     for (size_t q = 0; q < order.size(); ++q) {
       const int k = order[q];
       fstat::BatchEntry& e = eh[q];
       WuDev v = make_dev(p, &wus[k], &outs[k]);
-      const WuScratch sc = wu_scratch(&wus[k]);
+      const WuScratch sc = wu_scratch(p, &wus[k]);
       char* base = (char*)p->arena + offs[k];
       v.geo = (double2*)base;
       v.abcd = (double4*)(base + sc.geo);
       v.coef = (float4*)(base + sc.geo + sc.abcd);
+      v.cexp = sc.cexp ? (int32_t*)(base + sc.geo + sc.abcd + sc.coef) : nullptr;
       v.acc = nullptr;
       e.w = v;
       e.nfd = wus[k].n_fd >= 8 ? 8 : 4;
-      e.seg = interp_seg_tau(&wus[k], e.nfd, fstat::kThreads, status_tau(p->bstat_h[k]));
+      e.seg = interp_seg_tau(&wus[k], e.nfd, fstat::kThreads, coef16(p), status_tau(p->bstat_h[k]));
       e.n_tiles = fstat::interp_tiles(v, e.nfd);
       e.tile_begin = tiles;
       e.coef_begin = blocks;
+      e.sft_begin = sfts;
       tiles += e.n_tiles;
       blocks += fstat::coef_blocks(v);
+      sfts += wus[k].n_sft;
     }
     const int m = (int)order.size();
     fstat::BatchEntry* ed = p->ents_d + g.first;
@@ -502,14 +537,19 @@ int batch_interp(fstat_plan* p, const fstat_wu* wus, int n, const fstat_out* out
       (void)hipEventRecord(p->ev0, st);
       first = false;
     }
+    const bool c16 = coef16(p);
     if (p->d.flags & FSTAT_FLAG_NO_GRAPH) {
-      rc = check_launch(p, fstat::launch_coef_batch(ed, m, blocks, st), "coefficient kernel");
+      if (c16) {
+        rc = check_launch(p, fstat::launch_cexp_batch(ed, m, sfts, st), "coefficient exponent kernel");
+        if (rc) return rc;
+      }
+      rc = check_launch(p, fstat::launch_coef_batch(ed, m, blocks, c16, st), "coefficient kernel");
       if (rc) return rc;
-      rc = check_launch(p, fstat::launch_interp_batch(ed, m, tiles, p->counter, p->batch_grid, st), "batch kernel");
+      rc = check_launch(p, fstat::launch_interp_batch(ed, m, tiles, p->counter, p->batch_grid, c16, st), "batch kernel");
       if (rc) return rc;
       continue;
     }
-    const std::vector<int64_t> sig = {(int64_t)(intptr_t)ed, m, blocks, tiles, p->batch_grid};
+    const std::vector<int64_t> sig = {(int64_t)(intptr_t)ed, m, blocks, tiles, p->batch_grid, sfts};
     auto it = p->graphs.find(sig);
     if (it == p->graphs.end()) {
       if (!p->cap_stream) {
@@ -518,8 +558,9 @@ int batch_interp(fstat_plan* p, const fstat_wu* wus, int n, const fstat_out* out
       }
       e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal);
       if (e != hipSuccess) return hip_err(p, e, "graph capture");
-      hipError_t e1 = fstat::launch_coef_batch(ed, m, blocks, p->cap_stream);
-      hipError_t e2 = fstat::launch_interp_batch(ed, m, tiles, p->counter, p->batch_grid, p->cap_stream);
+      hipError_t e0 = c16 ? fstat::launch_cexp_batch(ed, m, sfts, p->cap_stream) : hipSuccess;
+      hipError_t e1 = e0 != hipSuccess ? e0 : fstat::launch_coef_batch(ed, m, blocks, c16, p->cap_stream);
+      hipError_t e2 = fstat::launch_interp_batch(ed, m, tiles, p->counter, p->batch_grid, c16, p->cap_stream);
       hipGraph_t graph = nullptr;
       e = hipStreamEndCapture(p->cap_stream, &graph);
       if (e1 != hipSuccess || e2 != hipSuccess || e != hipSuccess) {
@@ -554,6 +595,7 @@ int fstat_plan_create(fstat_plan** out, const fstat_desc* d) {
   if (d->storage < 0 || d->storage > 2) return FSTAT_E_ARG;
   if (d->phase_mode < 0 || d->phase_mode > 1) return FSTAT_E_ARG;
   if (d->kernel < 0 || d->kernel > 2) return FSTAT_E_ARG;
+  if (d->flags & ~(FSTAT_FLAG_NO_GRAPH | FSTAT_FLAG_COEF16)) return FSTAT_E_ARG;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
     (void)hipGetLastError();
@@ -576,8 +618,9 @@ int fstat_plan_create(fstat_plan** out, const fstat_desc* d) {
     return FSTAT_E_DEVICE;
   }
   p->cu_count = prop.multiProcessorCount;
-  if (p->d.phase_mode == FSTAT_PHASE_SPLIT_FP32 && p->d.kernel == FSTAT_KERNEL_DIRECT) {
-    // the split phase form is built into the interpolated kernel only
+  if ((p->d.phase_mode == FSTAT_PHASE_SPLIT_FP32 || (p->d.flags & FSTAT_FLAG_COEF16)) &&
+      p->d.kernel == FSTAT_KERNEL_DIRECT) {
+    // the split phase form and the FP16 coefficients belong to the interpolated kernel only
     delete p;
     return FSTAT_E_UNSUPPORTED;
   }
@@ -681,6 +724,8 @@ static bool valid_tile(const fstat_plan* p, const Tile& t) {
   if (t.sblock < 0) return false;
   if (resolved_kernel(p) == fstat::KERNEL_INTERP) {
     const bool nf_ok = t.nf_reg == 8 || t.nf_reg == 4 || t.nf_reg == 2 || t.nf_reg == 1;
+    if (coef16(p))   // 256-thread tiles; 4 waves per SIMD with 8 spindowns per thread
+      return nf_ok && t.threads == 256 && (t.chunk == 2 || t.chunk == 3 || (t.chunk == 4 && t.nf_reg == 8));
     return nf_ok && (t.chunk == 2 || t.chunk == 3) && (t.threads == 256 || (t.threads == 64 && t.nf_reg >= 4));
   }
   return (t.nf_reg == 1 && (t.chunk == 16 || t.chunk == 8)) || (t.nf_reg == 2 && (t.chunk == 8 || t.chunk == 4)) ||
@@ -716,10 +761,11 @@ int fstat_autotune(fstat_plan* p, const fstat_wu* wu, const fstat_out* out, void
   if (resolved_kernel(p) == fstat::KERNEL_INTERP) {
     for (int nt : {256, 64})
       for (int nfd : {8, 4, 2, 1})
-        for (int minw : {2, 3})
-          for (int sb : {64, 256, 0})
-            if ((nfd <= 2 * wu->n_fd || nfd == 1) && (nfd == 8 || minw == 3) && (nt == 256 || nfd >= 4))
-              cands.push_back(Tile{nfd, minw, 0, sb, nt});
+        for (int minw : {2, 3, 4})
+          for (int sb : {64, 256, 0}) {
+            const Tile t{nfd, minw, 0, sb, nt};
+            if ((nfd <= 2 * wu->n_fd || nfd == 1) && (nfd == 8 || minw == 3) && valid_tile(p, t)) cands.push_back(t);
+          }
   } else {
     cands = {Tile{1, 16, 0, 0, 0}, Tile{1, 8, 0, 0, 0}, Tile{2, 8, 0, 0, 0}, Tile{2, 4, 0, 0, 0}, Tile{4, 4, 0, 0, 0}};
   }

@@ -20,7 +20,11 @@ struct WuDev {
   float* twoF;             // [n_sky][n_fd][n_f]
   float2* fa;              // optional, same shape
   float2* fb;              // optional
-  float4* coef;            // interp kernel scratch: [n_sft][kCoefPairs][n_bins] coefficient pairs
+  float4* coef;            // interp kernel scratch: [n_sft][kCoefPairs][n_bins] coefficient pairs, or with
+                           // coef16 [n_sft][2][n_bins] of four FP16 complex coefficients each
+  int32_t* cexp;           // coef16: per-SFT exponent e, coefficients stored times 2^-e
+  double csum;             // coef16: max_p sum_m |t[m][p]| of the table (bounds |c_p| / max|x|)
+  int32_t coef16;
   const double* ctab;      // interp kernel: [2D][kCoef] polynomial coefficients of sinc(kappa+m)
   float4* acc;             // interp kernel scratch: running (Fa, Fb) per template between SFT blocks
   int64_t n_sft, n_bins, k_first, n_sky, n_f, n_fd;
@@ -55,6 +59,13 @@ constexpr int kCoefPairs = kCoef / 2;
 constexpr int kMaxRuns = 5;
 __host__ __device__ constexpr int seg_cap(int nt) { return nt + nt / 4; }
 constexpr int kSegMax = seg_cap(256);
+// FP16 coefficient form: one bin is 2 float4-sized rows (four complex FP16
+// coefficients each); each thread stages 3 of them per SFT, a row holds
+// 3 NT / 2 bins (384 for 256 threads).
+constexpr int kRows16 = 2;
+constexpr int kRuns16 = 3;
+__host__ __device__ constexpr int seg_cap16(int nt) { return 3 * nt / 2; }
+constexpr int kSegMax16 = seg_cap16(256);
 
 // One work unit of a batched launch: its device view, its slice width, its
 // spindowns per thread (4 or 8) and the index of its first tile in the
@@ -66,6 +77,7 @@ struct BatchEntry {
   int64_t tile_begin;   // first tile in the concatenated tile list
   int64_t n_tiles;
   int64_t coef_begin;   // first block of the batched coefficient pass
+  int64_t sft_begin;    // first SFT in the concatenated SFT list (coef16 exponent pass)
 };
 
 // Geometry pass results read back by the host.
@@ -91,13 +103,15 @@ hipError_t launch_demod(const WuDev& w, const Tile& t, int kernel, hipStream_t s
 int interp_launches(const WuDev& w, const Tile& t);
 int64_t interp_tiles(const WuDev& w, int nfd);
 int64_t coef_blocks(const WuDev& w);
-hipError_t launch_coef_batch(const BatchEntry* ents_dev, int n_ent, int64_t total_blocks, hipStream_t s);
+hipError_t launch_coef_batch(const BatchEntry* ents_dev, int n_ent, int64_t total_blocks, bool c16, hipStream_t s);
 hipError_t launch_interp_batch(const BatchEntry* ents_dev, int n_ent, int64_t total_tiles,
-                               unsigned long long* counter, int grid, hipStream_t s);
-int interp_batch_grid();
+                               unsigned long long* counter, int grid, bool c16, hipStream_t s);
+int interp_batch_grid(bool c16);
 hipError_t launch_bins(const WuDev& w, int64_t n, const int32_t* i_sky, const int32_t* i_fd, const int32_t* i_f,
                        const int32_t* i_sft, int64_t* kstar, double* kappa, double* phi_frac, hipStream_t s);
 size_t demod_lds_bytes(const WuDev& w, const Tile& t, int kernel);
-int interp_max_seg(int threads);
+int interp_max_seg(int threads, bool c16);
+hipError_t launch_cexp(const WuDev& w, hipStream_t s);
+hipError_t launch_cexp_batch(const BatchEntry* ents_dev, int n_ent, int64_t total_sfts, hipStream_t s);
 
 }  // namespace fstat

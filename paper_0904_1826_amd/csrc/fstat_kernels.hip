@@ -383,6 +383,16 @@ __global__ __launch_bounds__(kThreads) void demod_direct_kernel(WuDev w) {
 // (c_p, c_p+1) per float4); the demodulation kernel then evaluates one
 // polynomial per (template, SFT) pair instead of 2D weighted terms.  Bins
 // whose window would leave the band get zeros (no valid k* selects them).
+typedef _Float16 h2v __attribute__((ext_vector_type(2)));
+typedef _Float16 h8v __attribute__((ext_vector_type(8)));
+
+// Two FP64 values rounded to FP16 and packed into the bits of one float.
+__device__ __forceinline__ float pack_h2(double re, double im) {
+  const h2v h = {(_Float16)(float)re, (_Float16)(float)im};
+  return __builtin_bit_cast(float, h);
+}
+
+template <bool C16>
 __device__ __forceinline__ void coef_block(const WuDev& w, int64_t block, float2* xs, double* tab) {
   const int D = w.dterms;
   const int64_t n_cc = (w.n_bins + 255) / 256;
@@ -416,20 +426,33 @@ __device__ __forceinline__ void coef_block(const WuDev& w, int64_t block, float2
       }
     }
   }
-  float4* dst = w.coef + (al * kCoefPairs) * w.n_bins + c;
+  if constexpr (C16) {          // four complex coefficients per row, times 2^-e of the SFT
+    const double sc = ldexp(1.0, -w.cexp[al]);
+    float4* dst = w.coef + (al * kRows16) * w.n_bins + c;
 #pragma unroll
-  for (int q = 0; q < kCoefPairs; ++q)
-    dst[q * w.n_bins] = make_float4((float)cr[2 * q], (float)ci[2 * q], (float)cr[2 * q + 1], (float)ci[2 * q + 1]);
+    for (int q = 0; q < kRows16; ++q)
+      dst[q * w.n_bins] = make_float4(pack_h2(cr[4 * q] * sc, ci[4 * q] * sc),
+                                      pack_h2(cr[4 * q + 1] * sc, ci[4 * q + 1] * sc),
+                                      pack_h2(cr[4 * q + 2] * sc, ci[4 * q + 2] * sc),
+                                      pack_h2(cr[4 * q + 3] * sc, ci[4 * q + 3] * sc));
+  } else {
+    float4* dst = w.coef + (al * kCoefPairs) * w.n_bins + c;
+#pragma unroll
+    for (int q = 0; q < kCoefPairs; ++q)
+      dst[q * w.n_bins] = make_float4((float)cr[2 * q], (float)ci[2 * q], (float)cr[2 * q + 1], (float)ci[2 * q + 1]);
+  }
 }
 
+template <bool C16>
 __global__ __launch_bounds__(256) void coef_kernel(WuDev w) {
   __shared__ float2 xs[256 + 2 * kMaxDterms];
   __shared__ double tab[2 * kMaxDterms * kCoef];
-  coef_block(w, blockIdx.x, xs, tab);
+  coef_block<C16>(w, blockIdx.x, xs, tab);
 }
 
 // The coefficient pass of many work units in one launch; block b belongs to
 // the last entry whose coef_begin <= b.
+template <bool C16>
 __global__ __launch_bounds__(256) void coef_batch_kernel(const BatchEntry* __restrict__ ents, int n_ent) {
   __shared__ float2 xs[256 + 2 * kMaxDterms];
   __shared__ double tab[2 * kMaxDterms * kCoef];
@@ -440,11 +463,63 @@ __global__ __launch_bounds__(256) void coef_batch_kernel(const BatchEntry* __res
     if (ents[mid].coef_begin <= b) lo = mid; else hi = mid - 1;
   }
   const WuDev w = ents[lo].w;
-  coef_block(w, b - ents[lo].coef_begin, xs, tab);
+  coef_block<C16>(w, b - ents[lo].coef_begin, xs, tab);
+}
+
+// Per-SFT exponent of the FP16 coefficient form: e = (binary exponent of
+// max|x| csum) - 15, max over the SFT's bins of max(|re|, |im|), so that every
+// stored coefficient |c 2^-e| <= 2^15 < 65504 (the FP16 range).  An all-zero
+// SFT gets 0; e is clamped to [-120, 120].
+__device__ __forceinline__ void cexp_sft(const WuDev& w, int64_t al, float* red) {
+  float mx = 0.f;
+  for (int64_t n = threadIdx.x; n < w.n_bins; n += 256) {
+    const float2 v = load_bin(w, al, n);
+    mx = fmaxf(mx, fmaxf(fabsf(v.x), fabsf(v.y)));
+  }
+  for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double m = (double)fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3])) * w.csum;
+    int e = 0;
+    if (m > 0.0) {
+      int ex = 121;
+      if (m < 1e300) (void)frexp(m, &ex);
+      e = ex - 15;
+      e = e < -120 ? -120 : (e > 120 ? 120 : e);
+    }
+    w.cexp[al] = e;
+  }
+  __syncthreads();                                 // red is reused by the next SFT
+}
+
+__global__ __launch_bounds__(256) void cexp_kernel(WuDev w) {
+  __shared__ float red[4];
+  for (int64_t al = blockIdx.x; al < w.n_sft; al += gridDim.x) cexp_sft(w, al, red);
+}
+
+// The exponent pass of many work units: block b takes SFT b of the
+// concatenated SFT list (the last entry whose sft_begin <= b).
+__global__ __launch_bounds__(256) void cexp_batch_kernel(const BatchEntry* __restrict__ ents, int n_ent) {
+  __shared__ float red[4];
+  const int64_t b = blockIdx.x;
+  int lo = 0, hi = n_ent - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (ents[mid].sft_begin <= b) lo = mid; else hi = mid - 1;
+  }
+  const WuDev w = ents[lo].w;
+  cexp_sft(w, b - ents[lo].sft_begin, red);
 }
 
 struct CoefSet {
   float4 c[kCoefPairs];
+};
+
+typedef float v4f __attribute__((ext_vector_type(4)));   // native vector: stays in registers
+
+struct CoefSet16 {
+  v4f c[kRows16];
 };
 
 // Coefficients of one bin read straight from global memory, for a lane whose
@@ -457,6 +532,16 @@ __device__ __forceinline__ CoefSet load_coef_global(const WuDev& w, int64_t al, 
   CoefSet r;
 #pragma unroll
   for (int q = 0; q < kCoefPairs; ++q) r.c[q] = src[q * w.n_bins];
+  __asm__ volatile("" ::: "memory");
+  return r;
+}
+
+__device__ __forceinline__ CoefSet16 load_coef16_global(const WuDev& w, int64_t al, int64_t col) {
+  col = col < 0 ? 0 : (col >= w.n_bins ? w.n_bins - 1 : col);   // memory safety only
+  const v4f* src = reinterpret_cast<const v4f*>(w.coef) + al * kRows16 * w.n_bins + col;
+  CoefSet16 r;
+#pragma unroll
+  for (int q = 0; q < kRows16; ++q) r.c[q] = src[q * w.n_bins];
   __asm__ volatile("" ::: "memory");
   return r;
 }
@@ -488,8 +573,10 @@ __device__ __forceinline__ void group_meta(const WuDev& w, const double2* geo, c
   if (t3 >= 0 && t3 < n) {
     m.geo[t3] = geo[al0 + t3];
     m.tsplit[t3] = split64(geo[al0 + t3].x);
-    m.a[t3] = arow[al0 + t3];
-    m.b[t3] = brow[al0 + t3];
+    // the FP16 coefficient form stores c 2^-e: the weights carry 2^e
+    const float sa = w.coef16 ? ldexpf(1.f, w.cexp[al0 + t3]) : 1.f;
+    m.a[t3] = arow[al0 + t3] * sa;
+    m.b[t3] = brow[al0 + t3] * sa;
   }
   for (int e = tid; e < n * NFD; e += NT) {
     const int c = e / NFD, r = e % NFD;
@@ -530,8 +617,6 @@ __device__ __forceinline__ void group_meta(const WuDev& w, const double2* geo, c
 // carries, and fill only padding columns.  The loads are issued before the
 // current SFT is evaluated and written to LDS after it, so their latency
 // hides behind the arithmetic.
-typedef float v4f __attribute__((ext_vector_type(4)));   // native vector: stays in registers
-
 // LDS (address space 3) pointers as 32-bit byte addresses.
 typedef const __attribute__((address_space(3))) v4f* LdsPtr;
 __device__ __forceinline__ uint32_t lds_address(const float4* p) {
@@ -543,42 +628,55 @@ __device__ __forceinline__ float4 lds_load(LdsPtr p, int i) {
   return make_float4(v.x, v.y, v.z, v.w);
 }
 
+// Slice geometry of each coefficient form: float4 rows per bin, float4 each
+// thread stages per SFT, and bins per LDS row (rows x cap = runs x NT).
+template <int NT, bool C16>
+struct SliceForm {
+  static constexpr int rows = C16 ? kRows16 : kCoefPairs;
+  static constexpr int runs = C16 ? kRuns16 : kMaxRuns;
+  static constexpr int cap = C16 ? seg_cap16(NT) : seg_cap(NT);
+  static_assert(rows * cap == runs * NT, "slice rows must fill the staging runs exactly");
+};
+
+template <int R>
 struct SlicePrefetch {
-  v4f v[kMaxRuns];
+  v4f v[R];
 };
 
-template <int NT>
+template <int R>
 struct SliceOffsets {
-  uint32_t o[kMaxRuns];   // bytes from the slice start
+  uint32_t o[R];   // bytes from the slice start
 };
 
-template <int NT>
-__device__ __forceinline__ SliceOffsets<NT> slice_offsets(const WuDev& w) {
-  constexpr int cap = seg_cap(NT);
-  SliceOffsets<NT> so;
+template <int NT, bool C16>
+__device__ __forceinline__ SliceOffsets<SliceForm<NT, C16>::runs> slice_offsets(const WuDev& w) {
+  using F = SliceForm<NT, C16>;
+  SliceOffsets<F::runs> so;
 #pragma unroll
-  for (int i = 0; i < kMaxRuns; ++i) {
+  for (int i = 0; i < F::runs; ++i) {
     const int e = (int)threadIdx.x + NT * i;
-    so.o[i] = (uint32_t)(((e / cap) * w.n_bins + e % cap) * (int64_t)sizeof(float4));
+    so.o[i] = (uint32_t)(((e / F::cap) * w.n_bins + e % F::cap) * (int64_t)sizeof(float4));
   }
   return so;
 }
 
-template <int NT>
-__device__ __forceinline__ SlicePrefetch slice_load(const WuDev& w, const SliceOffsets<NT>& so, int64_t al, int lo) {
-  SlicePrefetch p;
+template <int NT, bool C16>
+__device__ __forceinline__ SlicePrefetch<SliceForm<NT, C16>::runs> slice_load(
+    const WuDev& w, const SliceOffsets<SliceForm<NT, C16>::runs>& so, int64_t al, int lo) {
+  using F = SliceForm<NT, C16>;
+  SlicePrefetch<F::runs> p;
   const int lo_u = __builtin_amdgcn_readfirstlane(lo);   // uniform: keeps the base in scalar registers
-  const char* base = reinterpret_cast<const char*>(w.coef + (al * kCoefPairs * w.n_bins + lo_u));
+  const char* base = reinterpret_cast<const char*>(w.coef + (al * F::rows * w.n_bins + lo_u));
 #pragma unroll
-  for (int i = 0; i < kMaxRuns; ++i) p.v[i] = *reinterpret_cast<const v4f*>(base + so.o[i]);
+  for (int i = 0; i < F::runs; ++i) p.v[i] = *reinterpret_cast<const v4f*>(base + so.o[i]);
   return p;
 }
 
-template <int NT>
-__device__ __forceinline__ void slice_store(const SlicePrefetch& p, float4* buf_) {
+template <int NT, int R>
+__device__ __forceinline__ void slice_store(const SlicePrefetch<R>& p, float4* buf_) {
   v4f* buf = reinterpret_cast<v4f*>(buf_);
 #pragma unroll
-  for (int i = 0; i < kMaxRuns; ++i) buf[(int)threadIdx.x + NT * i] = p.v[i];
+  for (int i = 0; i < R; ++i) buf[(int)threadIdx.x + NT * i] = p.v[i];
 }
 
 // Degree-7 complex polynomial in u = kappa (Horner) times exp(-2 pi i phi),
@@ -604,6 +702,33 @@ __device__ __forceinline__ void interp_accumulate(float4 c01, float4 c23, float4
   fbi = __builtin_fmaf(b, zi, fbi);
 }
 
+// The same with the FP16 coefficient form: two float4-sized rows hold c0..c3
+// and c4..c7 as FP16 (re, im) pairs; each Horner step is one FP32 fused
+// multiply-add whose addend is read as FP16.
+__device__ __forceinline__ void interp_accumulate16(v4f r0, v4f r1, float u, float cf, float sf, float2 eq, float a,
+                                                    float b, float& far, float& fai, float& fbr, float& fbi) {
+  // whole rows are reinterpreted (bit-casting single vector elements is not
+  // reliable): lo[2p], lo[2p+1] = re, im of c_p, hi likewise for c_{p+4}
+  const h8v lo = __builtin_bit_cast(h8v, r0), hi = __builtin_bit_cast(h8v, r1);
+  float gr = __builtin_fmaf((float)hi[6], u, (float)hi[4]), gi = __builtin_fmaf((float)hi[7], u, (float)hi[5]);
+  gr = __builtin_fmaf(gr, u, (float)hi[2]); gi = __builtin_fmaf(gi, u, (float)hi[3]);
+  gr = __builtin_fmaf(gr, u, (float)hi[0]); gi = __builtin_fmaf(gi, u, (float)hi[1]);
+  gr = __builtin_fmaf(gr, u, (float)lo[6]); gi = __builtin_fmaf(gi, u, (float)lo[7]);
+  gr = __builtin_fmaf(gr, u, (float)lo[4]); gi = __builtin_fmaf(gi, u, (float)lo[5]);
+  gr = __builtin_fmaf(gr, u, (float)lo[2]); gi = __builtin_fmaf(gi, u, (float)lo[3]);
+  gr = __builtin_fmaf(gr, u, (float)lo[0]); gi = __builtin_fmaf(gi, u, (float)lo[1]);
+  const float er = __builtin_fmaf(cf, eq.x, sf * eq.y);
+  const float ei = __builtin_fmaf(cf, eq.y, -sf * eq.x);
+  const float zr = __builtin_fmaf(gr, er, -gi * ei);
+  const float zi = __builtin_fmaf(gr, ei, gi * er);
+  far = __builtin_fmaf(a, zr, far);
+  fai = __builtin_fmaf(a, zi, fai);
+  fbr = __builtin_fmaf(b, zr, fbr);
+  fbi = __builtin_fmaf(b, zi, fbi);
+}
+
+__device__ __forceinline__ v4f lds_load_v(LdsPtr p, int i) { return p[i]; }
+
 // Demodulation over SFTs [al_begin, al_end) for tiles of (sky s, NFD
 // spindowns, NT frequencies), sky point fastest, one tile per work-group.
 // The host may split the SFT loop into launches of a few dozen SFTs: the
@@ -620,12 +745,13 @@ __device__ __forceinline__ void interp_accumulate(float4 c01, float4 c23, float4
 // a/b accumulation in registers.  An SFT whose windows are not all inside
 // the slice (only possible for slices narrower than the tile's spread) takes
 // the same arithmetic with coefficients read from global memory.
-template <int NFD, int S, int G, int NT>
+template <int NFD, int S, int G, int NT, bool C16>
 __device__ __forceinline__ void interp_tile(const WuDev& w, int W, int64_t tile, int64_t al_begin, int64_t al_end,
                                             float4* cbuf0, float4* cbuf1, GroupMeta<NFD, S>* meta) {
   const int tid = threadIdx.x;
   const int64_t n_fdb = (w.n_fd + NFD - 1) / NFD;
-  constexpr int Wp = seg_cap(NT);                  // LDS row stride
+  using F = SliceForm<NT, C16>;
+  constexpr int Wp = F::cap;                       // LDS row stride
   int64_t t = tile;
   const int64_t s = t % w.n_sky;
   t /= w.n_sky;
@@ -660,13 +786,13 @@ __device__ __forceinline__ void interp_tile(const WuDev& w, int W, int64_t tile,
     }
   }
 
-  const SliceOffsets<NT> so = slice_offsets<NT>(w);
+  const SliceOffsets<F::runs> so = slice_offsets<NT, C16>(w);
   // waves whose frequencies all lie beyond the band's last template only
   // help stage slices
   const bool wave_live = __builtin_amdgcn_readfirstlane((int)(j0 + (tid & ~63) < w.n_f));
   group_meta<NFD, S, NT>(w, geo, arow, brow, al_begin, n < S ? n : S, i0, i_last, f_first, f_last, W, meta[0]);
   __syncthreads();
-  slice_store<NT>(slice_load<NT>(w, so, al_begin, meta[0].lo[0]), cbuf0);
+  slice_store<NT>(slice_load<NT, C16>(w, so, al_begin, meta[0].lo[0]), cbuf0);
   __syncthreads();
   // One SFT per step; the step is written twice (even SFTs read cbuf0 and
   // fill cbuf1, odd SFTs the reverse) so that every LDS access has a fixed
@@ -685,7 +811,7 @@ __device__ __forceinline__ void interp_tile(const WuDev& w, int W, int64_t tile,
     // that the registers carry no branch-merged values the compiler must wait
     // for
     const int k1 = more ? k + 1 : k;
-    const SlicePrefetch pre = slice_load<NT>(w, so, al_begin + k1, meta[(k1 / S) & 1].lo[k1 % S]);
+    const SlicePrefetch<F::runs> pre = slice_load<NT, C16>(w, so, al_begin + k1, meta[(k1 / S) & 1].lo[k1 % S]);
     const GroupMeta<NFD, S>& m = meta[gq];
     const int64_t al = al_begin + k;
     if constexpr (decltype(live)::value) {
@@ -706,18 +832,27 @@ __device__ __forceinline__ void interp_tile(const WuDev& w, int W, int64_t tile,
         const double dphi = bin_position(f, m.g[kk][r], g.y);
         const LdsPtr c = lds_pointer(((uint32_t)(int)dphi << 4) + boff);
         const float u = (float)fract64(dphi);   // kappa
-        interp_accumulate(lds_load(c, 0), lds_load(c, Wp), lds_load(c, 2 * Wp), lds_load(c, 3 * Wp), u, cf, sf,
-                          m.e[kk][r], a, b, far[r], fai[r], fbr[r], fbi[r]);
+        if constexpr (C16)
+          interp_accumulate16(lds_load_v(c, 0), lds_load_v(c, Wp), u, cf, sf, m.e[kk][r], a, b, far[r], fai[r],
+                              fbr[r], fbi[r]);
+        else
+          interp_accumulate(lds_load(c, 0), lds_load(c, Wp), lds_load(c, 2 * Wp), lds_load(c, 3 * Wp), u, cf, sf,
+                            m.e[kk][r], a, b, far[r], fai[r], fbr[r], fbi[r]);
         if (r % G == G - 1) __builtin_amdgcn_sched_barrier(0);   // bounds the coefficient registers in flight
       }
     } else {
 #pragma unroll
       for (int r = 0; r < NFD; ++r) {
         const double dphi = bin_position(f, m.g[kk][r], g.y);
-        const CoefSet cs = load_coef_global(w, al, (int64_t)(int)dphi - w.k_first);
         const float u = (float)fract64(dphi);   // kappa
-        interp_accumulate(cs.c[0], cs.c[1], cs.c[2], cs.c[3], u, cf, sf, m.e[kk][r], a, b, far[r], fai[r], fbr[r],
-                          fbi[r]);
+        if constexpr (C16) {
+          const CoefSet16 cs = load_coef16_global(w, al, (int64_t)(int)dphi - w.k_first);
+          interp_accumulate16(cs.c[0], cs.c[1], u, cf, sf, m.e[kk][r], a, b, far[r], fai[r], fbr[r], fbi[r]);
+        } else {
+          const CoefSet cs = load_coef_global(w, al, (int64_t)(int)dphi - w.k_first);
+          interp_accumulate(cs.c[0], cs.c[1], cs.c[2], cs.c[3], u, cf, sf, m.e[kk][r], a, b, far[r], fai[r], fbr[r],
+                            fbi[r]);
+        }
       }
     }
     }
@@ -757,12 +892,13 @@ __device__ __forceinline__ void interp_tile(const WuDev& w, int W, int64_t tile,
 }
 
 // One tile per work-group (see interp_tile).
-template <int NFD, int S, int MINW, int G, int NT>
+template <int NFD, int S, int MINW, int G, int NT, bool C16>
 __global__ __launch_bounds__(NT, MINW) void demod_interp_kernel(WuDev w, int W, int64_t al_begin, int64_t al_end) {
+  using F = SliceForm<NT, C16>;
   __shared__ GroupMeta<NFD, S> meta[2];
-  __shared__ float4 cbuf0[kCoefPairs * seg_cap(NT)];
-  __shared__ float4 cbuf1[kCoefPairs * seg_cap(NT)];
-  interp_tile<NFD, S, G, NT>(w, W, blockIdx.x, al_begin, al_end, cbuf0, cbuf1, meta);
+  __shared__ float4 cbuf0[F::rows * F::cap];
+  __shared__ float4 cbuf1[F::rows * F::cap];
+  interp_tile<NFD, S, G, NT, C16>(w, W, blockIdx.x, al_begin, al_end, cbuf0, cbuf1, meta);
 }
 
 // Many work units in one persistent launch: the grid holds as many
@@ -773,11 +909,13 @@ __global__ __launch_bounds__(NT, MINW) void demod_interp_kernel(WuDev w, int W, 
 // one work unit are sky point fastest, as in the single-unit kernel, so the
 // work-groups running at once share coefficient slices in L2.  Dterms may
 // differ between work units: the window is folded into the coefficients.
+template <bool C16>
 __global__ __launch_bounds__(kThreads, 2) void demod_interp_batch_kernel(const BatchEntry* __restrict__ ents,
                                                                          int n_ent, int64_t total_tiles,
                                                                          unsigned long long* counter) {
-  __shared__ float4 cbuf0[kCoefPairs * kSegMax];
-  __shared__ float4 cbuf1[kCoefPairs * kSegMax];
+  using F = SliceForm<kThreads, C16>;
+  __shared__ float4 cbuf0[F::rows * F::cap];
+  __shared__ float4 cbuf1[F::rows * F::cap];
   __shared__ GroupMeta<8, 16> meta8[2];
   __shared__ GroupMeta<4, 16> meta4[2];
   __shared__ unsigned long long next;
@@ -797,9 +935,9 @@ __global__ __launch_bounds__(kThreads, 2) void demod_interp_batch_kernel(const B
     const int W = ents[lo].seg;
     const int64_t local = tile - ents[lo].tile_begin;
     if (ents[lo].nfd == 8)
-      interp_tile<8, 16, 4, kThreads>(w, W, local, 0, w.n_sft, cbuf0, cbuf1, meta8);
+      interp_tile<8, 16, 4, kThreads, C16>(w, W, local, 0, w.n_sft, cbuf0, cbuf1, meta8);
     else
-      interp_tile<4, 16, 4, kThreads>(w, W, local, 0, w.n_sft, cbuf0, cbuf1, meta4);
+      interp_tile<4, 16, 4, kThreads, C16>(w, W, local, 0, w.n_sft, cbuf0, cbuf1, meta4);
     __syncthreads();                                 // LDS free for the next tile
   }
 }
@@ -853,23 +991,46 @@ hipError_t launch_geometry(const WuDev& w, GeoStatus* status, hipStream_t st) {
 }
 
 size_t demod_lds_bytes(const WuDev& w, const Tile& t, int kernel) {
-  if (kernel == KERNEL_INTERP) return 2 * (size_t)kCoefPairs * seg_cap(t.threads == 64 ? 64 : kThreads) * sizeof(float4);
+  if (kernel == KERNEL_INTERP) {
+    const int nt = t.threads == 64 ? 64 : kThreads;
+    return 2 * (size_t)(w.coef16 ? kRuns16 : kMaxRuns) * nt * sizeof(float4);
+  }
   return (size_t)t.chunk * seg_width(kThreads * t.nf_reg, w.dterms) * sizeof(float2);
-}
-
-hipError_t launch_coef(const WuDev& w, hipStream_t st) {
-  const int64_t blocks = ((w.n_bins + 255) / 256) * w.n_sft;
-  if (blocks <= 0 || blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL(coef_kernel, dim3((unsigned)blocks), dim3(256), 0, st, w);
-  return hipGetLastError();
 }
 
 int64_t coef_blocks(const WuDev& w) { return ((w.n_bins + 255) / 256) * w.n_sft; }
 
-hipError_t launch_coef_batch(const BatchEntry* ents_dev, int n_ent, int64_t total_blocks, hipStream_t st) {
+hipError_t launch_coef(const WuDev& w, hipStream_t st) {
+  const int64_t blocks = coef_blocks(w);
+  if (blocks <= 0 || blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+  if (w.coef16)
+    hipLaunchKernelGGL(coef_kernel<true>, dim3((unsigned)blocks), dim3(256), 0, st, w);
+  else
+    hipLaunchKernelGGL(coef_kernel<false>, dim3((unsigned)blocks), dim3(256), 0, st, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_cexp(const WuDev& w, hipStream_t st) {
+  const int64_t blocks = w.n_sft < 65536 ? w.n_sft : 65536;
+  if (blocks <= 0) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL(cexp_kernel, dim3((unsigned)blocks), dim3(256), 0, st, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_cexp_batch(const BatchEntry* ents_dev, int n_ent, int64_t total_sfts, hipStream_t st) {
+  if (n_ent <= 0 || total_sfts <= 0) return hipSuccess;
+  if (total_sfts > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL(cexp_batch_kernel, dim3((unsigned)total_sfts), dim3(256), 0, st, ents_dev, n_ent);
+  return hipGetLastError();
+}
+
+hipError_t launch_coef_batch(const BatchEntry* ents_dev, int n_ent, int64_t total_blocks, bool c16, hipStream_t st) {
   if (n_ent <= 0 || total_blocks <= 0) return hipSuccess;
   if (total_blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL(coef_batch_kernel, dim3((unsigned)total_blocks), dim3(256), 0, st, ents_dev, n_ent);
+  if (c16)
+    hipLaunchKernelGGL(coef_batch_kernel<true>, dim3((unsigned)total_blocks), dim3(256), 0, st, ents_dev, n_ent);
+  else
+    hipLaunchKernelGGL(coef_batch_kernel<false>, dim3((unsigned)total_blocks), dim3(256), 0, st, ents_dev, n_ent);
   return hipGetLastError();
 }
 
@@ -877,23 +1038,29 @@ int64_t interp_tiles(const WuDev& w, int nfd) {
   return ((w.n_f + kThreads - 1) / kThreads) * ((w.n_fd + nfd - 1) / nfd) * w.n_sky;
 }
 
-int interp_batch_grid() {
+int interp_batch_grid(bool c16) {
   int dev = 0, cus = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     cus = 256;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, demod_interp_batch_kernel, kThreads, 0) != hipSuccess ||
-      per_cu < 1)
-    per_cu = 1;
+  const hipError_t e = c16 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, demod_interp_batch_kernel<true>,
+                                                                          kThreads, 0)
+                           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, demod_interp_batch_kernel<false>,
+                                                                          kThreads, 0);
+  if (e != hipSuccess || per_cu < 1) per_cu = 1;
   return per_cu * cus;
 }
 
 hipError_t launch_interp_batch(const BatchEntry* ents_dev, int n_ent, int64_t total_tiles,
-                               unsigned long long* counter, int grid, hipStream_t st) {
+                               unsigned long long* counter, int grid, bool c16, hipStream_t st) {
   if (n_ent <= 0 || total_tiles <= 0) return hipSuccess;
   hipError_t e = launch_fill_int((int*)counter, 0, 2, st);   // kernel, not memset: safe under capture
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(demod_interp_batch_kernel, dim3((unsigned)grid), dim3(kThreads), 0, st, ents_dev, n_ent,
-                     total_tiles, counter);
+  if (c16)
+    hipLaunchKernelGGL(demod_interp_batch_kernel<true>, dim3((unsigned)grid), dim3(kThreads), 0, st, ents_dev, n_ent,
+                       total_tiles, counter);
+  else
+    hipLaunchKernelGGL(demod_interp_batch_kernel<false>, dim3((unsigned)grid), dim3(kThreads), 0, st, ents_dev,
+                       n_ent, total_tiles, counter);
   return hipGetLastError();
 }
 
@@ -902,46 +1069,66 @@ int interp_launches(const WuDev& w, const Tile& t) {
   return (int)((w.n_sft + sb - 1) / sb);
 }
 
-template <int NFD, int S, int MINW, int G, int NT>
+template <int NFD, int S, int MINW, int G, int NT, bool C16>
 static hipError_t launch_interp_t(const WuDev& w, const Tile& t, hipStream_t st) {
   const int W = t.seg;
   const int64_t n_ft = (w.n_f + NT - 1) / NT;
   const int64_t n_tiles = n_ft * ((w.n_fd + NFD - 1) / NFD) * w.n_sky;
-  if (n_tiles <= 0 || n_tiles > 0x7fffffffLL || W < 8 || W > seg_cap(NT)) return hipErrorInvalidConfiguration;
+  if (n_tiles <= 0 || n_tiles > 0x7fffffffLL || W < 8 || W > SliceForm<NT, C16>::cap)
+    return hipErrorInvalidConfiguration;
   const int64_t sb = t.sblock > 0 ? t.sblock : w.n_sft;
   if (sb < w.n_sft && !w.acc) return hipErrorInvalidValue;
   for (int64_t al = 0; al < w.n_sft; al += sb) {
     const int64_t end = al + sb < w.n_sft ? al + sb : w.n_sft;
-    hipLaunchKernelGGL((demod_interp_kernel<NFD, S, MINW, G, NT>), dim3((unsigned)n_tiles), dim3(NT), 0, st, w, W,
-                       al, end);
+    hipLaunchKernelGGL((demod_interp_kernel<NFD, S, MINW, G, NT, C16>), dim3((unsigned)n_tiles), dim3(NT), 0, st, w,
+                       W, al, end);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
 }
 
-int interp_max_seg(int threads) { return seg_cap(threads == 64 ? 64 : kThreads); }
+int interp_max_seg(int threads, bool c16) {
+  const int nt = threads == 64 ? 64 : kThreads;
+  return c16 ? seg_cap16(nt) : seg_cap(nt);
+}
 
 // Tile: nf_reg = spindowns per thread, chunk = minimum waves per SIMD the
 // compiler must leave room for (2 or 3), threads = work-group size (64: one
 // wave per work-group, no barrier between waves; 256: four waves share one
-// staged slice).
+// staged slice; the FP16 coefficient form has 256-thread tiles only).
 static hipError_t launch_interp(const WuDev& w, const Tile& t, hipStream_t st) {
   const bool w3 = t.chunk >= 3;
+  if (w.coef16) {
+    if (t.threads == 64) return hipErrorInvalidValue;
+    switch (t.nf_reg) {
+      case 8: return t.chunk >= 4 ? launch_interp_t<8, 16, 4, 4, kThreads, true>(w, t, st)
+                     : w3         ? launch_interp_t<8, 16, 3, 4, kThreads, true>(w, t, st)
+                                  : launch_interp_t<8, 16, 2, 4, kThreads, true>(w, t, st);
+      case 4: return w3 ? launch_interp_t<4, 16, 3, 4, kThreads, true>(w, t, st)
+                        : launch_interp_t<4, 16, 2, 4, kThreads, true>(w, t, st);
+      case 2: return launch_interp_t<2, 16, 3, 4, kThreads, true>(w, t, st);
+      case 1: return launch_interp_t<1, 16, 3, 4, kThreads, true>(w, t, st);
+      default: return hipErrorInvalidValue;
+    }
+  }
   if (t.threads == 64) {
     switch (t.nf_reg) {
-      case 8: return w3 ? launch_interp_t<8, 16, 3, 4, 64>(w, t, st) : launch_interp_t<8, 16, 2, 4, 64>(w, t, st);
-      case 4: return launch_interp_t<4, 16, 3, 4, 64>(w, t, st);
-      case 2: return launch_interp_t<2, 16, 3, 4, 64>(w, t, st);
-      case 1: return launch_interp_t<1, 16, 3, 4, 64>(w, t, st);
+      case 8: return w3 ? launch_interp_t<8, 16, 3, 4, 64, false>(w, t, st)
+                        : launch_interp_t<8, 16, 2, 4, 64, false>(w, t, st);
+      case 4: return launch_interp_t<4, 16, 3, 4, 64, false>(w, t, st);
+      case 2: return launch_interp_t<2, 16, 3, 4, 64, false>(w, t, st);
+      case 1: return launch_interp_t<1, 16, 3, 4, 64, false>(w, t, st);
       default: return hipErrorInvalidValue;
     }
   }
   switch (t.nf_reg) {
-    case 8: return w3 ? launch_interp_t<8, 16, 3, 4, kThreads>(w, t, st) : launch_interp_t<8, 16, 2, 4, kThreads>(w, t, st);
-    case 4: return w3 ? launch_interp_t<4, 16, 3, 4, kThreads>(w, t, st) : launch_interp_t<4, 16, 2, 4, kThreads>(w, t, st);
-    case 2: return launch_interp_t<2, 16, 3, 4, kThreads>(w, t, st);
-    case 1: return launch_interp_t<1, 16, 3, 4, kThreads>(w, t, st);
+    case 8: return w3 ? launch_interp_t<8, 16, 3, 4, kThreads, false>(w, t, st)
+                      : launch_interp_t<8, 16, 2, 4, kThreads, false>(w, t, st);
+    case 4: return w3 ? launch_interp_t<4, 16, 3, 4, kThreads, false>(w, t, st)
+                      : launch_interp_t<4, 16, 2, 4, kThreads, false>(w, t, st);
+    case 2: return launch_interp_t<2, 16, 3, 4, kThreads, false>(w, t, st);
+    case 1: return launch_interp_t<1, 16, 3, 4, kThreads, false>(w, t, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -1,0 +1,157 @@
+"""Mixed-precision form of the interp kernel (FSTAT_FLAG_COEF16): the per-bin
+window polynomials stored as FP16 with a per-SFT power-of-two scale and
+evaluated in FP32.  2F against the FP64 oracle within e <= 5e-3 (the bound
+for 16-bit storage), reported per template block; batched results identical
+to single-unit calls; every tile shape; inputs far from unit scale."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from synth.device import to_device, alloc_output
+from tests._helpers import small_workload, replace, twoF_error
+
+pytestmark = pytest.mark.gpu
+TOL16 = 5e-3
+SKY_SAMPLE = list(range(0, 2000, 200))            # 10 blocks of 8 x 3600 templates
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _plan(ws, **kw):
+    import paper_0904_1826_amd as P
+    return P.Plan(max_sft=max(w.n_sft for w in ws), max_bins=max(w.n_bins for w in ws),
+                  max_sky=max(w.n_sky for w in ws), max_fd=max(w.n_fd for w in ws), max_f=max(w.n_f for w in ws),
+                  max_dterms=max(max(w.dterms for w in ws), 16), **kw)
+
+
+def _run(torch, w, storage="c64", coef="f16", cache=None):
+    wu, deq = to_device(w, storage)
+    out = alloc_output(w)
+    with _plan([w], storage=storage, coef=coef, kernel="interp") as p:
+        if cache:
+            p.autotune(wu, out, cache_path=cache)
+        p.compute(wu, out)
+        torch.cuda.synchronize()
+    tw = out.twoF.cpu().numpy()
+    del wu, out
+    torch.cuda.empty_cache()
+    return tw, deq
+
+
+def test_mixed_config1_blocks(torch_cuda, oracle_lib):
+    """The work-unit-shaped case, ten sky points (all spindowns and
+    frequencies, all SFTs) plus every injection, plain and mixed forms."""
+    torch = torch_cuda
+    w = synth.make_config(1)
+    s, i, j = oracle_lib.all_templates(w, SKY_SAMPLE)
+    inj = [(x.sky_index, x.fdot_index, x.f_index) for x in w.injections]
+    ref = oracle_lib.fstat(w, (s, i, j))["twoF"]
+    nb = len(SKY_SAMPLE)
+    rows = {}
+    for name, storage, coef in [("c64/f32", "c64", "f32"), ("c64/f16", "c64", "f16"), ("bf16/f16", "bf16", "f16")]:
+        tw, deq = _run(torch, w, storage, coef)
+        g = tw[s, i, j].astype(np.float64)
+        assert np.all(np.isfinite(g))
+        r = ref if deq is None else oracle_lib.fstat(w, (s, i, j), sft=deq)["twoF"]
+        e = twoF_error(g, r).reshape(nb, -1)
+        rows[name] = (e.max(axis=1).max(), np.sqrt(np.mean(e * e, axis=1)).max())
+        _say(f"  {name:9s} max {rows[name][0]:.2e} rms {rows[name][1]:.2e}  injections "
+             f"{[float(tw[a, b, c]) for a, b, c in inj]}")
+        for (a, b, c), x in zip(inj, w.injections):
+            assert tw[a, b, c] > 0.5 * x.snr ** 2, (name, x)
+    assert rows["c64/f32"][0] <= 1e-4
+    assert rows["c64/f16"][0] <= TOL16
+    assert rows["bf16/f16"][0] <= TOL16
+
+
+@pytest.mark.parametrize("dterms", [1, 8, 33])
+def test_mixed_ragged(torch_cuda, oracle_lib, dterms):
+    w = small_workload(700 + dterms, n_det=2, slots=23, keep=0.8, n_sky=3, n_fd=5, n_f=700, dterms=dterms,
+                       injections=((1, 2, 333, 15.0),))
+    tw, _ = _run(torch_cuda, w)
+    e = twoF_error(tw.ravel(), oracle_lib.fstat(w)["twoF"])
+    _say(f"D={dterms}: max e {e.max():.2e} rms {math.sqrt(np.mean(e * e)):.2e}")
+    assert e.max() <= TOL16
+
+
+MIXED_TILES = [(8, 3, 0, 256), (8, 2, 7, 256), (8, 4, 0, 256), (8, 4, 7, 256), (4, 3, 0, 256), (4, 2, 7, 256),
+               (2, 3, 0, 256), (1, 3, 7, 256)]
+
+
+@pytest.mark.parametrize("tile", MIXED_TILES, ids=lambda t: "nf%d_w%d_sb%d_t%d" % t)
+def test_mixed_tile_variants(torch_cuda, oracle_lib, tile, tmp_path):
+    """Every tile shape of the FP16 form, forced through the tile cache, on a
+    wide-spindown workload whose widest tiles take the global-memory path."""
+    w = small_workload(300, n_det=2, slots=23, keep=0.85, n_sky=3, n_fd=9, n_f=700, dterms=8,
+                       fdot_lo=-2.4e-6, injections=((1, 5, 333, 15.0),))
+    cache = tmp_path / "tiles.txt"
+    cache.write_text("s0_d8_k2_c1 %d %d %d %d\n" % tile)
+    tw, _ = _run(torch_cuda, w, cache=str(cache))
+    e = twoF_error(tw.ravel(), oracle_lib.fstat(w)["twoF"])
+    _say(f"tile {tile}: max e {e.max():.2e}")
+    assert e.max() <= TOL16
+
+
+@pytest.mark.parametrize("scale", ["tiny", "huge", "mixed"])
+def test_mixed_far_from_unit_scale(torch_cuda, oracle_lib, scale):
+    """SFT amplitudes of 1e-12, 1e+12, or per-SFT factors from 1e-9 to 1e+9:
+    the per-SFT exponent keeps the FP16 coefficients in range."""
+    w = small_workload(800, n_det=2, slots=20, keep=0.9, n_sky=2, n_fd=3, n_f=400, dterms=8,
+                       injections=((0, 1, 150, 15.0),))
+    rng = np.random.default_rng(5)
+    if scale == "tiny":
+        f = np.full(w.n_sft, 1e-12)
+    elif scale == "huge":
+        f = np.full(w.n_sft, 1e12)
+    else:
+        f = 10.0 ** rng.uniform(-9, 9, w.n_sft)
+    w = replace(w, sft=(w.sft * f[:, None]).astype(np.complex64))
+    tw, _ = _run(torch_cuda, w)
+    ref = oracle_lib.fstat(w)["twoF"]
+    assert np.all(np.isfinite(tw))
+    e = np.abs(tw.ravel().astype(np.float64) - ref) / np.maximum(ref, 4.0 * np.median(ref) / 3.36)
+    _say(f"{scale}: max e {e.max():.2e}")
+    assert e.max() <= TOL16
+
+
+def test_mixed_batch_matches_single(torch_cuda, oracle_lib):
+    torch = torch_cuda
+    ws = synth.make_batch(3, n_wu=5, scale=0.1)
+    devs = [to_device(w, "c64") for w in ws]
+    outs = [alloc_output(w) for w in ws]
+    with _plan(ws, coef="f16") as p:
+        p.batch_compute([d[0] for d in devs], outs)
+        torch.cuda.synchronize()
+    for k, w in enumerate(ws):
+        single = alloc_output(w)
+        with _plan([w], coef="f16") as p:
+            p.compute(devs[k][0], single)
+            torch.cuda.synchronize()
+        a, b = outs[k].twoF.cpu().numpy(), single.twoF.cpu().numpy()
+        assert np.array_equal(a, b), (k, np.max(np.abs(a - b)))
+        s, i, j = oracle_lib.all_templates(w, [0, w.n_sky - 1])
+        e = twoF_error(a[s, i, j], oracle_lib.fstat(w, (s, i, j))["twoF"])
+        _say(f"work unit {k}: n_sft {w.n_sft} D {w.dterms} max e {e.max():.2e}")
+        assert e.max() <= TOL16
+
+
+def test_mixed_with_direct_kernel_is_unsupported(torch_cuda):
+    import paper_0904_1826_amd as P
+    w = small_workload(801, n_sky=1, n_fd=1, n_f=10, injections=())
+    with pytest.raises(P.FstatError) as e:
+        _plan([w], coef="f16", kernel="direct")
+    assert e.value.code == P.FSTAT_E_UNSUPPORTED

@@ -127,7 +127,7 @@ def test_interp_tile_variants(torch_cuda, oracle_lib, tile, tmp_path):
     w = small_workload(300, n_det=2, slots=23, keep=0.85, n_sky=3, n_fd=9, n_f=700, dterms=8,
                        fdot_lo=-2.4e-6, injections=((1, 5, 333, 15.0),))
     cache = tmp_path / "tiles.txt"
-    cache.write_text("s0_d8_k2 %d %d %d %d\n" % tile)
+    cache.write_text("s0_d8_k2_c0 %d %d %d %d\n" % tile)
     _say(f"tile {tile}: n_sft={w.n_sft} n_bins={w.n_bins} templates={w.n_templates}")
     wu, _ = to_device(w)
     out = alloc_output(w)
