@@ -59,7 +59,7 @@ struct fstat_plan {
   size_t ents_cap = 0;
   unsigned long long* counter = nullptr;
   hipStream_t cap_stream = nullptr;
-  int batch_grid = 0;
+  int batch_grid = 0, batch_grid4 = 0;   // persistent grids of the 8- and 4-spindown batch kernels
   std::map<std::vector<int64_t>, hipGraphExec_t> graphs;
   // fault injection (host-side forcing of error paths)
   long fail_malloc_at = -1, fail_launch_at = -1;
@@ -487,7 +487,10 @@ int batch_interp(fstat_plan* p, const fstat_wu* wus, int n, const fstat_out* out
     rc = dev_alloc(p, (void**)&p->counter, &have, 64, "tile counter");
     if (rc) return rc;
   }
-  if (!p->batch_grid) p->batch_grid = fstat::interp_batch_grid(coef16(p));
+  if (!p->batch_grid) {
+    p->batch_grid = fstat::interp_batch_grid(coef16(p), 8);
+    p->batch_grid4 = fstat::interp_batch_grid(coef16(p), 4);
+  }
   // every work unit is checked before anything is demodulated
   if (groups.size() > 1) {
     for (auto& g : groups) {
@@ -501,14 +504,24 @@ int batch_interp(fstat_plan* p, const fstat_wu* wus, int n, const fstat_out* out
   for (auto& g : groups) {
     rc = batch_check(p, wus, outs, g.first, g.second, (char*)p->arena, offs, st);
     if (rc) return rc;
-    // table of the group, most SFTs first
+    // table of the group: the units with 8 spindowns per thread, then those
+    // with 4 (one persistent launch each), most SFTs first within each
     std::vector<int> order;
     for (int k = g.first; k < g.second; ++k) order.push_back(k);
-    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return wus[x].n_sft > wus[y].n_sft; });
+    auto nfd_of = [&](int k) { return wus[k].n_fd >= 8 ? 8 : 4; };
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+      return nfd_of(x) != nfd_of(y) ? nfd_of(x) > nfd_of(y) : wus[x].n_sft > wus[y].n_sft;
+    });
     fstat::BatchEntry* eh = p->ents_h + g.first;
-    int64_t tiles = 0, blocks = 0, sfts = 0;
+    int64_t tiles = 0, blocks = 0, sfts = 0, tiles8 = 0;
+    int m8 = 0;
     for (size_t q = 0; q < order.size(); ++q) {
       const int k = order[q];
+      if (nfd_of(k) == 8) m8 = (int)q + 1;
+      if (nfd_of(k) == 4 && (q == 0 || nfd_of(order[q - 1]) == 8)) {
+        tiles8 = tiles;                              // the 4-spindown table numbers its tiles from 0
+        tiles = 0;
+      }
       fstat::BatchEntry& e = eh[q];
       WuDev v = make_dev(p, &wus[k], &outs[k]);
       const WuScratch sc = wu_scratch(p, &wus[k]);
@@ -519,7 +532,7 @@ int batch_interp(fstat_plan* p, const fstat_wu* wus, int n, const fstat_out* out
       v.cexp = sc.cexp ? (int32_t*)(base + sc.geo + sc.abcd + sc.coef) : nullptr;
       v.acc = nullptr;
       e.w = v;
-      e.nfd = wus[k].n_fd >= 8 ? 8 : 4;
+      e.nfd = nfd_of(k);
       e.seg = interp_seg_tau(&wus[k], e.nfd, fstat::kThreads, coef16(p), status_tau(p->bstat_h[k]));
       e.n_tiles = fstat::interp_tiles(v, e.nfd);
       e.tile_begin = tiles;
@@ -530,6 +543,8 @@ int batch_interp(fstat_plan* p, const fstat_wu* wus, int n, const fstat_out* out
       sfts += wus[k].n_sft;
     }
     const int m = (int)order.size();
+    if (m8 == m) tiles8 = tiles;                     // only 8-spindown units
+    const int64_t tiles4 = m8 == m ? 0 : tiles;
     fstat::BatchEntry* ed = p->ents_d + g.first;
     hipError_t e = hipMemcpyAsync(ed, eh, (size_t)m * sizeof(fstat::BatchEntry), hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return hip_err(p, e, "work-unit table upload");
@@ -545,11 +560,16 @@ int batch_interp(fstat_plan* p, const fstat_wu* wus, int n, const fstat_out* out
       }
       rc = check_launch(p, fstat::launch_coef_batch(ed, m, blocks, c16, st), "coefficient kernel");
       if (rc) return rc;
-      rc = check_launch(p, fstat::launch_interp_batch(ed, m, tiles, p->counter, p->batch_grid, c16, st), "batch kernel");
+      rc = check_launch(p, fstat::launch_interp_batch(ed, m8, tiles8, p->counter, p->batch_grid, c16, 8, st),
+                        "batch kernel");
+      if (rc) return rc;
+      rc = check_launch(p, fstat::launch_interp_batch(ed + m8, m - m8, tiles4, p->counter + 1, p->batch_grid4, c16, 4,
+                                                      st),
+                        "batch kernel");
       if (rc) return rc;
       continue;
     }
-    const std::vector<int64_t> sig = {(int64_t)(intptr_t)ed, m, blocks, tiles, p->batch_grid, sfts};
+    const std::vector<int64_t> sig = {(int64_t)(intptr_t)ed, m, m8, blocks, tiles8, tiles4, p->batch_grid, sfts};
     auto it = p->graphs.find(sig);
     if (it == p->graphs.end()) {
       if (!p->cap_stream) {
@@ -560,7 +580,10 @@ int batch_interp(fstat_plan* p, const fstat_wu* wus, int n, const fstat_out* out
       if (e != hipSuccess) return hip_err(p, e, "graph capture");
       hipError_t e0 = c16 ? fstat::launch_cexp_batch(ed, m, sfts, p->cap_stream) : hipSuccess;
       hipError_t e1 = e0 != hipSuccess ? e0 : fstat::launch_coef_batch(ed, m, blocks, c16, p->cap_stream);
-      hipError_t e2 = fstat::launch_interp_batch(ed, m, tiles, p->counter, p->batch_grid, c16, p->cap_stream);
+      hipError_t e2 = fstat::launch_interp_batch(ed, m8, tiles8, p->counter, p->batch_grid, c16, 8, p->cap_stream);
+      if (e2 == hipSuccess)
+        e2 = fstat::launch_interp_batch(ed + m8, m - m8, tiles4, p->counter + 1, p->batch_grid4, c16, 4,
+                                        p->cap_stream);
       hipGraph_t graph = nullptr;
       e = hipStreamEndCapture(p->cap_stream, &graph);
       if (e1 != hipSuccess || e2 != hipSuccess || e != hipSuccess) {

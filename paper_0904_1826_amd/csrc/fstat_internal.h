@@ -105,8 +105,8 @@ int64_t interp_tiles(const WuDev& w, int nfd);
 int64_t coef_blocks(const WuDev& w);
 hipError_t launch_coef_batch(const BatchEntry* ents_dev, int n_ent, int64_t total_blocks, bool c16, hipStream_t s);
 hipError_t launch_interp_batch(const BatchEntry* ents_dev, int n_ent, int64_t total_tiles,
-                               unsigned long long* counter, int grid, bool c16, hipStream_t s);
-int interp_batch_grid(bool c16);
+                               unsigned long long* counter, int grid, bool c16, int nfd, hipStream_t s);
+int interp_batch_grid(bool c16, int nfd);
 hipError_t launch_bins(const WuDev& w, int64_t n, const int32_t* i_sky, const int32_t* i_fd, const int32_t* i_f,
                        const int32_t* i_sft, int64_t* kstar, double* kappa, double* phi_frac, hipStream_t s);
 size_t demod_lds_bytes(const WuDev& w, const Tile& t, int kernel);

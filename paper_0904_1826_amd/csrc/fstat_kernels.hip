@@ -909,15 +909,16 @@ __global__ __launch_bounds__(NT, MINW) void demod_interp_kernel(WuDev w, int W, 
 // one work unit are sky point fastest, as in the single-unit kernel, so the
 // work-groups running at once share coefficient slices in L2.  Dterms may
 // differ between work units: the window is folded into the coefficients.
-template <bool C16>
-__global__ __launch_bounds__(kThreads, 2) void demod_interp_batch_kernel(const BatchEntry* __restrict__ ents,
-                                                                         int n_ent, int64_t total_tiles,
-                                                                         unsigned long long* counter) {
+// One launch serves the work units of one spindown block size (8 or 4 per
+// thread), so that each specialisation keeps the registers, and hence the
+// occupancy, of the single-unit kernel.
+template <int NFD, bool C16>
+__global__ __launch_bounds__(kThreads, (C16 && NFD == 8) ? 4 : 3) void demod_interp_batch_kernel(
+    const BatchEntry* __restrict__ ents, int n_ent, int64_t total_tiles, unsigned long long* counter) {
   using F = SliceForm<kThreads, C16>;
+  __shared__ GroupMeta<NFD, 16> meta[2];
   __shared__ float4 cbuf0[F::rows * F::cap];
   __shared__ float4 cbuf1[F::rows * F::cap];
-  __shared__ GroupMeta<8, 16> meta8[2];
-  __shared__ GroupMeta<4, 16> meta4[2];
   __shared__ unsigned long long next;
   for (;;) {
     if (threadIdx.x == 0) next = atomicAdd(counter, 1ull);
@@ -934,10 +935,7 @@ __global__ __launch_bounds__(kThreads, 2) void demod_interp_batch_kernel(const B
     const WuDev w = ents[lo].w;
     const int W = ents[lo].seg;
     const int64_t local = tile - ents[lo].tile_begin;
-    if (ents[lo].nfd == 8)
-      interp_tile<8, 16, 4, kThreads, C16>(w, W, local, 0, w.n_sft, cbuf0, cbuf1, meta8);
-    else
-      interp_tile<4, 16, 4, kThreads, C16>(w, W, local, 0, w.n_sft, cbuf0, cbuf1, meta4);
+    interp_tile<NFD, 16, 4, kThreads, C16>(w, W, local, 0, w.n_sft, cbuf0, cbuf1, meta);
     __syncthreads();                                 // LDS free for the next tile
   }
 }
@@ -1038,29 +1036,41 @@ int64_t interp_tiles(const WuDev& w, int nfd) {
   return ((w.n_f + kThreads - 1) / kThreads) * ((w.n_fd + nfd - 1) / nfd) * w.n_sky;
 }
 
-int interp_batch_grid(bool c16) {
-  int dev = 0, cus = 0, per_cu = 0;
-  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-    cus = 256;
-  const hipError_t e = c16 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, demod_interp_batch_kernel<true>,
-                                                                          kThreads, 0)
-                           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, demod_interp_batch_kernel<false>,
-                                                                          kThreads, 0);
-  if (e != hipSuccess || per_cu < 1) per_cu = 1;
+template <int NFD, bool C16>
+static int batch_grid_t(int cus) {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, demod_interp_batch_kernel<NFD, C16>, kThreads, 0) !=
+          hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
   return per_cu * cus;
 }
 
+int interp_batch_grid(bool c16, int nfd) {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    cus = 256;
+  if (nfd == 8) return c16 ? batch_grid_t<8, true>(cus) : batch_grid_t<8, false>(cus);
+  return c16 ? batch_grid_t<4, true>(cus) : batch_grid_t<4, false>(cus);
+}
+
 hipError_t launch_interp_batch(const BatchEntry* ents_dev, int n_ent, int64_t total_tiles,
-                               unsigned long long* counter, int grid, bool c16, hipStream_t st) {
+                               unsigned long long* counter, int grid, bool c16, int nfd, hipStream_t st) {
   if (n_ent <= 0 || total_tiles <= 0) return hipSuccess;
   hipError_t e = launch_fill_int((int*)counter, 0, 2, st);   // kernel, not memset: safe under capture
   if (e != hipSuccess) return e;
-  if (c16)
-    hipLaunchKernelGGL(demod_interp_batch_kernel<true>, dim3((unsigned)grid), dim3(kThreads), 0, st, ents_dev, n_ent,
-                       total_tiles, counter);
-  else
-    hipLaunchKernelGGL(demod_interp_batch_kernel<false>, dim3((unsigned)grid), dim3(kThreads), 0, st, ents_dev,
-                       n_ent, total_tiles, counter);
+  const dim3 g((unsigned)grid), b(kThreads);
+  if (nfd == 8) {
+    if (c16)
+      hipLaunchKernelGGL((demod_interp_batch_kernel<8, true>), g, b, 0, st, ents_dev, n_ent, total_tiles, counter);
+    else
+      hipLaunchKernelGGL((demod_interp_batch_kernel<8, false>), g, b, 0, st, ents_dev, n_ent, total_tiles, counter);
+  } else {
+    if (c16)
+      hipLaunchKernelGGL((demod_interp_batch_kernel<4, true>), g, b, 0, st, ents_dev, n_ent, total_tiles, counter);
+    else
+      hipLaunchKernelGGL((demod_interp_batch_kernel<4, false>), g, b, 0, st, ents_dev, n_ent, total_tiles, counter);
+  }
   return hipGetLastError();
 }
 

@@ -72,6 +72,28 @@ def test_batch_64_work_units_full_size(torch_cuda, oracle_lib):
         assert e.max() <= 1e-4, (k, e.max())
         assert outs[k].twoF[x.sky_index, x.fdot_index, x.f_index].item() > 0.4 * x.snr ** 2
     _say(f"  sampled max 2F error over 64 units: {worst:.2e}")
+    # the mixed-precision form (FP16 polynomial coefficients) on the same inputs
+    with _plan_for(ws, coef="f16") as p:
+        p.batch_compute(devs, outs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        p.batch_compute(devs, outs)
+        torch.cuda.synchronize()
+        el16 = time.perf_counter() - t0
+    _say(f"  FP16 coefficients: batched call {el16 * 1e3:.0f} ms -> {pairs / el16:.3e} template*SFT/s "
+         f"({el / el16:.2f}x the plain form)")
+    worst = 0.0
+    for k in range(0, 64, 9):
+        w = ws[k]
+        x = w.injections[0]
+        j = np.arange(0, w.n_f, 16)
+        s_, i_, j_ = np.meshgrid([x.sky_index], np.arange(w.n_fd), j, indexing="ij")
+        s_, i_, j_ = (a.ravel().astype(np.int32) for a in (s_, i_, j_))
+        ref = oracle_lib.fstat(w, (s_, i_, j_))["twoF"]
+        got = outs[k].twoF[x.sky_index].cpu().numpy()[i_, j_].astype(np.float64)
+        worst = max(worst, twoF_error(got, ref).max())
+    _say(f"  FP16 coefficients: sampled max 2F error {worst:.2e}")
+    assert worst <= 5e-3
 
 
 def test_batch_256_work_units_bf16_full_size(torch_cuda, oracle_lib):
@@ -101,4 +123,23 @@ def test_batch_256_work_units_bf16_full_size(torch_cuda, oracle_lib):
         e = twoF_error(got, ref)
         _say(f"  unit {k}: {w.n_sft} SFTs x {w.n_bins} bins, sampled max 2F error {e.max():.2e}")
         assert e.max() <= 1e-4, (k, e.max())
+        del vals
+    # the mixed-precision form: BF16 storage and FP16 polynomial coefficients
+    with _plan_for(ws, storage="bf16", coef="f16") as p:
+        t0 = time.perf_counter()
+        p.batch_compute(devs, outs)
+        torch.cuda.synchronize()
+        el16 = time.perf_counter() - t0
+    _say(f"  FP16 coefficients: batched call {el16:.1f} s -> {pairs / el16:.3e} template*SFT/s "
+         f"({el / el16:.2f}x the BF16-storage form)")
+    for k in (0, 255):
+        w = ws[k]
+        vals = host_values(devs[k], "bf16")
+        j = np.arange(0, w.n_f, 8)
+        s_, i_, j_ = np.meshgrid([0], np.arange(w.n_fd), j, indexing="ij")
+        s_, i_, j_ = (a.ravel().astype(np.int32) for a in (s_, i_, j_))
+        ref = oracle_lib.fstat(w, (s_, i_, j_), sft=vals)["twoF"]
+        e = twoF_error(outs[k].twoF[0].cpu().numpy()[i_, j_].astype(np.float64), ref)
+        _say(f"  FP16 coefficients, unit {k}: sampled max 2F error {e.max():.2e}")
+        assert e.max() <= 5e-3, (k, e.max())
         del vals
