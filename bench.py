@@ -109,6 +109,8 @@ def main():
     ap.add_argument("--compare-direct", type=int, default=2,
                     help="also time this many steps of the direct kernel on complex64 storage")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--toplist", type=int, default=1000,
+                    help="also time the plain form writing only a top-K toplist above 2F = 20 (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (HBM counter calibration)")
@@ -188,6 +190,25 @@ def main():
         print(f"[bench] direct c64: {kernels['direct']}", file=sys.stderr, flush=True)
         del wu, out
         torch.cuda.empty_cache()
+    toplist = None
+    if args.toplist > 0:
+        wu, _ = to_device(w, "c64")
+        out = alloc_output(w, top_k=args.toplist, threshold=20.0, full=False)
+        with P.Plan(max_sft=w.n_sft, max_bins=w.n_bins, max_sky=w.n_sky, max_fd=w.n_fd, max_f=w.n_f,
+                    max_dterms=w.dterms, kernel=args.kernel) as plan:
+            plan.compute(wu, out)
+            torch.cuda.synchronize()
+            t_start = time.perf_counter()
+            for _ in range(2):
+                plan.compute(wu, out)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t_start
+        n_above = int(out.n_above.cpu().item())
+        toplist = {"top_k": args.toplist, "threshold": 20.0, "n_above": n_above, "ms_per_step": 1e3 * el / 2,
+                   "value": 2 * pairs / el, "full_2F_written": False}
+        print(f"[bench] toplist: {toplist}", file=sys.stderr, flush=True)
+        del wu, out
+        torch.cuda.empty_cache()
     main_form = forms[0]
     r = results[main_form]
     slots = slots_per_pair(kernel, w.dterms) * pairs
@@ -213,6 +234,7 @@ def main():
                       "vs_plain": v["value"] / results[main_form]["value"]}
                   for k, v in results.items()},
         "kernels": kernels,
+        "toplist": toplist,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12, "unit": "TOP/s",
                      "frac": achieved / PEAK_SLOTS, "traffic": measured_traffic(f"demod_{kernel}", "config1"),
                      "kernel": f"demod_{kernel}", "slots_per_pair": slots_per_pair(kernel, w.dterms),

@@ -94,6 +94,8 @@ typedef struct fstat_desc {
   int32_t kernel;      /* FSTAT_KERNEL_* */
   int32_t flags;       /* FSTAT_FLAG_* */
   int32_t device;      /* HIP device ordinal, or -1 for the current device */
+  int64_t max_cands;   /* toplist: capacity of the per-work-unit buffer of templates above the
+                          threshold, rounded up to a power of two (0: 65536; at most 2^24) */
 } fstat_desc;
 
 /* One work unit (all pointers are device pointers, caller-owned). */
@@ -120,11 +122,33 @@ typedef struct fstat_wu {
   int32_t dterms;             /* D: 2D bins per SFT, 1 <= D <= max_dterms */
 } fstat_wu;
 
-/* Outputs, [n_sky][n_fd][n_f] with frequency fastest (device pointers). */
+/* One toplist entry: 2F and the template's sky, spindown and frequency
+ * indices (all -1 past the last template that passed the threshold). */
+typedef struct fstat_cand {
+  float twoF;
+  int32_t sky, fdot, f;
+} fstat_cand;
+
+/* Outputs, [n_sky][n_fd][n_f] with frequency fastest (device pointers).
+ *
+ * Toplist (the step after the demodulation, as the search client keeps only
+ * the strongest candidates of a work unit for the next stage): with top_k > 0
+ * the call also writes to `top` the top_k templates of largest 2F among
+ * those with 2F >= threshold, by 2F descending (equal 2F: smaller linear
+ * template index (sky * n_fd + fdot) * n_f + f first), and to *n_above the
+ * number of templates with 2F >= threshold.  The 2F values are the ones the
+ * full output would hold.  If *n_above exceeds the plan's max_cands, the
+ * buffer overflowed and `top` holds the best of only max_cands of them: the
+ * caller should raise the threshold or max_cands.  twoF may then be NULL, so
+ * that the full 2F array is not written at all. */
 typedef struct fstat_out {
-  float* twoF;                /* required */
+  float* twoF;                /* [n_sky][n_fd][n_f]; required unless top_k > 0 */
   float* fa;                  /* optional complex (re, im) pairs, or NULL */
   float* fb;                  /* optional complex (re, im) pairs, or NULL */
+  int32_t top_k;              /* toplist length, 0 for none; at most max_cands */
+  float threshold;            /* toplist: 2F threshold */
+  fstat_cand* top;            /* toplist: [top_k] */
+  unsigned long long* n_above;/* toplist: one counter */
 } fstat_out;
 
 typedef struct fstat_plan fstat_plan;

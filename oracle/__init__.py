@@ -162,3 +162,15 @@ def window_weights(kappa: float, dterms: int) -> np.ndarray:
     out = np.empty(2 * dterms, dtype=np.float64)
     _load().oracle_window_weights(float(kappa), int(dterms), _p(out))
     return out
+
+
+def toplist(twoF, threshold: float, k: int):
+    """Toplist of a work unit from its 2F over all templates, given in linear
+    template order ((sky * n_fd + fdot) * n_f + f): the indices of the k
+    largest 2F among those >= threshold, largest first, equal 2F by smaller
+    index first; and the number of templates >= threshold.  A plain
+    selection by full sort."""
+    v = np.asarray(twoF, dtype=np.float64).ravel()
+    idx = np.nonzero(v >= threshold)[0]
+    order = np.lexsort((idx, -v[idx]))          # primary key -2F, then index
+    return idx[order[:k]], len(idx)

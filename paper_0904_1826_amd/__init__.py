@@ -56,7 +56,7 @@ class fstat_desc(ctypes.Structure):
     _fields_ = [("max_sft", ctypes.c_int64), ("max_bins", ctypes.c_int64), ("max_sky", ctypes.c_int64),
                 ("max_fd", ctypes.c_int64), ("max_f", ctypes.c_int64), ("max_dterms", ctypes.c_int32),
                 ("storage", ctypes.c_int32), ("phase_mode", ctypes.c_int32), ("kernel", ctypes.c_int32),
-                ("flags", ctypes.c_int32), ("device", ctypes.c_int32)]
+                ("flags", ctypes.c_int32), ("device", ctypes.c_int32), ("max_cands", ctypes.c_int64)]
 
 
 class fstat_wu(ctypes.Structure):
@@ -70,7 +70,9 @@ class fstat_wu(ctypes.Structure):
 
 
 class fstat_out(ctypes.Structure):
-    _fields_ = [("twoF", ctypes.c_void_p), ("fa", ctypes.c_void_p), ("fb", ctypes.c_void_p)]
+    _fields_ = [("twoF", ctypes.c_void_p), ("fa", ctypes.c_void_p), ("fb", ctypes.c_void_p),
+                ("top_k", ctypes.c_int32), ("threshold", ctypes.c_float), ("top", ctypes.c_void_p),
+                ("n_above", ctypes.c_void_p)]
 
 
 _lib = None
@@ -156,9 +158,16 @@ class WorkUnit:
 
 @dataclasses.dataclass
 class Output:
+    """Device outputs.  For a toplist set top_k > 0, threshold, top (int32
+    tensor [top_k, 4]: 2F as float bits, sky, fdot, f) and n_above (int64
+    tensor [1]); twoF may then be None."""
     twoF: object
     fa: object = None
     fb: object = None
+    top_k: int = 0
+    threshold: float = 0.0
+    top: object = None
+    n_above: object = None
 
 
 def _wu_struct(w) -> fstat_wu:
@@ -169,7 +178,19 @@ def _wu_struct(w) -> fstat_wu:
 
 
 def _out_struct(o) -> fstat_out:
-    return fstat_out(_ptr(o.twoF), _ptr(getattr(o, "fa", None)), _ptr(getattr(o, "fb", None)))
+    return fstat_out(_ptr(o.twoF), _ptr(getattr(o, "fa", None)), _ptr(getattr(o, "fb", None)),
+                     int(getattr(o, "top_k", 0)), float(getattr(o, "threshold", 0.0)),
+                     _ptr(getattr(o, "top", None)), _ptr(getattr(o, "n_above", None)))
+
+
+def toplist(o):
+    """Host copy of an Output's toplist: (twoF float32, sky, fdot, f) numpy
+    arrays cut at min(n_above, top_k), and n_above."""
+    import numpy as np
+    t = o.top.cpu().numpy().reshape(-1, 4)
+    n_above = int(o.n_above.cpu().numpy().reshape(-1)[0])
+    n = min(n_above, t.shape[0])
+    return (t[:n, 0].view(np.float32).copy(), t[:n, 1].copy(), t[:n, 2].copy(), t[:n, 3].copy(), n_above)
 
 
 def fstat_strerror(code: int) -> str:
@@ -187,7 +208,7 @@ def _check(plan, rc: int):
 
 
 def fstat_plan_create(*, max_sft, max_bins, max_sky, max_fd, max_f, max_dterms=16, storage="c64", phase="fp64",
-                      kernel="auto", coef="f32", flags=0, device=-1):
+                      kernel="auto", coef="f32", flags=0, device=-1, max_cands=0):
     """coef="f16" selects the mixed-precision form of the interp kernel
     (FP16 window-polynomial coefficients, FSTAT_FLAG_COEF16)."""
     lib = load_library()
@@ -197,7 +218,7 @@ def fstat_plan_create(*, max_sft, max_bins, max_sky, max_fd, max_f, max_dterms=1
         flags |= FSTAT_FLAG_COEF16
     d = fstat_desc(int(max_sft), int(max_bins), int(max_sky), int(max_fd), int(max_f), int(max_dterms),
                    STORAGE.get(storage, storage), PHASES.get(phase, phase), KERNELS.get(kernel, kernel), int(flags),
-                   int(device))
+                   int(device), int(max_cands))
     h = ctypes.c_void_p()
     rc = lib.fstat_plan_create(ctypes.byref(h), ctypes.byref(d))
     _check(None, rc)

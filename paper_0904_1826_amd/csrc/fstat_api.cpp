@@ -41,6 +41,17 @@ struct fstat_plan {
   std::map<int, double> csum;              // per Dterms: max_p sum_m |t[m][p]|
   void* cexp = nullptr;                    // FP16 coefficient form: per-SFT exponents
   size_t cexp_bytes = 0;
+  // toplist: candidate capacity per work unit (power of two), the single-unit
+  // buffer and counter, and the batched ones (one segment per work unit)
+  int64_t cand_cap = 0;
+  void* cand = nullptr;
+  size_t cand_bytes = 0;
+  void* cand_count = nullptr;
+  size_t cand_count_bytes = 0;
+  void* bcand = nullptr;
+  size_t bcand_bytes = 0;
+  void* bcount = nullptr;
+  size_t bcount_bytes = 0;
   // timing
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   hipStream_t ev_stream = nullptr;
@@ -129,7 +140,14 @@ int validate_wu(fstat_plan* p, const fstat_wu* w, const fstat_out* o, int idx) {
     return set_err(p, FSTAT_E_ARG, "%snull input array", tag);
   if (d.storage != FSTAT_STORAGE_C64 && !w->sft_scale)
     return set_err(p, FSTAT_E_ARG, "%s16-bit storage needs sft_scale", tag);
-  if (!o->twoF) return set_err(p, FSTAT_E_ARG, "%snull twoF output", tag);
+  if (o->top_k < 0) return set_err(p, FSTAT_E_ARG, "%snegative top_k", tag);
+  if (!o->twoF && o->top_k == 0) return set_err(p, FSTAT_E_ARG, "%snull twoF output and no toplist", tag);
+  if (o->top_k > 0 && (!o->top || !o->n_above)) return set_err(p, FSTAT_E_ARG, "%stoplist needs top and n_above", tag);
+  if (o->top_k > p->cand_cap)
+    return set_err(p, FSTAT_E_SIZE, "%stop_k %d exceeds the candidate capacity %lld", tag, o->top_k,
+                   (long long)p->cand_cap);
+  if (o->top_k > 0 && !std::isfinite(o->threshold))
+    return set_err(p, FSTAT_E_ARG, "%snon-finite toplist threshold", tag);
   if (w->n_det < 1) return set_err(p, FSTAT_E_ARG, "%sn_det < 1", tag);
   if (w->dterms < 1 || w->dterms > d.max_dterms) return set_err(p, FSTAT_E_ARG, "%sdterms %d outside [1, %d]", tag, w->dterms, d.max_dterms);
   if (w->n_sft < 1 || w->n_bins < 1 || w->n_sky < 1 || w->n_f < 1 || w->n_fd < 1)
@@ -171,6 +189,21 @@ WuDev make_dev(const fstat_plan* p, const fstat_wu* w, const fstat_out* o) {
   v.csum = is != p->csum.end() ? is->second : 0.0;
   v.coef16 = (p->d.flags & FSTAT_FLAG_COEF16) ? 1 : 0;
   v.cexp = (int32_t*)p->cexp;
+  v.cand = nullptr;
+  v.cand_count = nullptr;
+  v.cand_cap = p->cand_cap;
+  v.top_k = 0;
+  v.top = nullptr;
+  v.n_above = nullptr;
+  v.threshold = 0.f;
+  if (o && o->top_k > 0) {
+    v.cand = (uint4*)p->cand;
+    v.cand_count = (unsigned long long*)p->cand_count;
+    v.top_k = o->top_k;
+    v.top = (int4*)o->top;
+    v.n_above = o->n_above;
+    v.threshold = o->threshold;
+  }
   v.n_sft = w->n_sft;
   v.n_bins = w->n_bins;
   v.k_first = w->k_first;
@@ -318,6 +351,13 @@ Tile pick_tile(const fstat_plan* p, const fstat_wu* w) {
   return t;
 }
 
+int ensure_toplist(fstat_plan* p, const fstat_out* o) {
+  if (!o || o->top_k <= 0) return FSTAT_OK;
+  int rc = dev_alloc(p, &p->cand, &p->cand_bytes, (size_t)p->cand_cap * sizeof(uint4), "toplist candidates");
+  if (rc) return rc;
+  return dev_alloc(p, &p->cand_count, &p->cand_count_bytes, 64, "toplist counter");
+}
+
 int ensure_scratch(fstat_plan* p, const fstat_wu* w) {
   int rc = dev_alloc(p, &p->geo, &p->geo_bytes, (size_t)w->n_sky * w->n_sft * sizeof(double2), "geometry scratch");
   if (rc) return rc;
@@ -369,11 +409,16 @@ int run_demod(fstat_plan* p, const WuDev& v, const Tile& t, hipStream_t st) {
     int rc = check_launch(p, fstat::launch_coef(v, st), "coefficient kernel");
     if (rc) return rc;
   }
+  if (v.cand) {
+    int rc = check_launch(p, fstat::launch_fill_int((int*)v.cand_count, 0, 2, st), "toplist counter reset");
+    if (rc) return rc;
+  }
   (void)hipEventRecord(p->ev0, st);
   int rc = check_launch(p, fstat::launch_demod(v, t, kernel, st), "demodulation kernel");
   (void)hipEventRecord(p->ev1, st);
   p->ev_stream = st;
   p->timed = (rc == FSTAT_OK);
+  if (rc == FSTAT_OK && v.cand) rc = check_launch(p, fstat::launch_top_select(v, st), "toplist selection");
   return rc;
 }
 
@@ -487,6 +532,15 @@ int batch_interp(fstat_plan* p, const fstat_wu* wus, int n, const fstat_out* out
     rc = dev_alloc(p, (void**)&p->counter, &have, 64, "tile counter");
     if (rc) return rc;
   }
+  bool any_top = false;
+  for (int k = 0; k < n; ++k) any_top = any_top || outs[k].top_k > 0;
+  if (any_top) {   // one candidate segment and counter per work unit
+    rc = dev_alloc(p, &p->bcand, &p->bcand_bytes, (size_t)n * p->cand_cap * sizeof(uint4), "toplist candidates");
+    if (rc) return rc;
+    rc = dev_alloc(p, &p->bcount, &p->bcount_bytes, align256((size_t)n * sizeof(unsigned long long)),
+                   "toplist counters");
+    if (rc) return rc;
+  }
   if (!p->batch_grid) {
     p->batch_grid = fstat::interp_batch_grid(coef16(p), 8);
     p->batch_grid4 = fstat::interp_batch_grid(coef16(p), 4);
@@ -514,7 +568,9 @@ int batch_interp(fstat_plan* p, const fstat_wu* wus, int n, const fstat_out* out
     });
     fstat::BatchEntry* eh = p->ents_h + g.first;
     int64_t tiles = 0, blocks = 0, sfts = 0, tiles8 = 0;
-    int m8 = 0;
+    int m8 = 0, max_top_k = 0;
+    uint4* gcand = any_top ? (uint4*)p->bcand + (size_t)g.first * p->cand_cap : nullptr;
+    unsigned long long* gcount = any_top ? (unsigned long long*)p->bcount + g.first : nullptr;
     for (size_t q = 0; q < order.size(); ++q) {
       const int k = order[q];
       if (nfd_of(k) == 8) m8 = (int)q + 1;
@@ -531,6 +587,14 @@ int batch_interp(fstat_plan* p, const fstat_wu* wus, int n, const fstat_out* out
       v.coef = (float4*)(base + sc.geo + sc.abcd);
       v.cexp = sc.cexp ? (int32_t*)(base + sc.geo + sc.abcd + sc.coef) : nullptr;
       v.acc = nullptr;
+      if (outs[k].top_k > 0) {                         // segment q of the group's candidates
+        v.cand = gcand + q * p->cand_cap;
+        v.cand_count = gcount + q;
+        max_top_k = outs[k].top_k > max_top_k ? outs[k].top_k : max_top_k;
+      } else {
+        v.cand = nullptr;
+        v.cand_count = nullptr;
+      }
       e.w = v;
       e.nfd = nfd_of(k);
       e.seg = interp_seg_tau(&wus[k], e.nfd, fstat::kThreads, coef16(p), status_tau(p->bstat_h[k]));
@@ -554,6 +618,10 @@ int batch_interp(fstat_plan* p, const fstat_wu* wus, int n, const fstat_out* out
     }
     const bool c16 = coef16(p);
     if (p->d.flags & FSTAT_FLAG_NO_GRAPH) {
+      if (max_top_k > 0) {
+        rc = check_launch(p, fstat::launch_fill_int((int*)gcount, 0, 2 * m, st), "toplist counter reset");
+        if (rc) return rc;
+      }
       if (c16) {
         rc = check_launch(p, fstat::launch_cexp_batch(ed, m, sfts, st), "coefficient exponent kernel");
         if (rc) return rc;
@@ -567,9 +635,13 @@ int batch_interp(fstat_plan* p, const fstat_wu* wus, int n, const fstat_out* out
                                                       st),
                         "batch kernel");
       if (rc) return rc;
+      rc = check_launch(p, fstat::launch_top_select_batch(ed, m, gcand, p->cand_cap, max_top_k, st),
+                        "toplist selection");
+      if (rc) return rc;
       continue;
     }
-    const std::vector<int64_t> sig = {(int64_t)(intptr_t)ed, m, m8, blocks, tiles8, tiles4, p->batch_grid, sfts};
+    const std::vector<int64_t> sig = {(int64_t)(intptr_t)ed, m,     m8,          blocks, tiles8,
+                                      tiles4,                p->batch_grid, sfts, max_top_k};
     auto it = p->graphs.find(sig);
     if (it == p->graphs.end()) {
       if (!p->cap_stream) {
@@ -578,12 +650,15 @@ int batch_interp(fstat_plan* p, const fstat_wu* wus, int n, const fstat_out* out
       }
       e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal);
       if (e != hipSuccess) return hip_err(p, e, "graph capture");
-      hipError_t e0 = c16 ? fstat::launch_cexp_batch(ed, m, sfts, p->cap_stream) : hipSuccess;
+      hipError_t e0 = max_top_k > 0 ? fstat::launch_fill_int((int*)gcount, 0, 2 * m, p->cap_stream) : hipSuccess;
+      if (e0 == hipSuccess && c16) e0 = fstat::launch_cexp_batch(ed, m, sfts, p->cap_stream);
       hipError_t e1 = e0 != hipSuccess ? e0 : fstat::launch_coef_batch(ed, m, blocks, c16, p->cap_stream);
       hipError_t e2 = fstat::launch_interp_batch(ed, m8, tiles8, p->counter, p->batch_grid, c16, 8, p->cap_stream);
       if (e2 == hipSuccess)
         e2 = fstat::launch_interp_batch(ed + m8, m - m8, tiles4, p->counter + 1, p->batch_grid4, c16, 4,
                                         p->cap_stream);
+      if (e2 == hipSuccess)
+        e2 = fstat::launch_top_select_batch(ed, m, gcand, p->cand_cap, max_top_k, p->cap_stream);
       hipGraph_t graph = nullptr;
       e = hipStreamEndCapture(p->cap_stream, &graph);
       if (e1 != hipSuccess || e2 != hipSuccess || e != hipSuccess) {
@@ -641,6 +716,12 @@ int fstat_plan_create(fstat_plan** out, const fstat_desc* d) {
     return FSTAT_E_DEVICE;
   }
   p->cu_count = prop.multiProcessorCount;
+  if (d->max_cands < 0 || d->max_cands > ((int64_t)1 << 24)) {
+    delete p;
+    return FSTAT_E_ARG;
+  }
+  p->cand_cap = 1;
+  while (p->cand_cap < (d->max_cands > 0 ? d->max_cands : 65536)) p->cand_cap <<= 1;
   if ((p->d.phase_mode == FSTAT_PHASE_SPLIT_FP32 || (p->d.flags & FSTAT_FLAG_COEF16)) &&
       p->d.kernel == FSTAT_KERNEL_DIRECT) {
     // the split phase form and the FP16 coefficients belong to the interpolated kernel only
@@ -674,6 +755,11 @@ void fstat_plan_destroy(fstat_plan* p) {
   if (p->counter) (void)hipFree(p->counter);
   if (p->coef) (void)hipFree(p->coef);
   if (p->acc) (void)hipFree(p->acc);
+  if (p->cexp) (void)hipFree(p->cexp);
+  if (p->cand) (void)hipFree(p->cand);
+  if (p->cand_count) (void)hipFree(p->cand_count);
+  if (p->bcand) (void)hipFree(p->bcand);
+  if (p->bcount) (void)hipFree(p->bcount);
   for (auto& kv : p->ctab) (void)hipFree(kv.second);
   if (p->status_d) (void)hipFree(p->status_d);
   if (p->status_h) (void)hipHostFree(p->status_h);
@@ -692,6 +778,8 @@ int fstat_compute(fstat_plan* p, const fstat_wu* wu, const fstat_out* out, void*
   if (hipSetDevice(p->device) != hipSuccess) return set_err(p, FSTAT_E_DEVICE, "hipSetDevice failed");
   hipStream_t st = (hipStream_t)stream;
   rc = ensure_scratch(p, wu);
+  if (rc) return rc;
+  rc = ensure_toplist(p, out);
   if (rc) return rc;
   WuDev v = make_dev(p, wu, out);
   rc = run_geometry(p, v, st, -1);
@@ -715,6 +803,8 @@ int fstat_batch_compute(fstat_plan* p, const fstat_wu* wus, int32_t n_wu, const 
   // direct kernel: one work unit after the other
   for (int k = 0; k < n_wu; ++k) {
     int rc = ensure_scratch(p, &wus[k]);
+    if (rc) return rc;
+    rc = ensure_toplist(p, &outs[k]);
     if (rc) return rc;
     WuDev v = make_dev(p, &wus[k], &outs[k]);
     rc = run_geometry(p, v, st, k);
@@ -776,6 +866,8 @@ int fstat_autotune(fstat_plan* p, const fstat_wu* wu, const fstat_out* out, void
   if (hipSetDevice(p->device) != hipSuccess) return set_err(p, FSTAT_E_DEVICE, "hipSetDevice failed");
   hipStream_t st = (hipStream_t)stream;
   rc = ensure_scratch(p, wu);
+  if (rc) return rc;
+  rc = ensure_toplist(p, out);
   if (rc) return rc;
   WuDev v = make_dev(p, wu, out);
   rc = run_geometry(p, v, st, -1);

@@ -27,6 +27,15 @@ struct WuDev {
   int32_t coef16;
   const double* ctab;      // interp kernel: [2D][kCoef] polynomial coefficients of sinc(kappa+m)
   float4* acc;             // interp kernel scratch: running (Fa, Fb) per template between SFT blocks
+  // toplist: templates with 2F >= threshold are appended to cand (2F bits,
+  // 0, linear index lo, hi) through the counter cand_count; NULL: no toplist
+  uint4* cand;
+  unsigned long long* cand_count;
+  int64_t cand_cap;        // power of two
+  float threshold;
+  int32_t top_k;
+  int4* top;               // [top_k] (2F bits, sky, fdot, f)
+  unsigned long long* n_above;
   int64_t n_sft, n_bins, k_first, n_sky, n_f, n_fd;
   double t_sft, f0, df, fdot0, dfdot, t_ref;
   int32_t dterms;
@@ -112,6 +121,11 @@ hipError_t launch_bins(const WuDev& w, int64_t n, const int32_t* i_sky, const in
 size_t demod_lds_bytes(const WuDev& w, const Tile& t, int kernel);
 int interp_max_seg(int threads, bool c16);
 hipError_t launch_cexp(const WuDev& w, hipStream_t s);
+// Toplist selection after the demodulation: sort each work unit's candidate
+// segment (cap entries, cap a power of two) and write top and n_above.
+hipError_t launch_top_select(const WuDev& w, hipStream_t s);
+hipError_t launch_top_select_batch(const BatchEntry* ents_dev, int n_ent, uint4* cand, int64_t cap, int max_top_k,
+                                   hipStream_t s);
 hipError_t launch_cexp_batch(const BatchEntry* ents_dev, int n_ent, int64_t total_sfts, hipStream_t s);
 
 }  // namespace fstat

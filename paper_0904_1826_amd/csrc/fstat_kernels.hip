@@ -90,6 +90,27 @@ __device__ __forceinline__ float2 load_bin(const WuDev& w, int64_t al, int64_t c
 }
 
 // ------------------------------------------------------------- geometry
+// ------------------------------------------------------ toplist append
+// Templates with 2F >= threshold are appended to the work unit's candidate
+// buffer by the epilogue: one atomic per wave reserves the slots of its
+// qualifying lanes.  Slots beyond the capacity are dropped (the counter keeps
+// counting, which the caller sees as n_above > capacity).
+__device__ __forceinline__ void cand_push(const WuDev& w, float tf, int64_t o) {
+  const bool q = tf >= w.threshold;                      // NaN never qualifies
+  const unsigned long long mask = __ballot(q);
+  if (mask == 0ull) return;
+  const int lane = (int)__lane_id();
+  const int leader = __ffsll((long long)mask) - 1;
+  unsigned long long base = 0ull;
+  if (lane == leader) base = atomicAdd(w.cand_count, (unsigned long long)__popcll(mask));
+  base = __shfl(base, leader, 64);
+  if (q) {
+    const unsigned long long c = base + (unsigned long long)__popcll(mask & ((1ull << lane) - 1ull));
+    if (c < (unsigned long long)w.cand_cap)
+      w.cand[c] = make_uint4(__float_as_uint(tf), 0u, (uint32_t)o, (uint32_t)((uint64_t)o >> 32));
+  }
+}
+
 __device__ __forceinline__ double warp_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
@@ -365,7 +386,8 @@ __global__ __launch_bounds__(kThreads) void demod_direct_kernel(WuDev w) {
     const double fa2 = ar * ar + ai * ai, fb2 = br * br + bi * bi, re = ar * br + ai * bi;
     const double two_f = 2.0 * (abcd.y * fa2 + abcd.x * fb2 - 2.0 * abcd.z * re) / abcd.w;
     const int64_t o = (s * w.n_fd + i) * w.n_f + j;
-    w.twoF[o] = (float)two_f;
+    if (w.twoF) w.twoF[o] = (float)two_f;
+    if (w.cand) cand_push(w, (float)two_f, o);
     if (w.fa) w.fa[o] = make_float2(far[r], fai[r]);
     if (w.fb) w.fb[o] = make_float2(fbr[r], fbi[r]);
   }
@@ -885,7 +907,8 @@ __device__ __forceinline__ void interp_tile(const WuDev& w, int W, int64_t tile,
     const double ar = far[r], ai = fai[r], br = fbr[r], bi = fbi[r];
     const double fa2 = ar * ar + ai * ai, fb2 = br * br + bi * bi, re = ar * br + ai * bi;
     const double two_f = 2.0 * (abcd.y * fa2 + abcd.x * fb2 - 2.0 * abcd.z * re) / abcd.w;
-    w.twoF[o] = (float)two_f;
+    if (w.twoF) w.twoF[o] = (float)two_f;
+    if (w.cand) cand_push(w, (float)two_f, o);
     if (w.fa) w.fa[o] = make_float2(far[r], fai[r]);
     if (w.fb) w.fb[o] = make_float2(fbr[r], fbi[r]);
   }
@@ -938,6 +961,77 @@ __global__ __launch_bounds__(kThreads, (C16 && NFD == 8) ? 4 : 3) void demod_int
     interp_tile<NFD, 16, 4, kThreads, C16>(w, W, local, 0, w.n_sft, cbuf0, cbuf1, meta);
     __syncthreads();                                 // LDS free for the next tile
   }
+}
+
+// ------------------------------------------------------------ toplist
+// Ranking of candidates: larger 2F first, then smaller linear template index.
+__device__ __forceinline__ bool cand_better(uint4 x, uint4 y) {
+  const float fx = __uint_as_float(x.x), fy = __uint_as_float(y.x);
+  if (fx != fy) return fx > fy;
+  return (((uint64_t)x.w << 32) | x.z) < (((uint64_t)y.w << 32) | y.z);
+}
+
+// Segment q of the candidate arena belongs to work unit q: its counter and
+// output pointers, read from the work-unit table (batched) or the one device
+// view (single unit).
+struct SingleSeg {
+  WuDev w;
+  __device__ const WuDev& unit(int) const { return w; }
+};
+struct BatchSeg {
+  const BatchEntry* ents;
+  __device__ const WuDev& unit(int q) const { return ents[q].w; }
+};
+
+// Slots past a segment's count become sentinels that rank last.
+template <class Seg>
+__global__ __launch_bounds__(256) void cand_pad_kernel(Seg seg, uint4* cand, int64_t cap, int64_t total) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= total) return;
+  const int q = (int)(i / cap);
+  const WuDev& w = seg.unit(q);
+  const unsigned long long cnt = w.cand_count ? *w.cand_count : 0ull;
+  const int64_t n = cnt < (unsigned long long)cap ? (int64_t)cnt : cap;
+  if ((i & (cap - 1)) >= n) cand[i] = make_uint4(__float_as_uint(-__builtin_huge_valf()), 0u, ~0u, ~0u);
+}
+
+// One compare-exchange pass of a bitonic sort of every cap-long segment
+// (pass (k, j), j < k <= cap): best-ranked first when k reaches cap.
+__global__ __launch_bounds__(256) void cand_sort_pass_kernel(uint4* cand, int64_t total, int64_t cap, int64_t k,
+                                                             int64_t j) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= total) return;
+  const int64_t p = i ^ j;
+  if (p <= i) return;
+  const bool first_best = ((i & (cap - 1)) & k) == 0;
+  const uint4 a = cand[i], b = cand[p];
+  if (first_best ? cand_better(b, a) : cand_better(a, b)) {
+    cand[i] = b;
+    cand[p] = a;
+  }
+}
+
+// The first top_k entries of each sorted segment, decoded to (2F, sky, fdot,
+// f); entries past the count get indices -1.  Also publishes n_above.
+template <class Seg>
+__global__ __launch_bounds__(256) void top_write_kernel(Seg seg, const uint4* cand, int64_t cap) {
+  const int q = blockIdx.y;
+  const WuDev& w = seg.unit(q);
+  if (!w.cand || w.top_k <= 0) return;
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const unsigned long long cnt = *w.cand_count;
+  if (t == 0) *w.n_above = cnt;
+  if (t >= w.top_k) return;
+  const int64_t n = cnt < (unsigned long long)cap ? (int64_t)cnt : cap;
+  if (t >= n) {
+    w.top[t] = make_int4(0, -1, -1, -1);
+    return;
+  }
+  const uint4 c = cand[(int64_t)q * cap + t];
+  const int64_t o = (int64_t)(((uint64_t)c.w << 32) | c.z);
+  const int64_t per_sky = w.n_fd * w.n_f;
+  const int64_t s = o / per_sky, r = o - s * per_sky;
+  w.top[t] = make_int4((int)c.x, (int)s, (int)(r / w.n_f), (int)(r % w.n_f));
 }
 
 // ------------------------------------------------------------ bin probe
@@ -1141,6 +1235,37 @@ static hipError_t launch_interp(const WuDev& w, const Tile& t, hipStream_t st) {
     case 1: return launch_interp_t<1, 16, 3, 4, kThreads, false>(w, t, st);
     default: return hipErrorInvalidValue;
   }
+}
+
+template <class Seg>
+static hipError_t top_select(const Seg& seg, int n_seg, uint4* cand, int64_t cap, int max_top_k, hipStream_t st) {
+  const int64_t total = (int64_t)n_seg * cap;
+  if (n_seg <= 0 || cap <= 0 || (cap & (cap - 1)) != 0 || total / 256 + 1 > 0x7fffffffLL)
+    return hipErrorInvalidConfiguration;
+  const dim3 grid((unsigned)((total + 255) / 256)), block(256);
+  hipLaunchKernelGGL(cand_pad_kernel<Seg>, grid, block, 0, st, seg, cand, cap, total);
+  hipError_t e = hipGetLastError();
+  for (int64_t k = 2; k <= cap && e == hipSuccess; k <<= 1)
+    for (int64_t j = k >> 1; j > 0 && e == hipSuccess; j >>= 1) {
+      hipLaunchKernelGGL(cand_sort_pass_kernel, grid, block, 0, st, cand, total, cap, k, j);
+      e = hipGetLastError();
+    }
+  if (e != hipSuccess) return e;
+  if (max_top_k <= 0) return hipSuccess;
+  hipLaunchKernelGGL(top_write_kernel<Seg>, dim3((unsigned)((max_top_k + 255) / 256), (unsigned)n_seg), block, 0, st,
+                     seg, (const uint4*)cand, cap);
+  return hipGetLastError();
+}
+
+hipError_t launch_top_select(const WuDev& w, hipStream_t st) {
+  if (!w.cand || w.top_k <= 0) return hipSuccess;
+  return top_select(SingleSeg{w}, 1, w.cand, w.cand_cap, w.top_k, st);
+}
+
+hipError_t launch_top_select_batch(const BatchEntry* ents_dev, int n_ent, uint4* cand, int64_t cap, int max_top_k,
+                                   hipStream_t st) {
+  if (max_top_k <= 0) return hipSuccess;
+  return top_select(BatchSeg{ents_dev}, n_ent, cand, cap, max_top_k, st);
 }
 
 template <int DT, int NF, int CH>

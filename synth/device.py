@@ -34,14 +34,19 @@ def to_device(w, storage: str = "c64", device: str = "cuda"):
     return wu, deq
 
 
-def alloc_output(w, device: str = "cuda", fafb: bool = False):
+def alloc_output(w, device: str = "cuda", fafb: bool = False, top_k: int = 0, threshold: float = 0.0,
+                 full: bool = True):
+    """Output buffers; with top_k > 0 also a toplist of that length (and,
+    with full=False, no full 2F array)."""
     import torch
     from paper_0904_1826_amd import Output
     shape = (w.n_sky, w.n_fd, w.n_f)
-    tw = torch.empty(shape, dtype=torch.float32, device=device)
+    tw = torch.empty(shape, dtype=torch.float32, device=device) if full else None
     fa = torch.empty(shape + (2,), dtype=torch.float32, device=device) if fafb else None
     fb = torch.empty(shape + (2,), dtype=torch.float32, device=device) if fafb else None
-    return Output(twoF=tw, fa=fa, fb=fb)
+    top = torch.empty((top_k, 4), dtype=torch.int32, device=device) if top_k > 0 else None
+    n_above = torch.empty(1, dtype=torch.int64, device=device) if top_k > 0 else None
+    return Output(twoF=tw, fa=fa, fb=fb, top_k=top_k, threshold=threshold, top=top, n_above=n_above)
 
 
 def draw_noise_16bit(w, storage: str = "bf16", seed: int = 0, device: str = "cuda"):

@@ -291,3 +291,31 @@ def test_band_error(oracle_lib):
     for cut in (replace(w, sft=w.sft[:, c0 + 1:c1], k_first=lo + 1), replace(w, sft=w.sft[:, c0:c1 - 1], k_first=lo)):
         with pytest.raises(ValueError, match="band"):
             oracle_lib.fstat(cut, (s, i, j))
+
+
+# ------------------------------------------------ P9: toplist selection ---
+def test_toplist_selection_definition():
+    """Threshold, order by 2F descending, ties by smaller index, truncation."""
+    import oracle
+    v = np.array([5.0, 7.0, 7.0, 3.0, 9.0, 4.0, 7.0])
+    idx, n = oracle.toplist(v, 4.0, 3)
+    assert n == 6                                   # 5, 7, 7, 9, 4, 7 are >= 4
+    assert list(idx) == [4, 1, 2]                   # 9, then the first two 7s by index
+    idx, n = oracle.toplist(v, 7.5, 10)
+    assert n == 1 and list(idx) == [4]              # fewer than k pass
+    idx, n = oracle.toplist(v, 100.0, 3)
+    assert n == 0 and len(idx) == 0
+
+
+def test_toplist_brute_force_random():
+    """Against a pairwise-comparison ranking on random arrays with ties."""
+    import oracle
+    rng = np.random.default_rng(11)
+    for _ in range(20):
+        v = rng.integers(0, 12, 40).astype(np.float64)
+        thr, k = float(rng.integers(0, 12)), int(rng.integers(1, 15))
+        idx, n = oracle.toplist(v, thr, k)
+        cand = [t for t in range(len(v)) if v[t] >= thr]
+        rank = {t: sum(1 for u in cand if v[u] > v[t] or (v[u] == v[t] and u < t)) for t in cand}
+        expect = sorted(cand, key=lambda t: rank[t])[:k]
+        assert n == len(cand) and list(idx) == expect
