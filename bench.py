@@ -231,7 +231,10 @@ def main():
                    "kernel": kernel, "templates": w.n_templates, "pairs_per_step": pairs},
         "forms": {k: {"value": v["value"], "ms_per_step": v["ms_per_step"], "kernel_ms": v["kernel_ms"],
                       "err_bound": v["err_bound"],
-                      "vs_plain": v["value"] / results[main_form]["value"]}
+                      "vs_plain": v["value"] / results[main_form]["value"],
+                      "roofline_frac": slots_per_pair(kernel, w.dterms) * pairs / (v["kernel_ms"] * 1e-3) / PEAK_SLOTS,
+                      "traffic": measured_traffic("demod_interp_coef16" if k.endswith("+coef16") else f"demod_{kernel}",
+                                                  "config1")}
                   for k, v in results.items()},
         "kernels": kernels,
         "toplist": toplist,
