@@ -174,3 +174,42 @@ def toplist(twoF, threshold: float, k: int):
     idx = np.nonzero(v >= threshold)[0]
     order = np.lexsort((idx, -v[idx]))          # primary key -2F, then index
     return idx[order[:k]], len(idx)
+
+
+class _Earth(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_double) for k in ("t0", "orbit_radius", "orbit_rate", "orbit_phase", "obliquity",
+                                               "earth_radius", "sidereal_rate", "sidereal_phase")]
+
+
+class _Site(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_double) for k in ("lat", "lon", "az_x", "az_y")]
+
+
+def detector_inputs(earth: dict, sites, t_mid, site_of_sft, sky):
+    """Detector positions r [n_sft, 3] (light-s), velocities v [n_sft, 3]
+    (units of c) and antenna-pattern factors a, b [n_sky, n_sft], all FP64,
+    from the orbit/rotation model `earth` (keys of _Earth), the sites
+    (lat, lon, az_x, az_y in radians), SFT midpoints and sky directions.  See
+    oracle_detector_inputs in fstat_oracle.c for the formulas."""
+    lib = _load()
+    if not hasattr(lib, "_det_ready"):
+        P = ctypes.c_void_p
+        lib.oracle_detector_inputs.argtypes = [ctypes.POINTER(_Earth), ctypes.c_int, P, ctypes.c_int, P, P,
+                                               ctypes.c_int, P, P, P, P, P]
+        lib.oracle_detector_inputs.restype = ctypes.c_int
+        lib._det_ready = True
+    e = _Earth(*[float(earth[k]) for k, _ in _Earth._fields_])
+    st = (_Site * len(sites))(*[_Site(*map(float, x)) for x in sites])
+    t = np.ascontiguousarray(t_mid, dtype=np.float64)
+    idx = np.ascontiguousarray(site_of_sft, dtype=np.int32)
+    n = np.ascontiguousarray(sky, dtype=np.float64).reshape(-1, 3)
+    pos = np.empty((len(t), 3))
+    vel = np.empty((len(t), 3))
+    a = np.empty((len(n), len(t)))
+    b = np.empty((len(n), len(t)))
+    ptr = lambda x: x.ctypes.data_as(ctypes.c_void_p)
+    rc = lib.oracle_detector_inputs(ctypes.byref(e), len(sites), ctypes.cast(st, ctypes.c_void_p), len(t), ptr(t),
+                                    ptr(idx), len(n), ptr(n), ptr(pos), ptr(vel), ptr(a), ptr(b))
+    if rc != OK:
+        raise ValueError(f"oracle_detector_inputs: code {rc}")
+    return pos, vel, a, b

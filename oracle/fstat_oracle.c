@@ -210,3 +210,95 @@ int oracle_fstat(const oracle_wu* w, int n_tmpl, const int* tsky, const int* tfd
   if (bad) *bad = err_t;
   return err_t >= 0 ? ORACLE_E_BAND : ORACLE_OK;
 }
+
+/*
+ * Detector inputs of the demodulation (the step before it: the paper notes
+ * that such per-SFT data are computed on the fly, Section 4): for each SFT
+ * the detector position r and velocity v in the solar-system frame
+ * (equatorial axes, light-seconds and units of c) and, for each sky direction
+ * n, the antenna-pattern factors a, b at the SFT midpoint.
+ *
+ * Model (plain definitions, one formula per line below):
+ *   orbit phase   phi_o = phi_o0 + W_o (t - t0); Earth centre on a circle of
+ *                 radius R_o in the ecliptic, tilted by the obliquity eps:
+ *                 r_o = R_o (cos phi_o, sin phi_o cos eps, sin phi_o sin eps)
+ *   local sidereal angle  th = lon + th0 + W_s (t - t0)
+ *   site on a sphere of radius R_e: r_s = R_e (cos lat cos th, cos lat sin th, sin lat)
+ *   r = r_o + r_s, v = dr/dt
+ *   local east  e = (-sin th, cos th, 0), north  N = (-sin lat cos th, -sin lat sin th, cos lat)
+ *   arm directions  u = cos az_x N + sin az_x e,  w = cos az_y N + sin az_y e
+ *   detector tensor D = (u u^T - w w^T) / 2
+ *   wave frame of n = (cos d cos al, cos d sin al, sin d):
+ *     X = (sin al, -cos al, 0),  Y = (-sin d cos al, -sin d sin al, cos d)
+ *     (at the poles al = 0)
+ *   a = X^T D X - Y^T D Y,  b = 2 X^T D Y   (plus and cross responses)
+ */
+typedef struct oracle_earth {
+  double t0, orbit_radius, orbit_rate, orbit_phase, obliquity, earth_radius, sidereal_rate, sidereal_phase;
+} oracle_earth;
+
+typedef struct oracle_site {
+  double lat, lon, az_x, az_y;
+} oracle_site;
+
+static void quad_form(const double D[3][3], const double* x, const double* y, double* out) {
+  double s = 0.0;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) s += x[i] * D[i][j] * y[j];
+  *out = s;
+}
+
+int oracle_detector_inputs(const oracle_earth* e, int n_sites, const oracle_site* sites, int n_sft,
+                           const double* t_mid, const int* site_of_sft, int n_sky, const double* sky,
+                           double* pos, double* vel, double* a, double* b) {
+  for (int al = 0; al < n_sft; ++al) {
+    const int si = site_of_sft[al];
+    if (si < 0 || si >= n_sites) return ORACLE_E_ARG;
+    const oracle_site* st = &sites[si];
+    const double dt = t_mid[al] - e->t0;
+    const double po = e->orbit_phase + e->orbit_rate * dt;
+    const double ce = cos(e->obliquity), se = sin(e->obliquity);
+    const double th = st->lon + e->sidereal_phase + e->sidereal_rate * dt;
+    const double cl = cos(st->lat), sl = sin(st->lat);
+    double r[3], v[3];
+    r[0] = e->orbit_radius * cos(po);
+    r[1] = e->orbit_radius * sin(po) * ce;
+    r[2] = e->orbit_radius * sin(po) * se;
+    v[0] = -e->orbit_radius * e->orbit_rate * sin(po);
+    v[1] = e->orbit_radius * e->orbit_rate * cos(po) * ce;
+    v[2] = e->orbit_radius * e->orbit_rate * cos(po) * se;
+    r[0] += e->earth_radius * cl * cos(th);
+    r[1] += e->earth_radius * cl * sin(th);
+    r[2] += e->earth_radius * sl;
+    v[0] += -e->earth_radius * e->sidereal_rate * cl * sin(th);
+    v[1] += e->earth_radius * e->sidereal_rate * cl * cos(th);
+    for (int c = 0; c < 3; ++c) {
+      pos[3 * al + c] = r[c];
+      vel[3 * al + c] = v[c];
+    }
+    const double east[3] = {-sin(th), cos(th), 0.0};
+    const double north[3] = {-sl * cos(th), -sl * sin(th), cl};
+    double u[3], w[3], D[3][3];
+    for (int c = 0; c < 3; ++c) {
+      u[c] = cos(st->az_x) * north[c] + sin(st->az_x) * east[c];
+      w[c] = cos(st->az_y) * north[c] + sin(st->az_y) * east[c];
+    }
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) D[i][j] = 0.5 * (u[i] * u[j] - w[i] * w[j]);
+    for (int s = 0; s < n_sky; ++s) {
+      const double* n = sky + 3 * s;
+      const double dl = asin(n[2] > 1.0 ? 1.0 : (n[2] < -1.0 ? -1.0 : n[2]));
+      const double rho = sqrt(n[0] * n[0] + n[1] * n[1]);
+      const double alpha = rho > 0.0 ? atan2(n[1], n[0]) : 0.0;
+      const double X[3] = {sin(alpha), -cos(alpha), 0.0};
+      const double Y[3] = {-sin(dl) * cos(alpha), -sin(dl) * sin(alpha), cos(dl)};
+      double xx, yy, xy;
+      quad_form(D, X, X, &xx);
+      quad_form(D, Y, Y, &yy);
+      quad_form(D, X, Y, &xy);
+      a[(size_t)s * n_sft + al] = xx - yy;
+      b[(size_t)s * n_sft + al] = 2.0 * xy;
+    }
+  }
+  return ORACLE_OK;
+}
