@@ -151,6 +151,25 @@ typedef struct fstat_out {
   unsigned long long* n_above;/* toplist: one counter */
 } fstat_out;
 
+/* Detector site on a spherical Earth: latitude, east longitude, and the
+ * azimuths of the two arms from local north towards east (radians). */
+typedef struct fstat_site {
+  double lat, lon, az_x, az_y;
+} fstat_site;
+
+/* Orbit and rotation model of fstat_detector_inputs: the Earth's centre on a
+ * circle of radius orbit_radius (light-s) in the ecliptic, tilted by
+ * `obliquity` from the equatorial axes, at phase orbit_phase + orbit_rate
+ * (t - t0); the site at earth_radius (light-s; 0 drops the diurnal term) with
+ * local sidereal angle lon + sidereal_phase + sidereal_rate (t - t0). */
+typedef struct fstat_earth {
+  double t0;
+  double orbit_radius, orbit_rate, orbit_phase, obliquity;
+  double earth_radius, sidereal_rate, sidereal_phase;
+} fstat_earth;
+
+#define FSTAT_MAX_SITES 8
+
 typedef struct fstat_plan fstat_plan;
 
 /* ------------------------------------------------------------- calls --- */
@@ -188,6 +207,23 @@ int fstat_batch_compute(fstat_plan* p, const fstat_wu* wus, int32_t n_wu, const 
 int fstat_bins(fstat_plan* p, const fstat_wu* wu, int64_t n, const int32_t* i_sky, const int32_t* i_fd,
                const int32_t* i_f, const int32_t* i_sft, int64_t* kstar, double* kappa, double* phi_frac,
                void* stream);
+
+/* Detector inputs of a work unit, computed on the device (the step before
+ * the demodulation; the per-SFT data are computed on the fly, Section 4):
+ * for SFT al with midpoint t_mid[al] taken at site site_of_sft[al] (an index
+ * into the host array sites[n_sites], n_sites <= FSTAT_MAX_SITES), the
+ * detector position pos[al][3] (light-s) and velocity vel[al][3] (units of c)
+ * in equatorial axes, and for each sky direction sky[s][3] the antenna-pattern
+ * factors a[s][al], b[s][al]: the plus and cross projections of the detector
+ * tensor (u u^T - w w^T)/2 of arm directions u, w on the wave frame
+ * X = (sin al, -cos al, 0), Y = (-sin d cos al, -sin d sin al, cos d) of the
+ * direction (right ascension al, declination d; al = 0 at the poles).  earth
+ * and sites are host pointers; the arrays are device pointers, caller-owned.
+ * FP64 arithmetic; a, b are rounded to FP32.  A site index outside
+ * [0, n_sites) gives NaN outputs for that SFT. */
+int fstat_detector_inputs(fstat_plan* p, const fstat_earth* earth, int32_t n_sites, const fstat_site* sites,
+                          int64_t n_sft, const double* t_mid, const int32_t* site_of_sft, int64_t n_sky,
+                          const double* sky, double* pos, double* vel, float* a, float* b, void* stream);
 
 /* Measure the candidate tile shapes on this work unit (timed on `stream`,
  * outputs overwritten) and keep the fastest for work units of its class

@@ -43,7 +43,8 @@ PHASES = {"fp64": FSTAT_PHASE_FP64, "split": FSTAT_PHASE_SPLIT_FP32}
 
 # Every entry point include/fstat.h declares.
 EXPORTS = ("fstat_plan_create", "fstat_compute", "fstat_batch_compute", "fstat_bins", "fstat_autotune",
-           "fstat_last_kernel_ms", "fstat_plan_destroy", "fstat_strerror", "fstat_last_error")
+           "fstat_last_kernel_ms", "fstat_plan_destroy", "fstat_strerror", "fstat_last_error",
+           "fstat_detector_inputs")
 
 
 class FstatError(RuntimeError):
@@ -67,6 +68,15 @@ class fstat_wu(ctypes.Structure):
                 ("a", ctypes.c_void_p), ("b", ctypes.c_void_p), ("f0", ctypes.c_double), ("df", ctypes.c_double),
                 ("n_f", ctypes.c_int64), ("fdot0", ctypes.c_double), ("dfdot", ctypes.c_double),
                 ("n_fd", ctypes.c_int64), ("t_ref", ctypes.c_double), ("dterms", ctypes.c_int32)]
+
+
+class fstat_site(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_double) for k in ("lat", "lon", "az_x", "az_y")]
+
+
+class fstat_earth(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_double) for k in ("t0", "orbit_radius", "orbit_rate", "orbit_phase", "obliquity",
+                                               "earth_radius", "sidereal_rate", "sidereal_phase")]
 
 
 class fstat_out(ctypes.Structure):
@@ -105,6 +115,9 @@ def load_library(path: str = LIB_PATH):
     lib.fstat_strerror.restype = ctypes.c_char_p
     lib.fstat_last_error.argtypes = [P]
     lib.fstat_last_error.restype = ctypes.c_char_p
+    lib.fstat_detector_inputs.argtypes = [P, ctypes.POINTER(fstat_earth), I32, ctypes.POINTER(fstat_site), I64, P, P,
+                                          I64, P, P, P, P, P, P]
+    lib.fstat_detector_inputs.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -193,6 +206,20 @@ def toplist(o):
     return (t[:n, 0].view(np.float32).copy(), t[:n, 1].copy(), t[:n, 2].copy(), t[:n, 3].copy(), n_above)
 
 
+def fstat_detector_inputs(plan, earth: dict, sites, t_mid, site_of_sft, sky, pos, vel, a, b, stream=None) -> None:
+    """Detector positions, velocities and antenna patterns on the device.
+    earth: dict with the fstat_earth fields; sites: (lat, lon, az_x, az_y)
+    tuples in radians; the arrays are device tensors (t_mid float64 [n_sft],
+    site_of_sft int32 [n_sft], sky float64 [n_sky, 3], pos and vel float64
+    [n_sft, 3], a and b float32 [n_sky, n_sft])."""
+    e = fstat_earth(*[float(earth[k]) for k, _ in fstat_earth._fields_])
+    st = (fstat_site * len(sites))(*[fstat_site(*map(float, x)) for x in sites])
+    n_sft, n_sky = int(t_mid.shape[0]), int(sky.shape[0])
+    _check(plan, load_library().fstat_detector_inputs(plan, ctypes.byref(e), len(sites), st, n_sft, _ptr(t_mid),
+                                                      _ptr(site_of_sft), n_sky, _ptr(sky), _ptr(pos), _ptr(vel),
+                                                      _ptr(a), _ptr(b), _stream_handle(stream)))
+
+
 def fstat_strerror(code: int) -> str:
     return load_library().fstat_strerror(int(code)).decode()
 
@@ -275,6 +302,9 @@ class Plan:
 
     def bins(self, wu, i_sky, i_fd, i_f, i_sft, kstar, kappa, phi_frac, stream=None):
         fstat_bins(self.handle, wu, i_sky, i_fd, i_f, i_sft, kstar, kappa, phi_frac, stream)
+
+    def detector_inputs(self, earth, sites, t_mid, site_of_sft, sky, pos, vel, a, b, stream=None):
+        fstat_detector_inputs(self.handle, earth, sites, t_mid, site_of_sft, sky, pos, vel, a, b, stream)
 
     def autotune(self, wu, out, stream=None, cache_path=None):
         fstat_autotune(self.handle, wu, out, stream, cache_path)

@@ -10,7 +10,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "_build", "libfstat.so")
-SOURCES = ["fstat_kernels.hip", "fstat_api.cpp"]
+SOURCES = ["fstat_kernels.hip", "fstat_detector.hip", "fstat_api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # -ffp-contract=off: the FP64 bin-index arithmetic must round operation by

@@ -52,6 +52,9 @@ struct fstat_plan {
   size_t bcand_bytes = 0;
   void* bcount = nullptr;
   size_t bcount_bytes = 0;
+  // detector inputs: per-SFT detector tensors
+  void* dten = nullptr;
+  size_t dten_bytes = 0;
   // timing
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   hipStream_t ev_stream = nullptr;
@@ -760,6 +763,7 @@ void fstat_plan_destroy(fstat_plan* p) {
   if (p->cand_count) (void)hipFree(p->cand_count);
   if (p->bcand) (void)hipFree(p->bcand);
   if (p->bcount) (void)hipFree(p->bcount);
+  if (p->dten) (void)hipFree(p->dten);
   for (auto& kv : p->ctab) (void)hipFree(kv.second);
   if (p->status_d) (void)hipFree(p->status_d);
   if (p->status_h) (void)hipHostFree(p->status_h);
@@ -843,6 +847,45 @@ static bool valid_tile(const fstat_plan* p, const Tile& t) {
   }
   return (t.nf_reg == 1 && (t.chunk == 16 || t.chunk == 8)) || (t.nf_reg == 2 && (t.chunk == 8 || t.chunk == 4)) ||
          (t.nf_reg == 4 && t.chunk == 4);
+}
+
+int fstat_detector_inputs(fstat_plan* p, const fstat_earth* earth, int32_t n_sites, const fstat_site* sites,
+                          int64_t n_sft, const double* t_mid, const int32_t* site_of_sft, int64_t n_sky,
+                          const double* sky, double* pos, double* vel, float* a, float* b, void* stream) {
+  if (!p) return FSTAT_E_ARG;
+  p->err.clear();
+  if (!earth || !sites) return set_err(p, FSTAT_E_ARG, "null earth model or site list");
+  if (n_sites < 1 || n_sites > FSTAT_MAX_SITES) return set_err(p, FSTAT_E_ARG, "n_sites %d outside [1, 8]", n_sites);
+  if (n_sft < 1 || n_sky < 1) return set_err(p, FSTAT_E_ARG, "sizes must be >= 1");
+  if (!t_mid || !site_of_sft || !sky || !pos || !vel || !a || !b) return set_err(p, FSTAT_E_ARG, "null array");
+  if (n_sft > ((int64_t)1 << 40) / n_sky) return set_err(p, FSTAT_E_SIZE, "too many (sky, SFT) pairs");
+  const double vals[8] = {earth->t0, earth->orbit_radius, earth->orbit_rate, earth->orbit_phase, earth->obliquity,
+                          earth->earth_radius, earth->sidereal_rate, earth->sidereal_phase};
+  for (double x : vals)
+    if (!std::isfinite(x)) return set_err(p, FSTAT_E_ARG, "non-finite earth model parameter");
+  fstat::EarthModel m{};
+  m.t0 = earth->t0;
+  m.orbit_radius = earth->orbit_radius;
+  m.orbit_rate = earth->orbit_rate;
+  m.orbit_phase = earth->orbit_phase;
+  m.obliquity = earth->obliquity;
+  m.earth_radius = earth->earth_radius;
+  m.sidereal_rate = earth->sidereal_rate;
+  m.sidereal_phase = earth->sidereal_phase;
+  m.n_sites = n_sites;
+  for (int k = 0; k < n_sites; ++k) {
+    const fstat_site& s = sites[k];
+    if (!std::isfinite(s.lat) || !std::isfinite(s.lon) || !std::isfinite(s.az_x) || !std::isfinite(s.az_y))
+      return set_err(p, FSTAT_E_ARG, "non-finite site %d", k);
+    m.sites[k] = fstat::SiteModel{s.lat, s.lon, s.az_x, s.az_y};
+  }
+  if (hipSetDevice(p->device) != hipSuccess) return set_err(p, FSTAT_E_DEVICE, "hipSetDevice failed");
+  int rc = dev_alloc(p, &p->dten, &p->dten_bytes, (size_t)n_sft * 6 * sizeof(double), "detector tensors");
+  if (rc) return rc;
+  return check_launch(p,
+                      fstat::launch_detector_inputs(m, n_sft, t_mid, site_of_sft, n_sky, sky, pos, vel,
+                                                    (double*)p->dten, a, b, (hipStream_t)stream),
+                      "detector input kernels");
 }
 
 int fstat_autotune(fstat_plan* p, const fstat_wu* wu, const fstat_out* out, void* stream, const char* cache_path) {

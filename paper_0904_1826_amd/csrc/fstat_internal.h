@@ -121,6 +121,19 @@ hipError_t launch_bins(const WuDev& w, int64_t n, const int32_t* i_sky, const in
 size_t demod_lds_bytes(const WuDev& w, const Tile& t, int kernel);
 int interp_max_seg(int threads, bool c16);
 hipError_t launch_cexp(const WuDev& w, hipStream_t s);
+// Detector inputs (fstat_detector_inputs): per-SFT position, velocity and
+// detector tensor (6 unique components into dten), then a, b per (sky, SFT).
+struct SiteModel {
+  double lat, lon, az_x, az_y;
+};
+struct EarthModel {
+  double t0, orbit_radius, orbit_rate, orbit_phase, obliquity, earth_radius, sidereal_rate, sidereal_phase;
+  int32_t n_sites;
+  SiteModel sites[8];
+};
+hipError_t launch_detector_inputs(const EarthModel& m, int64_t n_sft, const double* t_mid, const int32_t* site_of_sft,
+                                  int64_t n_sky, const double* sky, double* pos, double* vel, double* dten, float* a,
+                                  float* b, hipStream_t s);
 // Toplist selection after the demodulation: sort each work unit's candidate
 // segment (cap entries, cap a power of two) and write top and n_above.
 hipError_t launch_top_select(const WuDev& w, hipStream_t s);
