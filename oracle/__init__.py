@@ -176,6 +176,22 @@ def toplist(twoF, threshold: float, k: int):
     return idx[order[:k]], len(idx)
 
 
+def semicoherent(segs, templates=None, *, sfts=None, nthreads: Optional[int] = None):
+    """Semi-coherent statistic of the listed templates: the sum over the
+    time segments `segs` (work units sharing one template grid and reference
+    time) of each segment's coherent 2F, in FP64.  The paper's client
+    combines per-segment F-statistics in a second, incoherent stage
+    (Section 2) without describing it; the plain sum of 2F over segments is
+    the reading taken here.  `sfts` optionally replaces each segment's SFT
+    values."""
+    total = None
+    for k, w in enumerate(segs):
+        r = fstat(w, templates, sft=None if sfts is None else sfts[k], nthreads=nthreads)
+        total = r["twoF"].copy() if total is None else total + r["twoF"]
+        templates = r["templates"]
+    return {"twoF": total, "templates": templates}
+
+
 class _Earth(ctypes.Structure):
     _fields_ = [(k, ctypes.c_double) for k in ("t0", "orbit_radius", "orbit_rate", "orbit_phase", "obliquity",
                                                "earth_radius", "sidereal_rate", "sidereal_phase")]

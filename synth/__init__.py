@@ -18,5 +18,5 @@ them with the shapes stated in `CONFIGS`.
 from .workloads import (  # noqa: F401
     Workload, Injection, CONFIG_NAMES, make_config, make_workload, orbit, sky_grid,
     antenna_patterns, SITES, band_limits, quantise_time, dequantise_16bit,
-    quantise_sfts, EPOCH, make_batch, BATCH_NAMES,
+    quantise_sfts, EPOCH, make_batch, BATCH_NAMES, make_segments, make_segment_config, SEGMENT_NAMES,
 )

@@ -233,10 +233,11 @@ CONFIG_NAMES = {
 
 def make_workload(name, *, seed, n_det, slots_per_det, keep_frac, jitter, t_sft, f0, n_f,
                   n_sky, n_fd, fdot_lo, fdot_hi, dterms, injections=(), sky_override=None,
-                  noise=True, sites=SITES):
+                  noise=True, sites=SITES, epoch=EPOCH, t_ref=None):
     """General recipe.  Each detector has `slots_per_det` consecutive T_sft
-    slots starting at EPOCH; a random `keep_frac` of them is kept (all if 1),
-    and each kept start is jittered by U[0, jitter) s and quantised."""
+    slots starting at `epoch`; a random `keep_frac` of them is kept (all if 1),
+    and each kept start is jittered by U[0, jitter) s and quantised.  The
+    reference time is the first SFT start unless `t_ref` is given."""
     rng = np.random.Generator(np.random.PCG64(seed))
     t_all, det_offset = [], [0]
     for d in range(n_det):
@@ -244,7 +245,7 @@ def make_workload(name, *, seed, n_det, slots_per_det, keep_frac, jitter, t_sft,
         if keep_frac < 1.0:
             n_keep = int(round(keep_frac * slots_per_det))
             slots = np.sort(rng.choice(slots_per_det, size=n_keep, replace=False))
-        t = EPOCH + slots * t_sft + rng.uniform(0.0, jitter, size=len(slots))
+        t = epoch + slots * t_sft + rng.uniform(0.0, jitter, size=len(slots))
         t_all.append(quantise_time(t))
         det_offset.append(det_offset[-1] + len(slots))
     t_start = np.concatenate(t_all)
@@ -258,7 +259,7 @@ def make_workload(name, *, seed, n_det, slots_per_det, keep_frac, jitter, t_sft,
         a[:, lo:hi], b[:, lo:hi] = antenna_patterns(sites[d % len(sites)], sky, t_mid[lo:hi])
     df = 1.0 / t_sft
     dfdot = (fdot_hi - fdot_lo) / (n_fd - 1) if n_fd > 1 else 0.0
-    t_ref = float(t_start.min())
+    t_ref = float(t_start.min()) if t_ref is None else float(t_ref)
     rmax = float(np.max(np.linalg.norm(pos, axis=1)))
     vmax = float(np.max(np.linalg.norm(vel, axis=1)))
     f_hi = f0 + (n_f - 1) * df
@@ -309,6 +310,50 @@ def make_config(idx: int, *, seed: Optional[int] = None, **over):
     name = over.pop("name", None) or CONFIG_NAMES[idx] + ("" if not over else "-custom")
     p.pop("name", None)
     return make_workload(name, seed=seed, **p)
+
+
+SEGMENT_NAMES = {
+    20: "semicoherent-20seg-2det-2000sft-2000sky-8fd-3600f-D8",
+}
+
+
+def make_segments(n_seg: int, *, seed: int, seg_slots: int, gap_slots: int = 0, name: Optional[str] = None,
+                  injections=(), **kw):
+    """Consecutive time segments of one observation for the semi-coherent
+    combination: segment k covers `seg_slots` T_sft slots per detector starting
+    (seg_slots + gap_slots) * k slots after EPOCH, with its own noise and gaps
+    (the remaining keywords as in make_workload).  All segments share the
+    template grid and the reference time t_ref = EPOCH, so a template names
+    the same signal in each of them.  Each injection (sky, fdot, f index, snr)
+    gets one set of amplitude parameters and is added to every segment with
+    that phase model, scaled to SNR `snr` in each segment."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    injs = []
+    for inj in injections:
+        s_i, fd_i, f_i, snr = inj
+        injs.append(Injection(int(s_i), int(fd_i), int(f_i), float(snr), float(rng.uniform(-1, 1)),
+                              float(rng.uniform(0, math.pi)), float(rng.uniform(0, 2 * math.pi))))
+    t_sft = kw["t_sft"]
+    segs = []
+    for k in range(n_seg):
+        segs.append(make_workload(f"{name or 'segments'}-{k}", seed=seed * 1000 + k, slots_per_det=seg_slots,
+                                  epoch=EPOCH + k * (seg_slots + gap_slots) * t_sft, t_ref=EPOCH,
+                                  injections=injs, **kw))
+    return segs
+
+
+def make_segment_config(n_seg: int = 20, *, seed: int = 2020, **over):
+    """The work-unit-shaped case (2 detectors, 2000 sky points x 8
+    spindowns x 3600 frequencies at 1000 Hz, Dterms 8, 60 % duty cycle) as
+    `n_seg` consecutive segments whose SFT counts add up to that case's:
+    1667 / n_seg slots per detector each (about 100 kept SFTs per segment for
+    20 segments), four signals at SNR 4 to 7 per segment."""
+    p = dict(n_det=2, seg_slots=1667 // n_seg, keep_frac=0.6, jitter=0.0, t_sft=1800.0, f0=1000.0, n_f=3600,
+             n_sky=2000, n_fd=8, fdot_lo=-1.0e-9, fdot_hi=0.0, dterms=8,
+             injections=[(137, 3, 500, 4.0), (901, 7, 1800, 5.0), (1402, 0, 2700, 7.0), (1999, 5, 3400, 6.0)])
+    p.update(over)
+    name = SEGMENT_NAMES.get(n_seg) if not over else None
+    return make_segments(n_seg, seed=seed, name=name or f"semicoherent-{n_seg}seg-custom", **p)
 
 
 BATCH_NAMES = {
