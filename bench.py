@@ -8,9 +8,14 @@ workload is the work-unit-shaped case: 2 detectors x 1000 SFTs of 1800 s,
 a 3600-bin band at 1000 Hz, 2000 sky points x 8 spindowns x 3600
 frequencies, Dterms = 8 (5.76e7 templates, 1.15e11 template-SFT pairs).
 Inputs are synthetic (seeded noise and injected signals) and resident in HBM
-before the timed region.  Prints one JSON line.
+before the timed region.  Prints one JSON line.  Besides the forms of the
+main case it times the direct kernel, the toplist-only output and the
+semi-coherent sum of the same case split into 20 time segments; with
+--workload semicoherent that split case is the main one (a step is then one
+fstat_semicoherent call over all segments).
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--forms c64,bf16,fp16]
+                  [--workload workunit|semicoherent]
 """
 import argparse
 import hashlib
@@ -111,6 +116,11 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--toplist", type=int, default=1000,
                     help="also time the plain form writing only a top-K toplist above 2F = 20 (0: skip)")
+    ap.add_argument("--semicoherent", type=int, default=20,
+                    help="also time the semi-coherent sum over this many segments of the same case (0: skip)")
+    ap.add_argument("--workload", default="workunit", choices=["workunit", "semicoherent"],
+                    help="the case the forms are timed on: the work-unit-shaped case, or the same case as "
+                         "--semicoherent segments combined by fstat_semicoherent")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (HBM counter calibration)")
@@ -136,28 +146,38 @@ def main():
         print(f"[bench] calibration copy: {n} bytes read, {n} bytes written", file=sys.stderr, flush=True)
         del src, dst
     t0 = time.time()
-    w = synth.make_config(1)
-    print(f"[bench] workload {w.name}: {w.n_sft} SFTs x {w.n_bins} bins, {w.n_templates} templates "
-          f"(generated in {time.time() - t0:.1f} s)", file=sys.stderr, flush=True)
-    pairs = w.n_templates * w.n_sft
+    semi_main = args.workload == "semicoherent"
+    if semi_main:
+        case = synth.make_segment_config(args.semicoherent or 20)
+        case_name = case[0].name.rsplit("-", 1)[0]
+    else:
+        case = [synth.make_config(1)]
+        case_name = case[0].name
+    w = case[0]
+    n_sft_total = sum(x.n_sft for x in case)
+    print(f"[bench] workload {case_name}: {n_sft_total} SFTs in {len(case)} part(s) x {w.n_bins} bins, "
+          f"{w.n_templates} templates (generated in {time.time() - t0:.1f} s)", file=sys.stderr, flush=True)
+    pairs = w.n_templates * n_sft_total
     forms = [f for f in args.forms.split(",") if f]
     results = {}
     for form in forms:
         storage, _, extra = form.partition("+")
         coef = "f16" if extra == "coef16" else "f32"
-        wu, _ = to_device(w, storage)
+        wus = [to_device(x, storage)[0] for x in case]
         out = alloc_output(w)
         torch.cuda.synchronize()
-        with P.Plan(max_sft=w.n_sft, max_bins=w.n_bins, max_sky=w.n_sky, max_fd=w.n_fd, max_f=w.n_f,
-                    max_dterms=w.dterms, storage=storage, coef=coef, kernel=args.kernel) as plan:
+        with P.Plan(max_sft=max(x.n_sft for x in case), max_bins=max(x.n_bins for x in case), max_sky=w.n_sky,
+                    max_fd=w.n_fd, max_f=w.n_f, max_dterms=w.dterms, storage=storage, coef=coef,
+                    kernel=args.kernel) as plan:
+            step = (lambda: plan.semicoherent(wus, out)) if semi_main else (lambda: plan.compute(wus[0], out))
             steps = args.steps if form == forms[0] else max(2, args.steps // 2)
             for _ in range(args.warmup):
-                plan.compute(wu, out)
+                step()
             torch.cuda.synchronize()
             kms = []
             t_start = time.perf_counter()
             for _ in range(steps):
-                plan.compute(wu, out)
+                step()
                 kms.append(plan.last_kernel_ms())
             torch.cuda.synchronize()
             el = time.perf_counter() - t_start
@@ -166,12 +186,12 @@ def main():
                          # the 2F error bound each form is tested to against the FP64 oracle
                          "err_bound": 5e-3 if (coef == "f16" or storage != "c64") else 1e-4}
         print(f"[bench] {form}: {results[form]}", file=sys.stderr, flush=True)
-        del wu, out
+        del wus, out
         torch.cuda.empty_cache()
 
     kernel = "direct" if args.kernel == "direct" else "interp"     # the library resolves auto to interp
     kernels = {}
-    if args.compare_direct > 0 and kernel != "direct":
+    if args.compare_direct > 0 and kernel != "direct" and not semi_main:
         wu, _ = to_device(w, "c64")
         out = alloc_output(w)
         with P.Plan(max_sft=w.n_sft, max_bins=w.n_bins, max_sky=w.n_sky, max_fd=w.n_fd, max_f=w.n_f,
@@ -191,7 +211,7 @@ def main():
         del wu, out
         torch.cuda.empty_cache()
     toplist = None
-    if args.toplist > 0:
+    if args.toplist > 0 and not semi_main:
         wu, _ = to_device(w, "c64")
         out = alloc_output(w, top_k=args.toplist, threshold=20.0, full=False)
         with P.Plan(max_sft=w.n_sft, max_bins=w.n_bins, max_sky=w.n_sky, max_fd=w.n_fd, max_f=w.n_f,
@@ -209,6 +229,37 @@ def main():
         print(f"[bench] toplist: {toplist}", file=sys.stderr, flush=True)
         del wu, out
         torch.cuda.empty_cache()
+    semi = None
+    if args.semicoherent > 0 and not semi_main:
+        t0 = time.time()
+        segs = synth.make_segment_config(args.semicoherent)
+        spairs = segs[0].n_templates * sum(x.n_sft for x in segs)
+        devs = [to_device(x, "c64")[0] for x in segs]
+        out = alloc_output(segs[0])
+        gen_s = time.time() - t0
+        semi = {"workload": segs[0].name.rsplit("-", 1)[0], "n_seg": len(segs),
+                "n_sft": [int(x.n_sft) for x in segs][:3] + ["..."], "pairs_per_step": spairs}
+        for coef in ("f32", "f16"):
+            with P.Plan(max_sft=max(x.n_sft for x in segs), max_bins=max(x.n_bins for x in segs),
+                        max_sky=segs[0].n_sky, max_fd=segs[0].n_fd, max_f=segs[0].n_f, max_dterms=segs[0].dterms,
+                        coef=coef, kernel=args.kernel) as plan:
+                plan.semicoherent(devs, out)
+                torch.cuda.synchronize()
+                kms = []
+                t_start = time.perf_counter()
+                for _ in range(2):
+                    plan.semicoherent(devs, out)
+                    kms.append(plan.last_kernel_ms())
+                torch.cuda.synchronize()
+                el = time.perf_counter() - t_start
+            semi["coef16" if coef == "f16" else "plain"] = {
+                "value": 2 * spairs / el, "ms_per_step": 1e3 * el / 2, "kernel_ms": float(np.mean(kms)),
+                "roofline_frac": slots_per_pair(kernel, segs[0].dterms) * spairs / (np.mean(kms) * 1e-3) / PEAK_SLOTS,
+                "err_bound": 5e-3 if coef == "f16" else 1e-4}
+        print(f"[bench] semi-coherent ({gen_s:.1f} s to generate): {semi}", file=sys.stderr, flush=True)
+        del devs, out
+        torch.cuda.empty_cache()
+    traffic_key = "semicoherent" if semi_main else "config1"
     main_form = forms[0]
     r = results[main_form]
     slots = slots_per_pair(kernel, w.dterms) * pairs
@@ -226,24 +277,26 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": w.name, "n_det": w.n_det, "n_sft": w.n_sft, "n_bins": w.n_bins, "n_sky": w.n_sky,
-                   "n_fd": w.n_fd, "n_f": w.n_f, "dterms": w.dterms, "form": main_form, "phase": "fp64",
-                   "kernel": kernel, "templates": w.n_templates, "pairs_per_step": pairs},
+        "config": {"workload": case_name, "n_det": w.n_det, "n_sft": n_sft_total, "n_bins": w.n_bins,
+                   "n_sky": w.n_sky, "n_fd": w.n_fd, "n_f": w.n_f, "dterms": w.dterms, "form": main_form,
+                   "phase": "fp64", "kernel": kernel, "templates": w.n_templates, "pairs_per_step": pairs,
+                   **({"n_seg": len(case)} if semi_main else {})},
         "forms": {k: {"value": v["value"], "ms_per_step": v["ms_per_step"], "kernel_ms": v["kernel_ms"],
                       "err_bound": v["err_bound"],
                       "vs_plain": v["value"] / results[main_form]["value"],
                       "roofline_frac": slots_per_pair(kernel, w.dterms) * pairs / (v["kernel_ms"] * 1e-3) / PEAK_SLOTS,
                       "traffic": measured_traffic("demod_interp_coef16" if k.endswith("+coef16") else f"demod_{kernel}",
-                                                  "config1")}
+                                                  traffic_key)}
                   for k, v in results.items()},
         "kernels": kernels,
         "toplist": toplist,
+        "semicoherent": semi,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12, "unit": "TOP/s",
-                     "frac": achieved / PEAK_SLOTS, "traffic": measured_traffic(f"demod_{kernel}", "config1"),
+                     "frac": achieved / PEAK_SLOTS, "traffic": measured_traffic(f"demod_{kernel}", traffic_key),
                      "kernel": f"demod_{kernel}", "slots_per_pair": slots_per_pair(kernel, w.dterms),
                      "kernel_ms": r["kernel_ms"]},
     }
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not semi_main:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
     print(json.dumps(line), flush=True)
 

@@ -200,6 +200,17 @@ int fstat_compute(fstat_plan* p, const fstat_wu* wu, const fstat_out* out, void*
 int fstat_batch_compute(fstat_plan* p, const fstat_wu* wus, int32_t n_wu, const fstat_out* outs,
                         void* stream);
 
+/* Semi-coherent combination (the search client's second stage combines
+ * per-segment statistics incoherently, Section 2): the n_seg work units are
+ * time segments of one observation that share the template grid (sky
+ * points, f0, df, n_f, fdot0, dfdot, n_fd, t_ref; bands and SFT counts may
+ * differ).  The call writes out->twoF = the sum over segments of each
+ * segment's coherent 2F, accumulated in segment order (so the result is
+ * reproducible bit for bit), and, if out->top_k > 0, the toplist of that sum
+ * with the threshold applied to the sum.  out->twoF is required (it holds the
+ * sum); Fa/Fb outputs are not available (must be NULL). */
+int fstat_semicoherent(fstat_plan* p, const fstat_wu* segs, int32_t n_seg, const fstat_out* out, void* stream);
+
 /* Bin index, offset and phase of (template, SFT) pairs, computed by the same
  * device code the demodulation kernels use (step "bin index + phase").
  * Index arrays and outputs are device arrays of length n: sky, spindown,
@@ -237,8 +248,9 @@ int fstat_autotune(fstat_plan* p, const fstat_wu* wu, const fstat_out* out, void
                    const char* cache_path);
 
 /* Duration in milliseconds of the last demodulation kernel of the last
- * fstat_compute / fstat_batch_compute call, measured with HIP events on the
- * stream it ran on (waits for it).  Returns a negative value if none. */
+ * fstat_compute / fstat_batch_compute call (after fstat_semicoherent: the
+ * sum over its segments' demodulation kernels), measured with HIP events on
+ * the stream it ran on (waits for it).  Returns a negative value if none. */
 double fstat_last_kernel_ms(fstat_plan* p);
 
 /* Release the plan and everything it allocated (waits for its device work).

@@ -44,7 +44,7 @@ PHASES = {"fp64": FSTAT_PHASE_FP64, "split": FSTAT_PHASE_SPLIT_FP32}
 # Every entry point include/fstat.h declares.
 EXPORTS = ("fstat_plan_create", "fstat_compute", "fstat_batch_compute", "fstat_bins", "fstat_autotune",
            "fstat_last_kernel_ms", "fstat_plan_destroy", "fstat_strerror", "fstat_last_error",
-           "fstat_detector_inputs")
+           "fstat_detector_inputs", "fstat_semicoherent")
 
 
 class FstatError(RuntimeError):
@@ -103,6 +103,8 @@ def load_library(path: str = LIB_PATH):
     lib.fstat_compute.restype = ctypes.c_int
     lib.fstat_batch_compute.argtypes = [P, ctypes.POINTER(fstat_wu), I32, ctypes.POINTER(fstat_out), P]
     lib.fstat_batch_compute.restype = ctypes.c_int
+    lib.fstat_semicoherent.argtypes = [P, ctypes.POINTER(fstat_wu), I32, ctypes.POINTER(fstat_out), P]
+    lib.fstat_semicoherent.restype = ctypes.c_int
     lib.fstat_bins.argtypes = [P, ctypes.POINTER(fstat_wu), I64, P, P, P, P, P, P, P, P]
     lib.fstat_bins.restype = ctypes.c_int
     lib.fstat_autotune.argtypes = [P, ctypes.POINTER(fstat_wu), ctypes.POINTER(fstat_out), P, ctypes.c_char_p]
@@ -271,6 +273,13 @@ def fstat_batch_compute(plan, wus: Sequence, outs: Sequence, stream=None) -> Non
     _check(plan, load_library().fstat_batch_compute(plan, ws, n, os_, _stream_handle(stream)))
 
 
+def fstat_semicoherent(plan, segs: Sequence, out, stream=None) -> None:
+    n = len(segs)
+    ws = (fstat_wu * max(n, 1))(*[_wu_struct(w) for w in segs])
+    o = _out_struct(out)
+    _check(plan, load_library().fstat_semicoherent(plan, ws, n, ctypes.byref(o), _stream_handle(stream)))
+
+
 def fstat_bins(plan, wu, i_sky, i_fd, i_f, i_sft, kstar, kappa, phi_frac, stream=None) -> None:
     s = _wu_struct(wu)
     n = int(i_sky.numel())
@@ -299,6 +308,9 @@ class Plan:
 
     def batch_compute(self, wus, outs, stream=None):
         fstat_batch_compute(self.handle, wus, outs, stream)
+
+    def semicoherent(self, segs, out, stream=None):
+        fstat_semicoherent(self.handle, segs, out, stream)
 
     def bins(self, wu, i_sky, i_fd, i_f, i_sft, kstar, kappa, phi_frac, stream=None):
         fstat_bins(self.handle, wu, i_sky, i_fd, i_f, i_sft, kstar, kappa, phi_frac, stream)

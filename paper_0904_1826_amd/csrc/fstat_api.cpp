@@ -59,6 +59,7 @@ struct fstat_plan {
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   hipStream_t ev_stream = nullptr;
   bool timed = false;
+  double ms_prev = 0.0;                    // semi-coherent: demodulation time of the earlier segments
   // tile choices per class key
   std::map<std::string, Tile> tiles;
   // batched form: scratch arena, per-work-unit statuses, work-unit tables,
@@ -777,6 +778,7 @@ int fstat_compute(fstat_plan* p, const fstat_wu* wu, const fstat_out* out, void*
   if (!p) return FSTAT_E_ARG;
   p->err.clear();
   p->timed = false;
+  p->ms_prev = 0.0;
   int rc = validate_wu(p, wu, out, -1);
   if (rc) return rc;
   if (hipSetDevice(p->device) != hipSuccess) return set_err(p, FSTAT_E_DEVICE, "hipSetDevice failed");
@@ -795,6 +797,7 @@ int fstat_batch_compute(fstat_plan* p, const fstat_wu* wus, int32_t n_wu, const 
   if (!p) return FSTAT_E_ARG;
   p->err.clear();
   p->timed = false;
+  p->ms_prev = 0.0;
   if (n_wu < 0 || (n_wu > 0 && (!wus || !outs))) return set_err(p, FSTAT_E_ARG, "bad work-unit list");
   for (int k = 0; k < n_wu; ++k) {
     int rc = validate_wu(p, &wus[k], &outs[k], k);
@@ -817,6 +820,58 @@ int fstat_batch_compute(fstat_plan* p, const fstat_wu* wus, int32_t n_wu, const 
     if (rc) return rc;
   }
   return FSTAT_OK;
+}
+
+int fstat_semicoherent(fstat_plan* p, const fstat_wu* segs, int32_t n_seg, const fstat_out* out, void* stream) {
+  if (!p) return FSTAT_E_ARG;
+  p->err.clear();
+  p->timed = false;
+  p->ms_prev = 0.0;
+  if (n_seg < 1 || !segs || !out) return set_err(p, FSTAT_E_ARG, "semi-coherent: need n_seg >= 1 segments and an output");
+  if (!out->twoF) return set_err(p, FSTAT_E_ARG, "semi-coherent: the twoF output holds the sum and is required");
+  if (out->fa || out->fb) return set_err(p, FSTAT_E_UNSUPPORTED, "semi-coherent: no Fa/Fb outputs");
+  const fstat_wu& g = segs[0];
+  for (int k = 0; k < n_seg; ++k) {
+    int rc = validate_wu(p, &segs[k], out, k);
+    if (rc) return rc;
+    const fstat_wu& w = segs[k];
+    if (w.n_sky != g.n_sky || w.n_f != g.n_f || w.n_fd != g.n_fd || w.f0 != g.f0 || w.df != g.df ||
+        w.fdot0 != g.fdot0 || w.dfdot != g.dfdot || w.t_ref != g.t_ref)
+      return set_err(p, FSTAT_E_ARG, "segment %d: template grid or reference time differs from segment 0", k);
+  }
+  if (hipSetDevice(p->device) != hipSuccess) return set_err(p, FSTAT_E_DEVICE, "hipSetDevice failed");
+  hipStream_t st = (hipStream_t)stream;
+  int rc = ensure_toplist(p, out);
+  if (rc) return rc;
+  fstat_out o = *out;
+  o.top_k = 0;                       // the toplist is taken of the sum, after the last segment
+  double ms_done = 0.0;
+  for (int k = 0; k < n_seg; ++k) {
+    rc = ensure_scratch(p, &segs[k]);
+    if (rc) return rc;
+    WuDev v = make_dev(p, &segs[k], &o);
+    v.accumulate = k > 0;
+    // the geometry pass waits for the stream, so the previous segment's
+    // demodulation events have completed
+    rc = run_geometry(p, v, st, k);
+    if (rc) return rc;
+    if (k > 0) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, p->ev0, p->ev1) == hipSuccess) ms_done += ms;
+    }
+    rc = run_demod(p, v, pick_tile(p, &segs[k]), st);
+    if (rc) return rc;
+  }
+  p->ms_prev = ms_done;
+  if (out->top_k > 0) {
+    WuDev v = make_dev(p, &g, out);
+    rc = check_launch(p, fstat::launch_fill_int((int*)v.cand_count, 0, 2, st), "toplist counter reset");
+    if (rc) return rc;
+    rc = check_launch(p, fstat::launch_cand_scan(v, st), "semi-coherent candidate scan");
+    if (rc) return rc;
+    rc = check_launch(p, fstat::launch_top_select(v, st), "toplist selection");
+  }
+  return rc;
 }
 
 int fstat_bins(fstat_plan* p, const fstat_wu* wu, int64_t n, const int32_t* i_sky, const int32_t* i_fd,
@@ -964,7 +1019,7 @@ double fstat_last_kernel_ms(fstat_plan* p) {
   if (hipEventSynchronize(p->ev1) != hipSuccess) return -1.0;
   float ms = 0.f;
   if (hipEventElapsedTime(&ms, p->ev0, p->ev1) != hipSuccess) return -1.0;
-  return ms;
+  return p->ms_prev + ms;
 }
 
 const char* fstat_strerror(int code) {

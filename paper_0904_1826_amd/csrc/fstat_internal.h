@@ -36,6 +36,7 @@ struct WuDev {
   int32_t top_k;
   int4* top;               // [top_k] (2F bits, sky, fdot, f)
   unsigned long long* n_above;
+  int32_t accumulate;      // 1: the epilogue adds 2F to twoF (semi-coherent sum) instead of storing it
   int64_t n_sft, n_bins, k_first, n_sky, n_f, n_fd;
   double t_sft, f0, df, fdot0, dfdot, t_ref;
   int32_t dterms;
@@ -137,6 +138,8 @@ hipError_t launch_detector_inputs(const EarthModel& m, int64_t n_sft, const doub
 // Toplist selection after the demodulation: sort each work unit's candidate
 // segment (cap entries, cap a power of two) and write top and n_above.
 hipError_t launch_top_select(const WuDev& w, hipStream_t s);
+// Candidates of an existing 2F array (the semi-coherent sum) for the toplist.
+hipError_t launch_cand_scan(const WuDev& w, hipStream_t s);
 hipError_t launch_top_select_batch(const BatchEntry* ents_dev, int n_ent, uint4* cand, int64_t cap, int max_top_k,
                                    hipStream_t s);
 hipError_t launch_cexp_batch(const BatchEntry* ents_dev, int n_ent, int64_t total_sfts, hipStream_t s);

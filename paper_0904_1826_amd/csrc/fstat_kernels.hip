@@ -386,7 +386,7 @@ __global__ __launch_bounds__(kThreads) void demod_direct_kernel(WuDev w) {
     const double fa2 = ar * ar + ai * ai, fb2 = br * br + bi * bi, re = ar * br + ai * bi;
     const double two_f = 2.0 * (abcd.y * fa2 + abcd.x * fb2 - 2.0 * abcd.z * re) / abcd.w;
     const int64_t o = (s * w.n_fd + i) * w.n_f + j;
-    if (w.twoF) w.twoF[o] = (float)two_f;
+    if (w.twoF) w.twoF[o] = w.accumulate ? w.twoF[o] + (float)two_f : (float)two_f;
     if (w.cand) cand_push(w, (float)two_f, o);
     if (w.fa) w.fa[o] = make_float2(far[r], fai[r]);
     if (w.fb) w.fb[o] = make_float2(fbr[r], fbi[r]);
@@ -907,7 +907,7 @@ __device__ __forceinline__ void interp_tile(const WuDev& w, int W, int64_t tile,
     const double ar = far[r], ai = fai[r], br = fbr[r], bi = fbi[r];
     const double fa2 = ar * ar + ai * ai, fb2 = br * br + bi * bi, re = ar * br + ai * bi;
     const double two_f = 2.0 * (abcd.y * fa2 + abcd.x * fb2 - 2.0 * abcd.z * re) / abcd.w;
-    if (w.twoF) w.twoF[o] = (float)two_f;
+    if (w.twoF) w.twoF[o] = w.accumulate ? w.twoF[o] + (float)two_f : (float)two_f;
     if (w.cand) cand_push(w, (float)two_f, o);
     if (w.fa) w.fa[o] = make_float2(far[r], fai[r]);
     if (w.fb) w.fb[o] = make_float2(fbr[r], fbi[r]);
@@ -964,6 +964,14 @@ __global__ __launch_bounds__(kThreads, (C16 && NFD == 8) ? 4 : 3) void demod_int
 }
 
 // ------------------------------------------------------------ toplist
+// Candidates of a 2F array already in memory (the semi-coherent sum): one
+// thread per template.
+__global__ __launch_bounds__(256) void cand_scan_kernel(WuDev w, int64_t n) {
+  const int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (o >= n) return;
+  cand_push(w, w.twoF[o], o);
+}
+
 // Ranking of candidates: larger 2F first, then smaller linear template index.
 __device__ __forceinline__ bool cand_better(uint4 x, uint4 y) {
   const float fx = __uint_as_float(x.x), fy = __uint_as_float(y.x);
@@ -1254,6 +1262,14 @@ static hipError_t top_select(const Seg& seg, int n_seg, uint4* cand, int64_t cap
   if (max_top_k <= 0) return hipSuccess;
   hipLaunchKernelGGL(top_write_kernel<Seg>, dim3((unsigned)((max_top_k + 255) / 256), (unsigned)n_seg), block, 0, st,
                      seg, (const uint4*)cand, cap);
+  return hipGetLastError();
+}
+
+hipError_t launch_cand_scan(const WuDev& w, hipStream_t st) {
+  const int64_t n = w.n_sky * w.n_fd * w.n_f;
+  const int64_t blocks = (n + 255) / 256;
+  if (!w.cand || !w.twoF || blocks <= 0 || blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(cand_scan_kernel, dim3((unsigned)blocks), dim3(256), 0, st, w, n);
   return hipGetLastError();
 }
 
