@@ -336,7 +336,8 @@ int interp_seg(const fstat_plan* p, const fstat_wu* w, int nfd, int threads) {
 
 Tile default_tile(const fstat_plan* p, const fstat_wu* w) {
   if (resolved_kernel(p) == fstat::KERNEL_INTERP) {
-    const int nfd = w->n_fd >= 8 ? 8 : (w->n_fd >= 4 ? 4 : (w->n_fd >= 2 ? 2 : 1));
+    // 5 to 7 spindowns: one partial block of 8 costs no more lanes than two of 4
+    const int nfd = w->n_fd >= 5 ? 8 : (w->n_fd >= 3 ? 4 : (w->n_fd >= 2 ? 2 : 1));
     // measured on the work-unit-shaped case: 8 spindowns per thread with room
     // for 3 waves per SIMD (4 with FP16 coefficients, whose slices take half
     // the LDS and registers) and one launch over all SFTs is fastest; with
@@ -351,7 +352,12 @@ Tile default_tile(const fstat_plan* p, const fstat_wu* w) {
 Tile pick_tile(const fstat_plan* p, const fstat_wu* w) {
   auto it = p->tiles.find(class_key(p, w));
   Tile t = it != p->tiles.end() ? it->second : default_tile(p, w);
-  if (resolved_kernel(p) == fstat::KERNEL_INTERP) t.seg = interp_seg(p, w, t.nf_reg, t.threads);
+  if (resolved_kernel(p) == fstat::KERNEL_INTERP) {
+    t.seg = interp_seg(p, w, t.nf_reg, t.threads);
+    // 8 spindowns per thread and 1 to 4 left over: those run 4 per thread
+    const int64_t rem = w->n_fd % 8;
+    t.seg4 = (t.nf_reg == 8 && w->n_fd > 8 && rem >= 1 && rem <= 4) ? interp_seg(p, w, 4, t.threads) : 0;
+  }
   return t;
 }
 
@@ -525,7 +531,8 @@ int batch_interp(fstat_plan* p, const fstat_wu* wus, int n, const fstat_out* out
   if (rc) return rc;
   rc = ensure_pinned_pair(p, &p->bstat_d, &p->bstat_h, &p->bstat_cap, (size_t)n, "batch status");
   if (rc) return rc;
-  rc = ensure_pinned_pair(p, &p->ents_d, &p->ents_h, &p->ents_cap, (size_t)n, "work-unit table");
+  // per group: one entry per unit and up to two demodulation entries per unit
+  rc = ensure_pinned_pair(p, &p->ents_d, &p->ents_h, &p->ents_cap, 3 * (size_t)n, "work-unit table");
   if (rc) return rc;
   for (int k = 0; k < n; ++k) {
     rc = ensure_ctab(p, wus[k].dterms);
@@ -562,27 +569,24 @@ int batch_interp(fstat_plan* p, const fstat_wu* wus, int n, const fstat_out* out
   for (auto& g : groups) {
     rc = batch_check(p, wus, outs, g.first, g.second, (char*)p->arena, offs, st);
     if (rc) return rc;
-    // table of the group: the units with 8 spindowns per thread, then those
-    // with 4 (one persistent launch each), most SFTs first within each
+    // table of the group: one entry per work unit (coefficient passes and
+    // toplists), most SFTs first; then the demodulation tables: each unit's
+    // spindowns [0, split) in blocks of 8 and the remaining 1 to 4 in one
+    // block of 4 (a remainder of 5 to 7 takes a partial block of 8), one
+    // persistent launch per table, most SFTs first within each
     std::vector<int> order;
     for (int k = g.first; k < g.second; ++k) order.push_back(k);
-    auto nfd_of = [&](int k) { return wus[k].n_fd >= 8 ? 8 : 4; };
-    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
-      return nfd_of(x) != nfd_of(y) ? nfd_of(x) > nfd_of(y) : wus[x].n_sft > wus[y].n_sft;
-    });
-    fstat::BatchEntry* eh = p->ents_h + g.first;
-    int64_t tiles = 0, blocks = 0, sfts = 0, tiles8 = 0;
-    int m8 = 0, max_top_k = 0;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return wus[x].n_sft > wus[y].n_sft; });
+    const int m = (int)order.size();
+    fstat::BatchEntry* eh = p->ents_h + 3 * (size_t)g.first;
+    int64_t blocks = 0, sfts = 0;
+    int max_top_k = 0;
     uint4* gcand = any_top ? (uint4*)p->bcand + (size_t)g.first * p->cand_cap : nullptr;
     unsigned long long* gcount = any_top ? (unsigned long long*)p->bcount + g.first : nullptr;
-    for (size_t q = 0; q < order.size(); ++q) {
+    for (int q = 0; q < m; ++q) {
       const int k = order[q];
-      if (nfd_of(k) == 8) m8 = (int)q + 1;
-      if (nfd_of(k) == 4 && (q == 0 || nfd_of(order[q - 1]) == 8)) {
-        tiles8 = tiles;                              // the 4-spindown table numbers its tiles from 0
-        tiles = 0;
-      }
       fstat::BatchEntry& e = eh[q];
+      e = fstat::BatchEntry{};
       WuDev v = make_dev(p, &wus[k], &outs[k]);
       const WuScratch sc = wu_scratch(p, &wus[k]);
       char* base = (char*)p->arena + offs[k];
@@ -592,7 +596,7 @@ int batch_interp(fstat_plan* p, const fstat_wu* wus, int n, const fstat_out* out
       v.cexp = sc.cexp ? (int32_t*)(base + sc.geo + sc.abcd + sc.coef) : nullptr;
       v.acc = nullptr;
       if (outs[k].top_k > 0) {                         // segment q of the group's candidates
-        v.cand = gcand + q * p->cand_cap;
+        v.cand = gcand + (size_t)q * p->cand_cap;
         v.cand_count = gcount + q;
         max_top_k = outs[k].top_k > max_top_k ? outs[k].top_k : max_top_k;
       } else {
@@ -600,21 +604,36 @@ int batch_interp(fstat_plan* p, const fstat_wu* wus, int n, const fstat_out* out
         v.cand_count = nullptr;
       }
       e.w = v;
-      e.nfd = nfd_of(k);
-      e.seg = interp_seg_tau(&wus[k], e.nfd, fstat::kThreads, coef16(p), status_tau(p->bstat_h[k]));
-      e.n_tiles = fstat::interp_tiles(v, e.nfd);
-      e.tile_begin = tiles;
       e.coef_begin = blocks;
       e.sft_begin = sfts;
-      tiles += e.n_tiles;
       blocks += fstat::coef_blocks(v);
       sfts += wus[k].n_sft;
     }
-    const int m = (int)order.size();
-    if (m8 == m) tiles8 = tiles;                     // only 8-spindown units
-    const int64_t tiles4 = m8 == m ? 0 : tiles;
-    fstat::BatchEntry* ed = p->ents_d + g.first;
-    hipError_t e = hipMemcpyAsync(ed, eh, (size_t)m * sizeof(fstat::BatchEntry), hipMemcpyHostToDevice, st);
+    int m8 = 0, m4 = 0;
+    int64_t tiles8 = 0, tiles4 = 0;
+    for (int nfd : {8, 4}) {
+      for (int q = 0; q < m; ++q) {
+        const int k = order[q];
+        const int64_t nf = wus[k].n_fd, rem = nf % 8;
+        const int64_t split = rem > 4 ? nf : nf - rem;
+        const int64_t lo = nfd == 8 ? 0 : split, hi = nfd == 8 ? split : nf;
+        if (hi <= lo) continue;
+        fstat::BatchEntry& e = eh[m + m8 + m4];
+        e = eh[q];
+        e.nfd = nfd;
+        e.fd_begin = (int32_t)lo;
+        e.fd_end = (int32_t)hi;
+        e.seg = interp_seg_tau(&wus[k], nfd, fstat::kThreads, coef16(p), status_tau(p->bstat_h[k]));
+        e.n_tiles = fstat::interp_tiles(e.w, nfd, lo, hi);
+        int64_t& tiles = nfd == 8 ? tiles8 : tiles4;
+        e.tile_begin = tiles;
+        tiles += e.n_tiles;
+        if (nfd == 8) ++m8; else ++m4;
+      }
+    }
+    fstat::BatchEntry* ed = p->ents_d + 3 * (size_t)g.first;
+    hipError_t e = hipMemcpyAsync(ed, eh, (size_t)(m + m8 + m4) * sizeof(fstat::BatchEntry), hipMemcpyHostToDevice,
+                                  st);
     if (e != hipSuccess) return hip_err(p, e, "work-unit table upload");
     if (first) {
       (void)hipEventRecord(p->ev0, st);
@@ -632,10 +651,10 @@ int batch_interp(fstat_plan* p, const fstat_wu* wus, int n, const fstat_out* out
       }
       rc = check_launch(p, fstat::launch_coef_batch(ed, m, blocks, c16, st), "coefficient kernel");
       if (rc) return rc;
-      rc = check_launch(p, fstat::launch_interp_batch(ed, m8, tiles8, p->counter, p->batch_grid, c16, 8, st),
+      rc = check_launch(p, fstat::launch_interp_batch(ed + m, m8, tiles8, p->counter, p->batch_grid, c16, 8, st),
                         "batch kernel");
       if (rc) return rc;
-      rc = check_launch(p, fstat::launch_interp_batch(ed + m8, m - m8, tiles4, p->counter + 1, p->batch_grid4, c16, 4,
+      rc = check_launch(p, fstat::launch_interp_batch(ed + m + m8, m4, tiles4, p->counter + 1, p->batch_grid4, c16, 4,
                                                       st),
                         "batch kernel");
       if (rc) return rc;
@@ -644,8 +663,8 @@ int batch_interp(fstat_plan* p, const fstat_wu* wus, int n, const fstat_out* out
       if (rc) return rc;
       continue;
     }
-    const std::vector<int64_t> sig = {(int64_t)(intptr_t)ed, m,     m8,          blocks, tiles8,
-                                      tiles4,                p->batch_grid, sfts, max_top_k};
+    const std::vector<int64_t> sig = {(int64_t)(intptr_t)ed, m, m8, m4, blocks, tiles8, tiles4, p->batch_grid, sfts,
+                                      max_top_k};
     auto it = p->graphs.find(sig);
     if (it == p->graphs.end()) {
       if (!p->cap_stream) {
@@ -657,9 +676,9 @@ int batch_interp(fstat_plan* p, const fstat_wu* wus, int n, const fstat_out* out
       hipError_t e0 = max_top_k > 0 ? fstat::launch_fill_int((int*)gcount, 0, 2 * m, p->cap_stream) : hipSuccess;
       if (e0 == hipSuccess && c16) e0 = fstat::launch_cexp_batch(ed, m, sfts, p->cap_stream);
       hipError_t e1 = e0 != hipSuccess ? e0 : fstat::launch_coef_batch(ed, m, blocks, c16, p->cap_stream);
-      hipError_t e2 = fstat::launch_interp_batch(ed, m8, tiles8, p->counter, p->batch_grid, c16, 8, p->cap_stream);
+      hipError_t e2 = fstat::launch_interp_batch(ed + m, m8, tiles8, p->counter, p->batch_grid, c16, 8, p->cap_stream);
       if (e2 == hipSuccess)
-        e2 = fstat::launch_interp_batch(ed + m8, m - m8, tiles4, p->counter + 1, p->batch_grid4, c16, 4,
+        e2 = fstat::launch_interp_batch(ed + m + m8, m4, tiles4, p->counter + 1, p->batch_grid4, c16, 4,
                                         p->cap_stream);
       if (e2 == hipSuccess)
         e2 = fstat::launch_top_select_batch(ed, m, gcand, p->cand_cap, max_top_k, p->cap_stream);

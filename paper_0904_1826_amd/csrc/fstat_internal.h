@@ -51,6 +51,8 @@ struct Tile {
   int32_t seg;      // interp: LDS segment width in bins (0: derived)
   int32_t sblock;   // interp: SFTs per launch (the SFT loop is split into launches of this many SFTs)
   int32_t threads;  // interp: work-group size, 64 or 256
+  int32_t seg4;     // interp with nf_reg 8: if > 0, spindowns past the last multiple of 8 (1 to 4 of them) run
+                    // in a second launch with 4 per thread and this slice width
 };
 
 enum Kernel : int32_t { KERNEL_DIRECT = 1, KERNEL_INTERP = 2 };
@@ -77,13 +79,16 @@ constexpr int kRuns16 = 3;
 __host__ __device__ constexpr int seg_cap16(int nt) { return 3 * nt / 2; }
 constexpr int kSegMax16 = seg_cap16(256);
 
-// One work unit of a batched launch: its device view, its slice width, its
-// spindowns per thread (4 or 8) and the index of its first tile in the
-// concatenated tile list.
+// One entry of a batched launch: a work unit's device view and, for the
+// demodulation tables, its slice width, its spindowns per thread (4 or 8),
+// the spindown range its tiles cover and the index of its first tile in the
+// concatenated tile list.  A work unit may have an entry in both the 8- and
+// the 4-spindown table (e.g. 12 spindowns: [0, 8) and [8, 12)).
 struct BatchEntry {
   WuDev w;
   int32_t seg;
   int32_t nfd;
+  int32_t fd_begin, fd_end;
   int64_t tile_begin;   // first tile in the concatenated tile list
   int64_t n_tiles;
   int64_t coef_begin;   // first block of the batched coefficient pass
@@ -111,7 +116,7 @@ hipError_t launch_geometry(const WuDev& w, GeoStatus* status, hipStream_t s);
 hipError_t launch_coef(const WuDev& w, hipStream_t s);
 hipError_t launch_demod(const WuDev& w, const Tile& t, int kernel, hipStream_t s);
 int interp_launches(const WuDev& w, const Tile& t);
-int64_t interp_tiles(const WuDev& w, int nfd);
+int64_t interp_tiles(const WuDev& w, int nfd, int64_t fd0, int64_t fd1);
 int64_t coef_blocks(const WuDev& w);
 hipError_t launch_coef_batch(const BatchEntry* ents_dev, int n_ent, int64_t total_blocks, bool c16, hipStream_t s);
 hipError_t launch_interp_batch(const BatchEntry* ents_dev, int n_ent, int64_t total_tiles,

@@ -767,11 +767,16 @@ __device__ __forceinline__ v4f lds_load_v(LdsPtr p, int i) { return p[i]; }
 // a/b accumulation in registers.  An SFT whose windows are not all inside
 // the slice (only possible for slices narrower than the tile's spread) takes
 // the same arithmetic with coefficients read from global memory.
+//
+// The tile covers spindowns [fd0, fd1) of the work unit in blocks of NFD
+// (the last block of a range may be partial: its missing spindowns repeat
+// the range's last one and are not written).
 template <int NFD, int S, int G, int NT, bool C16>
 __device__ __forceinline__ void interp_tile(const WuDev& w, int W, int64_t tile, int64_t al_begin, int64_t al_end,
-                                            float4* cbuf0, float4* cbuf1, GroupMeta<NFD, S>* meta) {
+                                            float4* cbuf0, float4* cbuf1, GroupMeta<NFD, S>* meta, int64_t fd0,
+                                            int64_t fd1) {
   const int tid = threadIdx.x;
-  const int64_t n_fdb = (w.n_fd + NFD - 1) / NFD;
+  const int64_t n_fdb = (fd1 - fd0 + NFD - 1) / NFD;
   using F = SliceForm<NT, C16>;
   constexpr int Wp = F::cap;                       // LDS row stride
   int64_t t = tile;
@@ -784,8 +789,8 @@ __device__ __forceinline__ void interp_tile(const WuDev& w, int W, int64_t tile,
   const bool jvalid = j < w.n_f;
   if (!jvalid) j = w.n_f - 1;
   const int64_t j_last = (j0 + NT - 1 < w.n_f - 1) ? j0 + NT - 1 : w.n_f - 1;
-  const int64_t i0 = ib * NFD;
-  const int64_t i_last = (i0 + NFD - 1 < w.n_fd - 1) ? i0 + NFD - 1 : w.n_fd - 1;
+  const int64_t i0 = fd0 + ib * NFD;
+  const int64_t i_last = (i0 + NFD - 1 < fd1 - 1) ? i0 + NFD - 1 : fd1 - 1;
   const double f = template_f(w, j);
   const float2 fsplit = split64(f);
   const bool split_phase = w.phase_mode != 0;
@@ -799,7 +804,7 @@ __device__ __forceinline__ void interp_tile(const WuDev& w, int W, int64_t tile,
   float far[NFD], fai[NFD], fbr[NFD], fbi[NFD];
 #pragma unroll
   for (int r = 0; r < NFD; ++r) {
-    const int64_t i = (i0 + r < w.n_fd) ? i0 + r : w.n_fd - 1;
+    const int64_t i = (i0 + r < fd1) ? i0 + r : fd1 - 1;
     if (al_begin > 0) {
       const float4 v = w.acc[(s * w.n_fd + i) * w.n_f + j];
       far[r] = v.x; fai[r] = v.y; fbr[r] = v.z; fbi[r] = v.w;
@@ -898,7 +903,7 @@ __device__ __forceinline__ void interp_tile(const WuDev& w, int W, int64_t tile,
 #pragma unroll
   for (int r = 0; r < NFD; ++r) {
     const int64_t i = i0 + r;
-    if (i >= w.n_fd) continue;
+    if (i >= fd1) continue;
     const int64_t o = (s * w.n_fd + i) * w.n_f + j;
     if (!last) {
       w.acc[o] = make_float4(far[r], fai[r], fbr[r], fbi[r]);
@@ -914,14 +919,15 @@ __device__ __forceinline__ void interp_tile(const WuDev& w, int W, int64_t tile,
   }
 }
 
-// One tile per work-group (see interp_tile).
+// One tile per work-group (see interp_tile) over spindowns [fd0, fd1).
 template <int NFD, int S, int MINW, int G, int NT, bool C16>
-__global__ __launch_bounds__(NT, MINW) void demod_interp_kernel(WuDev w, int W, int64_t al_begin, int64_t al_end) {
+__global__ __launch_bounds__(NT, MINW) void demod_interp_kernel(WuDev w, int W, int64_t al_begin, int64_t al_end,
+                                                                 int64_t fd0, int64_t fd1) {
   using F = SliceForm<NT, C16>;
   __shared__ GroupMeta<NFD, S> meta[2];
   __shared__ float4 cbuf0[F::rows * F::cap];
   __shared__ float4 cbuf1[F::rows * F::cap];
-  interp_tile<NFD, S, G, NT, C16>(w, W, blockIdx.x, al_begin, al_end, cbuf0, cbuf1, meta);
+  interp_tile<NFD, S, G, NT, C16>(w, W, blockIdx.x, al_begin, al_end, cbuf0, cbuf1, meta, fd0, fd1);
 }
 
 // Many work units in one persistent launch: the grid holds as many
@@ -958,7 +964,8 @@ __global__ __launch_bounds__(kThreads, (C16 && NFD == 8) ? 4 : 3) void demod_int
     const WuDev w = ents[lo].w;
     const int W = ents[lo].seg;
     const int64_t local = tile - ents[lo].tile_begin;
-    interp_tile<NFD, 16, 4, kThreads, C16>(w, W, local, 0, w.n_sft, cbuf0, cbuf1, meta);
+    interp_tile<NFD, 16, 4, kThreads, C16>(w, W, local, 0, w.n_sft, cbuf0, cbuf1, meta, ents[lo].fd_begin,
+                                           ents[lo].fd_end);
     __syncthreads();                                 // LDS free for the next tile
   }
 }
@@ -1134,8 +1141,8 @@ hipError_t launch_coef_batch(const BatchEntry* ents_dev, int n_ent, int64_t tota
   return hipGetLastError();
 }
 
-int64_t interp_tiles(const WuDev& w, int nfd) {
-  return ((w.n_f + kThreads - 1) / kThreads) * ((w.n_fd + nfd - 1) / nfd) * w.n_sky;
+int64_t interp_tiles(const WuDev& w, int nfd, int64_t fd0, int64_t fd1) {
+  return ((w.n_f + kThreads - 1) / kThreads) * ((fd1 - fd0 + nfd - 1) / nfd) * w.n_sky;
 }
 
 template <int NFD, bool C16>
@@ -1182,10 +1189,10 @@ int interp_launches(const WuDev& w, const Tile& t) {
 }
 
 template <int NFD, int S, int MINW, int G, int NT, bool C16>
-static hipError_t launch_interp_t(const WuDev& w, const Tile& t, hipStream_t st) {
+static hipError_t launch_interp_t(const WuDev& w, const Tile& t, hipStream_t st, int64_t fd0, int64_t fd1) {
   const int W = t.seg;
   const int64_t n_ft = (w.n_f + NT - 1) / NT;
-  const int64_t n_tiles = n_ft * ((w.n_fd + NFD - 1) / NFD) * w.n_sky;
+  const int64_t n_tiles = n_ft * ((fd1 - fd0 + NFD - 1) / NFD) * w.n_sky;
   if (n_tiles <= 0 || n_tiles > 0x7fffffffLL || W < 8 || W > SliceForm<NT, C16>::cap)
     return hipErrorInvalidConfiguration;
   const int64_t sb = t.sblock > 0 ? t.sblock : w.n_sft;
@@ -1193,7 +1200,7 @@ static hipError_t launch_interp_t(const WuDev& w, const Tile& t, hipStream_t st)
   for (int64_t al = 0; al < w.n_sft; al += sb) {
     const int64_t end = al + sb < w.n_sft ? al + sb : w.n_sft;
     hipLaunchKernelGGL((demod_interp_kernel<NFD, S, MINW, G, NT, C16>), dim3((unsigned)n_tiles), dim3(NT), 0, st, w,
-                       W, al, end);
+                       W, al, end, fd0, fd1);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -1209,40 +1216,56 @@ int interp_max_seg(int threads, bool c16) {
 // compiler must leave room for (2 or 3), threads = work-group size (64: one
 // wave per work-group, no barrier between waves; 256: four waves share one
 // staged slice; the FP16 coefficient form has 256-thread tiles only).
-static hipError_t launch_interp(const WuDev& w, const Tile& t, hipStream_t st) {
+static hipError_t launch_interp_range(const WuDev& w, const Tile& t, hipStream_t st, int64_t fd0, int64_t fd1) {
   const bool w3 = t.chunk >= 3;
   if (w.coef16) {
     if (t.threads == 64) return hipErrorInvalidValue;
     switch (t.nf_reg) {
-      case 8: return t.chunk >= 4 ? launch_interp_t<8, 16, 4, 4, kThreads, true>(w, t, st)
-                     : w3         ? launch_interp_t<8, 16, 3, 4, kThreads, true>(w, t, st)
-                                  : launch_interp_t<8, 16, 2, 4, kThreads, true>(w, t, st);
-      case 4: return w3 ? launch_interp_t<4, 16, 3, 4, kThreads, true>(w, t, st)
-                        : launch_interp_t<4, 16, 2, 4, kThreads, true>(w, t, st);
-      case 2: return launch_interp_t<2, 16, 3, 4, kThreads, true>(w, t, st);
-      case 1: return launch_interp_t<1, 16, 3, 4, kThreads, true>(w, t, st);
+      case 8: return t.chunk >= 4 ? launch_interp_t<8, 16, 4, 4, kThreads, true>(w, t, st, fd0, fd1)
+                     : w3         ? launch_interp_t<8, 16, 3, 4, kThreads, true>(w, t, st, fd0, fd1)
+                                  : launch_interp_t<8, 16, 2, 4, kThreads, true>(w, t, st, fd0, fd1);
+      case 4: return w3 ? launch_interp_t<4, 16, 3, 4, kThreads, true>(w, t, st, fd0, fd1)
+                        : launch_interp_t<4, 16, 2, 4, kThreads, true>(w, t, st, fd0, fd1);
+      case 2: return launch_interp_t<2, 16, 3, 4, kThreads, true>(w, t, st, fd0, fd1);
+      case 1: return launch_interp_t<1, 16, 3, 4, kThreads, true>(w, t, st, fd0, fd1);
       default: return hipErrorInvalidValue;
     }
   }
   if (t.threads == 64) {
     switch (t.nf_reg) {
-      case 8: return w3 ? launch_interp_t<8, 16, 3, 4, 64, false>(w, t, st)
-                        : launch_interp_t<8, 16, 2, 4, 64, false>(w, t, st);
-      case 4: return launch_interp_t<4, 16, 3, 4, 64, false>(w, t, st);
-      case 2: return launch_interp_t<2, 16, 3, 4, 64, false>(w, t, st);
-      case 1: return launch_interp_t<1, 16, 3, 4, 64, false>(w, t, st);
+      case 8: return w3 ? launch_interp_t<8, 16, 3, 4, 64, false>(w, t, st, fd0, fd1)
+                        : launch_interp_t<8, 16, 2, 4, 64, false>(w, t, st, fd0, fd1);
+      case 4: return launch_interp_t<4, 16, 3, 4, 64, false>(w, t, st, fd0, fd1);
+      case 2: return launch_interp_t<2, 16, 3, 4, 64, false>(w, t, st, fd0, fd1);
+      case 1: return launch_interp_t<1, 16, 3, 4, 64, false>(w, t, st, fd0, fd1);
       default: return hipErrorInvalidValue;
     }
   }
   switch (t.nf_reg) {
-    case 8: return w3 ? launch_interp_t<8, 16, 3, 4, kThreads, false>(w, t, st)
-                      : launch_interp_t<8, 16, 2, 4, kThreads, false>(w, t, st);
-    case 4: return w3 ? launch_interp_t<4, 16, 3, 4, kThreads, false>(w, t, st)
-                      : launch_interp_t<4, 16, 2, 4, kThreads, false>(w, t, st);
-    case 2: return launch_interp_t<2, 16, 3, 4, kThreads, false>(w, t, st);
-    case 1: return launch_interp_t<1, 16, 3, 4, kThreads, false>(w, t, st);
+    case 8: return w3 ? launch_interp_t<8, 16, 3, 4, kThreads, false>(w, t, st, fd0, fd1)
+                      : launch_interp_t<8, 16, 2, 4, kThreads, false>(w, t, st, fd0, fd1);
+    case 4: return w3 ? launch_interp_t<4, 16, 3, 4, kThreads, false>(w, t, st, fd0, fd1)
+                      : launch_interp_t<4, 16, 2, 4, kThreads, false>(w, t, st, fd0, fd1);
+    case 2: return launch_interp_t<2, 16, 3, 4, kThreads, false>(w, t, st, fd0, fd1);
+    case 1: return launch_interp_t<1, 16, 3, 4, kThreads, false>(w, t, st, fd0, fd1);
     default: return hipErrorInvalidValue;
   }
+}
+
+// The spindowns in blocks of nf_reg; with seg4 > 0 (nf_reg 8) the 1 to 4
+// spindowns past the last multiple of 8 run in a second launch with 4 per
+// thread instead of a partial block of 8.
+static hipError_t launch_interp(const WuDev& w, const Tile& t, hipStream_t st) {
+  const int64_t rem = w.n_fd % 8;
+  if (t.nf_reg != 8 || t.seg4 <= 0 || rem == 0 || rem > 4 || w.n_fd < 8) return launch_interp_range(w, t, st, 0, w.n_fd);
+  const int64_t split = w.n_fd - rem;
+  hipError_t e = launch_interp_range(w, t, st, 0, split);
+  if (e != hipSuccess) return e;
+  Tile t4 = t;
+  t4.nf_reg = 4;
+  t4.seg = t.seg4;
+  t4.chunk = t.chunk > 3 ? 3 : t.chunk;
+  return launch_interp_range(w, t4, st, split, w.n_fd);
 }
 
 template <class Seg>

@@ -63,6 +63,33 @@ def test_batch_matches_single_and_oracle(torch_cuda, oracle_lib):
         assert e.max() <= 1e-4
 
 
+@pytest.mark.parametrize("coef", ["f32", "f16"])
+def test_batch_spindown_ranges(torch_cuda, oracle_lib, coef):
+    """Spindown counts with every remainder modulo 8: the batched tables cover
+    [0, split) in blocks of 8 and the rest in one block of 4 (or a partial
+    block of 8 for remainders 5 to 7); every template against the oracle and
+    against the single-unit call."""
+    torch = torch_cuda
+    n_fds = [1, 3, 4, 5, 7, 8, 9, 12, 13, 16, 20]
+    ws = [small_workload(300 + k, n_sky=3, n_fd=nfd, n_f=300, slots=12, fdot_lo=-1e-9, injections=())
+          for k, nfd in enumerate(n_fds)]
+    outs, devs = _batch(torch, ws, coef=coef)
+    tol = 5e-3 if coef == "f16" else 1e-4
+    for k, w in enumerate(ws):
+        a = outs[k].twoF.cpu().numpy()
+        ref = oracle_lib.fstat(w)["twoF"].reshape(a.shape)
+        e = twoF_error(a, ref)
+        single = alloc_output(w)
+        with _plan_for([w], coef=coef) as p:
+            p.compute(devs[k][0], single)
+            torch.cuda.synchronize()
+        b = single.twoF.cpu().numpy()
+        d = np.max(np.abs(a - b) / np.maximum(np.abs(b), 4.0))
+        _say(f"  n_fd={w.n_fd}: max e vs oracle {e.max():.2e}, vs single call {d:.1e}")
+        assert e.max() <= tol, (w.n_fd, e.max())
+        assert d <= 1e-6, (w.n_fd, d)
+
+
 def test_batch_graph_replay_follows_new_contents(torch_cuda, oracle_lib):
     """The second call replays the captured graph; the work-unit table lives in
     device memory, so new data (and new buffers) of the same shapes are used."""
