@@ -628,17 +628,17 @@ __device__ __forceinline__ void group_meta(const WuDev& w, const double2* geo, c
   }
 }
 
-// Staging of one SFT's coefficient slice through registers: the slice is
-// kCoefPairs rows of seg_cap(NT) = 5 NT / 4 float4 starting at column lo
-// (columns W .. cap-1 are padding), 5 NT float4 in all, and thread t moves
-// elements t, t + NT, ..., five of them (row = index / cap, column =
-// index % cap).  The byte offset of each element from the slice start is the
-// same for every SFT, so the loads take a scalar base and a fixed per-thread
-// offset.  Reads past the band's last column land in the next row, or, for
-// the last SFT, in the kSegMax float4 of padding the coefficient buffer
-// carries, and fill only padding columns.  The loads are issued before the
-// current SFT is evaluated and written to LDS after it, so their latency
-// hides behind the arithmetic.
+// Staging of one SFT's coefficient slice: the slice is kCoefPairs rows of
+// seg_cap(NT) = 5 NT / 4 float4 starting at column lo (columns W .. cap-1 are
+// padding), 5 NT float4 in all, and thread t moves elements t, t + NT, ...,
+// five of them (row = index / cap, column = index % cap).  The byte offset
+// of each element from the slice start is the same for every SFT, so the
+// loads take a scalar base and a fixed per-thread offset.  Reads past the
+// band's last column land in the next row, or, for the last SFT, in the
+// kSegMax float4 of padding the coefficient buffer carries, and fill only
+// padding columns.  The loads go from global memory straight into LDS (each
+// wave's 64 lanes fill one contiguous 1 KB run), so they hold no registers
+// while the current SFT is evaluated.
 // LDS (address space 3) pointers as 32-bit byte addresses.
 typedef const __attribute__((address_space(3))) v4f* LdsPtr;
 __device__ __forceinline__ uint32_t lds_address(const float4* p) {
@@ -661,11 +661,6 @@ struct SliceForm {
 };
 
 template <int R>
-struct SlicePrefetch {
-  v4f v[R];
-};
-
-template <int R>
 struct SliceOffsets {
   uint32_t o[R];   // bytes from the slice start
 };
@@ -682,24 +677,30 @@ __device__ __forceinline__ SliceOffsets<SliceForm<NT, C16>::runs> slice_offsets(
   return so;
 }
 
-template <int NT, bool C16>
-__device__ __forceinline__ SlicePrefetch<SliceForm<NT, C16>::runs> slice_load(
-    const WuDev& w, const SliceOffsets<SliceForm<NT, C16>::runs>& so, int64_t al, int lo) {
-  using F = SliceForm<NT, C16>;
-  SlicePrefetch<F::runs> p;
-  const int lo_u = __builtin_amdgcn_readfirstlane(lo);   // uniform: keeps the base in scalar registers
-  const char* base = reinterpret_cast<const char*>(w.coef + (al * F::rows * w.n_bins + lo_u));
-#pragma unroll
-  for (int i = 0; i < F::runs; ++i) p.v[i] = *reinterpret_cast<const v4f*>(base + so.o[i]);
-  return p;
+// One 16-byte global load per lane written straight to LDS: the wave's lanes
+// fill the 1 KB at `lds` (wave-uniform) in lane order.
+__device__ __forceinline__ void lds_dma16(const void* g, float4* lds) {
+  __builtin_amdgcn_global_load_lds(g, (__attribute__((address_space(3))) void*)lds, 16, 0, 0);
 }
 
-template <int NT, int R>
-__device__ __forceinline__ void slice_store(const SlicePrefetch<R>& p, float4* buf_) {
-  v4f* buf = reinterpret_cast<v4f*>(buf_);
+// Loads the slice of SFT `al` from global memory directly into `buf`: run i
+// of the wave with index q lands at buf[NT i + 64 q .. NT i + 64 q + 63],
+// lane by lane, i.e. thread t fills element t + NT i.  Completion is awaited with
+// lds_dma_wait before the barrier that publishes the buffer.
+template <int NT, bool C16>
+__device__ __forceinline__ void slice_load_lds(const WuDev& w, const SliceOffsets<SliceForm<NT, C16>::runs>& so,
+                                               int64_t al, int lo, float4* buf) {
+  using F = SliceForm<NT, C16>;
+  const int lo_u = __builtin_amdgcn_readfirstlane(lo);
+  const char* base = reinterpret_cast<const char*>(w.coef + (al * F::rows * w.n_bins + lo_u));
+  const int q = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
 #pragma unroll
-  for (int i = 0; i < R; ++i) buf[(int)threadIdx.x + NT * i] = p.v[i];
+  for (int i = 0; i < F::runs; ++i)
+    lds_dma16(base + so.o[i], buf + NT * i + 64 * q);
 }
+
+// Waits for this wave's outstanding global loads, the LDS-direct ones included.
+__device__ __forceinline__ void lds_dma_wait() { __builtin_amdgcn_s_waitcnt(0x0F70); }   // vmcnt(0)
 
 // Degree-7 complex polynomial in u = kappa (Horner) times exp(-2 pi i phi),
 // added to Fa, Fb with the weights a, b.
@@ -819,7 +820,8 @@ __device__ __forceinline__ void interp_tile(const WuDev& w, int W, int64_t tile,
   const bool wave_live = __builtin_amdgcn_readfirstlane((int)(j0 + (tid & ~63) < w.n_f));
   group_meta<NFD, S, NT>(w, geo, arow, brow, al_begin, n < S ? n : S, i0, i_last, f_first, f_last, W, meta[0]);
   __syncthreads();
-  slice_store<NT>(slice_load<NT, C16>(w, so, al_begin, meta[0].lo[0]), cbuf0);
+  slice_load_lds<NT, C16>(w, so, al_begin, meta[0].lo[0], cbuf0);
+  lds_dma_wait();
   __syncthreads();
   // One SFT per step; the step is written twice (even SFTs read cbuf0 and
   // fill cbuf1, odd SFTs the reverse) so that every LDS access has a fixed
@@ -837,8 +839,9 @@ __device__ __forceinline__ void interp_tile(const WuDev& w, int W, int64_t tile,
     // unconditional (the last step reloads its own SFT and discards it), so
     // that the registers carry no branch-merged values the compiler must wait
     // for
+    // the other buffer was consumed before the last barrier
     const int k1 = more ? k + 1 : k;
-    const SlicePrefetch<F::runs> pre = slice_load<NT, C16>(w, so, al_begin + k1, meta[(k1 / S) & 1].lo[k1 % S]);
+    slice_load_lds<NT, C16>(w, so, al_begin + k1, meta[(k1 / S) & 1].lo[k1 % S], next);
     const GroupMeta<NFD, S>& m = meta[gq];
     const int64_t al = al_begin + k;
     if constexpr (decltype(live)::value) {
@@ -883,7 +886,7 @@ __device__ __forceinline__ void interp_tile(const WuDev& w, int W, int64_t tile,
       }
     }
     }
-    if (more) slice_store<NT>(pre, next);           // the other buffer was consumed before the last barrier
+    lds_dma_wait();
     __syncthreads();
   };
   if (wave_live) {
