@@ -964,7 +964,7 @@ __global__ __launch_bounds__(kThreads, (C16 && NFD == 8) ? 4 : 3) void demod_int
       if (ents[mid].tile_begin <= tile) lo = mid; else hi = mid - 1;
     }
     lo = __builtin_amdgcn_readfirstlane(lo);
-    const WuDev w = ents[lo].w;
+    const WuDev& w = ents[lo].w;                  // fields read from the table as needed, not copied
     const int W = ents[lo].seg;
     const int64_t local = tile - ents[lo].tile_begin;
     interp_tile<NFD, 16, 4, kThreads, C16>(w, W, local, 0, w.n_sft, cbuf0, cbuf1, meta, ents[lo].fd_begin,
