@@ -339,11 +339,10 @@ Tile default_tile(const fstat_plan* p, const fstat_wu* w) {
     // 5 to 7 spindowns: one partial block of 8 costs no more lanes than two of 4
     const int nfd = w->n_fd >= 5 ? 8 : (w->n_fd >= 3 ? 4 : (w->n_fd >= 2 ? 2 : 1));
     // measured on the work-unit-shaped case: 8 spindowns per thread with room
-    // for 3 waves per SIMD (4 with FP16 coefficients, whose slices take half
-    // the LDS and registers) and one launch over all SFTs is fastest; with
+    // for 4 waves per SIMD and one launch over all SFTs is fastest; with
     // fewer spindowns per thread the staged slices are reused less and
     // splitting the SFT loop into launches keeps them in L2
-    const int minw = (coef16(p) && nfd == 8) ? 4 : 3;
+    const int minw = nfd == 8 ? 4 : 3;
     return Tile{nfd, minw, 0, nfd >= 4 ? 0 : 256, fstat::kThreads};
   }
   return Tile{4, 4, 0, 0, 0};   // fastest direct tile on the work-unit-shaped case
@@ -915,9 +914,11 @@ static bool valid_tile(const fstat_plan* p, const Tile& t) {
   if (t.sblock < 0) return false;
   if (resolved_kernel(p) == fstat::KERNEL_INTERP) {
     const bool nf_ok = t.nf_reg == 8 || t.nf_reg == 4 || t.nf_reg == 2 || t.nf_reg == 1;
-    if (coef16(p))   // 256-thread tiles; 4 waves per SIMD with 8 spindowns per thread
-      return nf_ok && t.threads == 256 && (t.chunk == 2 || t.chunk == 3 || (t.chunk == 4 && t.nf_reg == 8));
-    return nf_ok && (t.chunk == 2 || t.chunk == 3) && (t.threads == 256 || (t.threads == 64 && t.nf_reg >= 4));
+    // 4 waves per SIMD: 256-thread tiles with 8 spindowns per thread
+    const bool w_ok = t.chunk == 2 || t.chunk == 3 || (t.chunk == 4 && t.nf_reg == 8 && t.threads == 256);
+    if (coef16(p))   // 256-thread tiles
+      return nf_ok && w_ok && t.threads == 256;
+    return nf_ok && w_ok && (t.threads == 256 || (t.threads == 64 && t.nf_reg >= 4));
   }
   return (t.nf_reg == 1 && (t.chunk == 16 || t.chunk == 8)) || (t.nf_reg == 2 && (t.chunk == 8 || t.chunk == 4)) ||
          (t.nf_reg == 4 && t.chunk == 4);

@@ -65,11 +65,12 @@ enum Kernel : int32_t { KERNEL_DIRECT = 1, KERNEL_INTERP = 2 };
 constexpr int kCoef = 8;
 constexpr int kCoefPairs = kCoef / 2;
 // Widest coefficient slice (bins) a work-group of NT threads stages per SFT:
-// NT frequency templates plus NT/4 - 6 bins of Doppler and spindown spread
-// (58 for 256 threads, 10 for 64) and the slack.  Two buffers of it take
-// 40 KB of LDS for 256 threads, so three work-groups fit a CU.
+// NT frequency templates plus NT/8 + 2 bins of Doppler and spindown spread
+// (34 for 256 threads, 10 for 64) and the slack of 6.  Two buffers of it take
+// 37 KB of LDS for 256 threads, so with the per-SFT values four work-groups
+// fit a CU.  Each thread stages up to 5 float4 of it per SFT.
 constexpr int kMaxRuns = 5;
-__host__ __device__ constexpr int seg_cap(int nt) { return nt + nt / 4; }
+__host__ __device__ constexpr int seg_cap(int nt) { return nt + nt / 8 + 8; }
 constexpr int kSegMax = seg_cap(256);
 // FP16 coefficient form: one bin is 2 float4-sized rows (four complex FP16
 // coefficients each); each thread stages 3 of them per SFT, a row holds

@@ -629,9 +629,9 @@ __device__ __forceinline__ void group_meta(const WuDev& w, const double2* geo, c
 }
 
 // Staging of one SFT's coefficient slice: the slice is kCoefPairs rows of
-// seg_cap(NT) = 5 NT / 4 float4 starting at column lo (columns W .. cap-1 are
-// padding), 5 NT float4 in all, and thread t moves elements t, t + NT, ...,
-// five of them (row = index / cap, column = index % cap).  The byte offset
+// seg_cap(NT) float4 starting at column lo (columns W .. cap-1 are padding),
+// and thread t moves elements t, t + NT, ..., up to five of them (row =
+// index / cap, column = index % cap).  The byte offset
 // of each element from the slice start is the same for every SFT, so the
 // loads take a scalar base and a fixed per-thread offset.  Reads past the
 // band's last column land in the next row, or, for the last SFT, in the
@@ -657,7 +657,8 @@ struct SliceForm {
   static constexpr int rows = C16 ? kRows16 : kCoefPairs;
   static constexpr int runs = C16 ? kRuns16 : kMaxRuns;
   static constexpr int cap = C16 ? seg_cap16(NT) : seg_cap(NT);
-  static_assert(rows * cap == runs * NT, "slice rows must fill the staging runs exactly");
+  static constexpr int total = rows * cap;          // float4 per slice; the last run may be partial
+  static_assert(total <= runs * NT && total > (runs - 1) * NT, "slice rows must fit the staging runs");
 };
 
 template <int R>
@@ -695,8 +696,14 @@ __device__ __forceinline__ void slice_load_lds(const WuDev& w, const SliceOffset
   const char* base = reinterpret_cast<const char*>(w.coef + (al * F::rows * w.n_bins + lo_u));
   const int q = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
 #pragma unroll
-  for (int i = 0; i < F::runs; ++i)
-    lds_dma16(base + so.o[i], buf + NT * i + 64 * q);
+  for (int i = 0; i < F::runs; ++i) {
+    const int e0 = NT * i + 64 * q;                // wave-uniform
+    if (e0 + 64 <= F::total) {
+      lds_dma16(base + so.o[i], buf + e0);
+    } else if (e0 < F::total) {                    // the partial last run
+      if ((int)(threadIdx.x & 63) < F::total - e0) lds_dma16(base + so.o[i], buf + e0);
+    }
+  }
 }
 
 // Waits for this wave's outstanding global loads, the LDS-direct ones included.
@@ -945,10 +952,11 @@ __global__ __launch_bounds__(NT, MINW) void demod_interp_kernel(WuDev w, int W, 
 // thread), so that each specialisation keeps the registers, and hence the
 // occupancy, of the single-unit kernel.
 template <int NFD, bool C16>
-__global__ __launch_bounds__(kThreads, (C16 && NFD == 8) ? 4 : 3) void demod_interp_batch_kernel(
+__global__ __launch_bounds__(kThreads, NFD == 8 ? 4 : 3) void demod_interp_batch_kernel(
     const BatchEntry* __restrict__ ents, int n_ent, int64_t total_tiles, unsigned long long* counter) {
   using F = SliceForm<kThreads, C16>;
-  __shared__ GroupMeta<NFD, 16> meta[2];
+  constexpr int S = C16 ? 16 : 8;                  // per-SFT values per group: four work-groups' LDS fits a CU
+  __shared__ GroupMeta<NFD, S> meta[2];
   __shared__ float4 cbuf0[F::rows * F::cap];
   __shared__ float4 cbuf1[F::rows * F::cap];
   __shared__ unsigned long long next;
@@ -967,7 +975,7 @@ __global__ __launch_bounds__(kThreads, (C16 && NFD == 8) ? 4 : 3) void demod_int
     const WuDev& w = ents[lo].w;                  // fields read from the table as needed, not copied
     const int W = ents[lo].seg;
     const int64_t local = tile - ents[lo].tile_begin;
-    interp_tile<NFD, 16, 4, kThreads, C16>(w, W, local, 0, w.n_sft, cbuf0, cbuf1, meta, ents[lo].fd_begin,
+    interp_tile<NFD, S, 4, kThreads, C16>(w, W, local, 0, w.n_sft, cbuf0, cbuf1, meta, ents[lo].fd_begin,
                                            ents[lo].fd_end);
     __syncthreads();                                 // LDS free for the next tile
   }
@@ -1245,8 +1253,11 @@ static hipError_t launch_interp_range(const WuDev& w, const Tile& t, hipStream_t
     }
   }
   switch (t.nf_reg) {
-    case 8: return w3 ? launch_interp_t<8, 16, 3, 4, kThreads, false>(w, t, st, fd0, fd1)
-                      : launch_interp_t<8, 16, 2, 4, kThreads, false>(w, t, st, fd0, fd1);
+    // 4 waves per SIMD: per-SFT values for 8 SFTs at a time, so that four
+    // work-groups' LDS fits a CU
+    case 8: return t.chunk >= 4 ? launch_interp_t<8, 8, 4, 4, kThreads, false>(w, t, st, fd0, fd1)
+                   : w3         ? launch_interp_t<8, 16, 3, 4, kThreads, false>(w, t, st, fd0, fd1)
+                                : launch_interp_t<8, 16, 2, 4, kThreads, false>(w, t, st, fd0, fd1);
     case 4: return w3 ? launch_interp_t<4, 16, 3, 4, kThreads, false>(w, t, st, fd0, fd1)
                       : launch_interp_t<4, 16, 2, 4, kThreads, false>(w, t, st, fd0, fd1);
     case 2: return launch_interp_t<2, 16, 3, 4, kThreads, false>(w, t, st, fd0, fd1);

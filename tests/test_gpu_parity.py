@@ -113,8 +113,8 @@ def test_parity_ragged_tiles(torch_cuda, oracle_lib, dterms, kernel):
     _compare(oracle_lib, w, out)
 
 
-INTERP_TILES = [(8, 3, 0, 256), (8, 2, 0, 256), (8, 3, 7, 256), (4, 3, 0, 256), (4, 2, 7, 256), (2, 3, 0, 256),
-                (1, 3, 7, 256), (8, 3, 0, 64), (8, 2, 7, 64), (4, 3, 0, 64)]
+INTERP_TILES = [(8, 4, 0, 256), (8, 4, 7, 256), (8, 3, 0, 256), (8, 2, 0, 256), (8, 3, 7, 256), (4, 3, 0, 256),
+                (4, 2, 7, 256), (2, 3, 0, 256), (1, 3, 7, 256), (8, 3, 0, 64), (8, 2, 7, 64), (4, 3, 0, 64)]
 
 
 @pytest.mark.parametrize("tile", INTERP_TILES, ids=lambda t: "nf%d_w%d_sb%d_t%d" % t)
