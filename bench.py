@@ -9,8 +9,10 @@ a 3600-bin band at 1000 Hz, 2000 sky points x 8 spindowns x 3600
 frequencies, Dterms = 8 (5.76e7 templates, 1.15e11 template-SFT pairs).
 Inputs are synthetic (seeded noise and injected signals) and resident in HBM
 before the timed region.  Prints one JSON line.  Besides the forms of the
-main case it times the direct kernel, the toplist-only output and the
-semi-coherent sum of the same case split into 20 time segments; with
+main case it times the direct kernel, the toplist-only output, the
+semi-coherent sum of the same case split into 20 time segments and the
+batched form on 256 work units with BF16 SFTs (one call each with FP32 and
+FP16 coefficients, graph capture included); with
 --workload semicoherent that split case is the main one (a step is then one
 fstat_semicoherent call over all segments).
 
@@ -118,6 +120,8 @@ def main():
                     help="also time the plain form writing only a top-K toplist above 2F = 20 (0: skip)")
     ap.add_argument("--semicoherent", type=int, default=20,
                     help="also time the semi-coherent sum over this many segments of the same case (0: skip)")
+    ap.add_argument("--batch", type=int, default=4, choices=[0, 3, 4],
+                    help="also time the batched form on the 64-unit (3) or the 256-unit BF16 (4) case (0: skip)")
     ap.add_argument("--workload", default="workunit", choices=["workunit", "semicoherent"],
                     help="the case the forms are timed on: the work-unit-shaped case, or the same case as "
                          "--semicoherent segments combined by fstat_semicoherent")
@@ -259,6 +263,49 @@ def main():
         print(f"[bench] semi-coherent ({gen_s:.1f} s to generate): {semi}", file=sys.stderr, flush=True)
         del devs, out
         torch.cuda.empty_cache()
+    batch = None
+    if args.batch and not semi_main and kernel != "direct":
+        from synth.device import draw_noise_16bit
+        t0 = time.time()
+        bws = synth.make_batch(args.batch, workers=min(16, os.cpu_count() or 1))
+        bpairs = sum(x.n_templates * x.n_sft for x in bws)
+        storage = "bf16" if args.batch == 4 else "c64"
+        if args.batch == 4:
+            bdevs = [draw_noise_16bit(x, "bf16", seed=7000 + k) for k, x in enumerate(bws)]
+        else:
+            bdevs = [to_device(x, "c64")[0] for x in bws]
+        bouts = [alloc_output(x) for x in bws]
+        torch.cuda.synchronize()
+        batch = {"workload": synth.BATCH_NAMES[args.batch], "n_wu": len(bws), "pairs_per_step": bpairs,
+                 "storage": storage, "inputs_s": time.time() - t0}
+        nfd_mix = {8: 0, 4: 0}
+        for x in bws:
+            rem = x.n_fd % 8
+            lanes8 = x.n_fd if rem > 4 else x.n_fd - rem
+            nfd_mix[8] += x.n_sky * lanes8 * x.n_f * x.n_sft
+            nfd_mix[4] += x.n_sky * (x.n_fd - lanes8) * x.n_f * x.n_sft
+        slots_b = (slots_per_pair(kernel, 8, 8) * nfd_mix[8] + slots_per_pair(kernel, 8, 4) * nfd_mix[4]) / bpairs
+        for coef in ("f32", "f16"):
+            with P.Plan(max_sft=max(x.n_sft for x in bws), max_bins=max(x.n_bins for x in bws),
+                        max_sky=max(x.n_sky for x in bws), max_fd=max(x.n_fd for x in bws),
+                        max_f=max(x.n_f for x in bws), max_dterms=16, storage=storage, coef=coef) as plan:
+                reps = 1 if args.batch == 4 else 2            # the first call also captures the graph
+                kms = []
+                t_start = time.perf_counter()
+                for _ in range(reps):
+                    plan.batch_compute(bdevs, bouts)
+                    kms.append(plan.last_kernel_ms())
+                torch.cuda.synchronize()
+                el = (time.perf_counter() - t_start) / reps
+            key = "coef16" if coef == "f16" else "plain"
+            batch[key] = {"value": bpairs / el, "s_per_step": el, "kernel_s": float(np.mean(kms)) / 1e3,
+                          "roofline_frac": slots_b * bpairs / (np.mean(kms) * 1e-3) / PEAK_SLOTS,
+                          "err_bound": 5e-3 if (coef == "f16" or storage != "c64") else 1e-4}
+            print(f"[bench] batch {key}: {batch[key]}", file=sys.stderr, flush=True)
+        batch["coef16_vs_plain"] = batch["coef16"]["value"] / batch["plain"]["value"]
+        batch["slots_per_pair"] = slots_b
+        del bdevs, bouts
+        torch.cuda.empty_cache()
     traffic_key = "semicoherent" if semi_main else "config1"
     main_form = forms[0]
     r = results[main_form]
@@ -291,6 +338,7 @@ def main():
         "kernels": kernels,
         "toplist": toplist,
         "semicoherent": semi,
+        "batch": batch,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12, "unit": "TOP/s",
                      "frac": achieved / PEAK_SLOTS, "traffic": measured_traffic(f"demod_{kernel}", traffic_key),
                      "kernel": f"demod_{kernel}", "slots_per_pair": slots_per_pair(kernel, w.dterms),
