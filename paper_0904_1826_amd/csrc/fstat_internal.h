@@ -68,15 +68,12 @@ constexpr int kCoefPairs = kCoef / 2;
 // NT frequency templates plus NT/8 + 2 bins of Doppler and spindown spread
 // (34 for 256 threads, 10 for 64) and the slack of 6.  Two buffers of it take
 // 37 KB of LDS for 256 threads, so with the per-SFT values four work-groups
-// fit a CU.  Each thread stages up to 5 float4 of it per SFT.
-constexpr int kMaxRuns = 5;
+// fit a CU.
 __host__ __device__ constexpr int seg_cap(int nt) { return nt + nt / 8 + 8; }
 constexpr int kSegMax = seg_cap(256);
 // FP16 coefficient form: one bin is 2 float4-sized rows (four complex FP16
-// coefficients each); each thread stages 3 of them per SFT, a row holds
-// 3 NT / 2 bins (384 for 256 threads).
+// coefficients each); a row holds 3 NT / 2 bins (384 for 256 threads).
 constexpr int kRows16 = 2;
-constexpr int kRuns16 = 3;
 __host__ __device__ constexpr int seg_cap16(int nt) { return 3 * nt / 2; }
 constexpr int kSegMax16 = seg_cap16(256);
 
@@ -125,7 +122,6 @@ hipError_t launch_interp_batch(const BatchEntry* ents_dev, int n_ent, int64_t to
 int interp_batch_grid(bool c16, int nfd);
 hipError_t launch_bins(const WuDev& w, int64_t n, const int32_t* i_sky, const int32_t* i_fd, const int32_t* i_f,
                        const int32_t* i_sft, int64_t* kstar, double* kappa, double* phi_frac, hipStream_t s);
-size_t demod_lds_bytes(const WuDev& w, const Tile& t, int kernel);
 int interp_max_seg(int threads, bool c16);
 hipError_t launch_cexp(const WuDev& w, hipStream_t s);
 // Detector inputs (fstat_detector_inputs): per-SFT position, velocity and

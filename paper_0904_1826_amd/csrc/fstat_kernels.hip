@@ -628,17 +628,6 @@ __device__ __forceinline__ void group_meta(const WuDev& w, const double2* geo, c
   }
 }
 
-// Staging of one SFT's coefficient slice: the slice is kCoefPairs rows of
-// seg_cap(NT) float4 starting at column lo (columns W .. cap-1 are padding),
-// and thread t moves elements t, t + NT, ..., up to five of them (row =
-// index / cap, column = index % cap).  The byte offset
-// of each element from the slice start is the same for every SFT, so the
-// loads take a scalar base and a fixed per-thread offset.  Reads past the
-// band's last column land in the next row, or, for the last SFT, in the
-// kSegMax float4 of padding the coefficient buffer carries, and fill only
-// padding columns.  The loads go from global memory straight into LDS (each
-// wave's 64 lanes fill one contiguous 1 KB run), so they hold no registers
-// while the current SFT is evaluated.
 // LDS (address space 3) pointers as 32-bit byte addresses.
 typedef const __attribute__((address_space(3))) v4f* LdsPtr;
 __device__ __forceinline__ uint32_t lds_address(const float4* p) {
@@ -650,60 +639,63 @@ __device__ __forceinline__ float4 lds_load(LdsPtr p, int i) {
   return make_float4(v.x, v.y, v.z, v.w);
 }
 
-// Slice geometry of each coefficient form: float4 rows per bin, float4 each
-// thread stages per SFT, and bins per LDS row (rows x cap = runs x NT).
+// Slice geometry of each coefficient form: float4 rows per bin and bins per
+// LDS row.  For staging, each row is cut into blocks of 64 columns (the last
+// one partial unless cap is a multiple of 64), and the NT / 64 waves of a
+// work-group take `runs` blocks each.
 template <int NT, bool C16>
 struct SliceForm {
   static constexpr int rows = C16 ? kRows16 : kCoefPairs;
-  static constexpr int runs = C16 ? kRuns16 : kMaxRuns;
   static constexpr int cap = C16 ? seg_cap16(NT) : seg_cap(NT);
-  static constexpr int total = rows * cap;          // float4 per slice; the last run may be partial
-  static_assert(total <= runs * NT && total > (runs - 1) * NT, "slice rows must fit the staging runs");
+  static constexpr int waves = NT / 64;
+  static constexpr int blocks_per_row = (cap + 63) / 64;
+  static constexpr int runs = rows * blocks_per_row / waves;
+  static_assert(rows * blocks_per_row == runs * waves, "the waves must share the slice blocks evenly");
 };
 
-template <int R>
-struct SliceOffsets {
-  uint32_t o[R];   // bytes from the slice start
-};
-
+// Staging of one SFT's coefficient slice: rows x cap float4 starting at band
+// column lo (columns W .. cap-1 are padding), loaded from global memory
+// straight into `buf` while the other buffer is evaluated, so the loads hold
+// no registers.  Wave q moves blocks q, q + NT/64, ...; block b is row
+// b / blocks_per_row, columns 64 (b % blocks_per_row) + lane.  Each load is
+// one buffer instruction: a resource over the SFT's coefficients from
+// column lo (bounds-checked: reads beyond it return 0), a scalar offset per
+// block and the lane's byte offset.  Reads past the band's last column land
+// in the next row, or, for the last SFT, in the padding the coefficient
+// buffer carries (at least cap float4), and fill only padding columns.
+// Completion is awaited with lds_dma_wait before the barrier that publishes
+// the buffer.
 template <int NT, bool C16>
-__device__ __forceinline__ SliceOffsets<SliceForm<NT, C16>::runs> slice_offsets(const WuDev& w) {
-  using F = SliceForm<NT, C16>;
-  SliceOffsets<F::runs> so;
-#pragma unroll
-  for (int i = 0; i < F::runs; ++i) {
-    const int e = (int)threadIdx.x + NT * i;
-    so.o[i] = (uint32_t)(((e / F::cap) * w.n_bins + e % F::cap) * (int64_t)sizeof(float4));
-  }
-  return so;
-}
-
-// One 16-byte global load per lane written straight to LDS: the wave's lanes
-// fill the 1 KB at `lds` (wave-uniform) in lane order.
-__device__ __forceinline__ void lds_dma16(const void* g, float4* lds) {
-  __builtin_amdgcn_global_load_lds(g, (__attribute__((address_space(3))) void*)lds, 16, 0, 0);
-}
-
-// Loads the slice of SFT `al` from global memory directly into `buf`: run i
-// of the wave with index q lands at buf[NT i + 64 q .. NT i + 64 q + 63],
-// lane by lane, i.e. thread t fills element t + NT i.  Completion is awaited with
-// lds_dma_wait before the barrier that publishes the buffer.
-template <int NT, bool C16>
-__device__ __forceinline__ void slice_load_lds(const WuDev& w, const SliceOffsets<SliceForm<NT, C16>::runs>& so,
-                                               int64_t al, int lo, float4* buf) {
+__device__ __forceinline__ void slice_load_lds(const WuDev& w, int64_t al, int lo, float4* buf, uint32_t lane16) {
   using F = SliceForm<NT, C16>;
   const int lo_u = __builtin_amdgcn_readfirstlane(lo);
-  const char* base = reinterpret_cast<const char*>(w.coef + (al * F::rows * w.n_bins + lo_u));
   const int q = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  // the base address through readfirstlane, so that the resource is known
+  // to be uniform (otherwise the compiler may loop over lanes to build it)
+  const uint64_t a = reinterpret_cast<uint64_t>(w.coef + (al * F::rows * w.n_bins + lo_u));
+  const uint64_t au = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(a >> 32)) << 32) |
+                      (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)a);
+  const int nb = __builtin_amdgcn_readfirstlane((int)w.n_bins);
+  const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
+      reinterpret_cast<void*>(au), (short)0, (int)(((F::rows - 1) * nb + F::cap) * (int)sizeof(float4)), 0x00020000);
 #pragma unroll
   for (int i = 0; i < F::runs; ++i) {
-    const int e0 = NT * i + 64 * q;                // wave-uniform
-    if (e0 + 64 <= F::total) {
-      lds_dma16(base + so.o[i], buf + e0);
-    } else if (e0 < F::total) {                    // the partial last run
-      if ((int)(threadIdx.x & 63) < F::total - e0) lds_dma16(base + so.o[i], buf + e0);
-    }
+    const int b = i * F::waves + q;                // wave-uniform
+    const int row = b / F::blocks_per_row, c0 = 64 * (b % F::blocks_per_row);
+    float4* dst = buf + row * F::cap + c0;
+    const uint32_t soff = __builtin_amdgcn_readfirstlane((row * nb + c0) * (int)sizeof(float4));
+    if (c0 + 64 <= F::cap || lane16 < 16u * (uint32_t)(F::cap - c0))
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc, (__attribute__((address_space(3))) void*)dst, 16, lane16, soff,
+                                               0, 0);
   }
+}
+
+// 16 x the lane index, kept in a register for the staging addresses (opaque,
+// so that it is not recomputed for every load).
+__device__ __forceinline__ uint32_t lane_bytes16() {
+  uint32_t v = (threadIdx.x & 63u) << 4;
+  __asm__ volatile("" : "+v"(v));
+  return v;
 }
 
 // Waits for this wave's outstanding global loads, the LDS-direct ones included.
@@ -821,13 +813,13 @@ __device__ __forceinline__ void interp_tile(const WuDev& w, int W, int64_t tile,
     }
   }
 
-  const SliceOffsets<F::runs> so = slice_offsets<NT, C16>(w);
   // waves whose frequencies all lie beyond the band's last template only
   // help stage slices
   const bool wave_live = __builtin_amdgcn_readfirstlane((int)(j0 + (tid & ~63) < w.n_f));
   group_meta<NFD, S, NT>(w, geo, arow, brow, al_begin, n < S ? n : S, i0, i_last, f_first, f_last, W, meta[0]);
   __syncthreads();
-  slice_load_lds<NT, C16>(w, so, al_begin, meta[0].lo[0], cbuf0);
+  const uint32_t lane16 = lane_bytes16();
+  slice_load_lds<NT, C16>(w, al_begin, meta[0].lo[0], cbuf0, lane16);
   lds_dma_wait();
   __syncthreads();
   // One SFT per step; the step is written twice (even SFTs read cbuf0 and
@@ -848,7 +840,7 @@ __device__ __forceinline__ void interp_tile(const WuDev& w, int W, int64_t tile,
     // for
     // the other buffer was consumed before the last barrier
     const int k1 = more ? k + 1 : k;
-    slice_load_lds<NT, C16>(w, so, al_begin + k1, meta[(k1 / S) & 1].lo[k1 % S], next);
+    slice_load_lds<NT, C16>(w, al_begin + k1, meta[(k1 / S) & 1].lo[k1 % S], next, lane16);
     const GroupMeta<NFD, S>& m = meta[gq];
     const int64_t al = al_begin + k;
     if constexpr (decltype(live)::value) {
@@ -1106,14 +1098,6 @@ hipError_t launch_geometry(const WuDev& w, GeoStatus* status, hipStream_t st) {
   const int64_t blocks = w.n_sky < 65536 ? w.n_sky : 65536;
   hipLaunchKernelGGL(geometry_kernel, dim3((unsigned)blocks), dim3(256), 0, st, w, status);
   return hipGetLastError();
-}
-
-size_t demod_lds_bytes(const WuDev& w, const Tile& t, int kernel) {
-  if (kernel == KERNEL_INTERP) {
-    const int nt = t.threads == 64 ? 64 : kThreads;
-    return 2 * (size_t)(w.coef16 ? kRuns16 : kMaxRuns) * nt * sizeof(float4);
-  }
-  return (size_t)t.chunk * seg_width(kThreads * t.nf_reg, w.dterms) * sizeof(float2);
 }
 
 int64_t coef_blocks(const WuDev& w) { return ((w.n_bins + 255) / 256) * w.n_sft; }
