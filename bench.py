@@ -71,18 +71,19 @@ def kernel_source_hash() -> str:
 
 
 def measured_traffic(kernel_name: str, workload: str):
-    """HBM bytes per launch of the dominant kernel from the committed
-    rocprofv3 counter summary, if it was taken on the current kernel source."""
+    """HBM bytes of one demodulation pass (all its launches) of the dominant
+    kernel from the committed rocprofv3 counter summary, and the number of
+    launches in the pass, if they were taken on the current kernel source."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as f:
             d = json.load(f)
     except (OSError, ValueError):
-        return None
+        return None, None
     e = d.get(f"{kernel_name}:{workload}")
     if not e or e.get("kernel_source_hash") != kernel_source_hash():
-        return None
-    return e.get("bytes_per_launch")
+        return None, None
+    return e.get("bytes_per_pass"), e.get("launches_per_pass")
 
 
 def cpu_baseline(w, budget_s: float):
@@ -307,6 +308,7 @@ def main():
         del bdevs, bouts
         torch.cuda.empty_cache()
     traffic_key = "semicoherent" if semi_main else "config1"
+    traffic, launches = measured_traffic(f"demod_{kernel}", traffic_key)
     main_form = forms[0]
     r = results[main_form]
     slots = slots_per_pair(kernel, w.dterms) * pairs
@@ -333,14 +335,16 @@ def main():
                       "vs_plain": v["value"] / results[main_form]["value"],
                       "roofline_frac": slots_per_pair(kernel, w.dterms) * pairs / (v["kernel_ms"] * 1e-3) / PEAK_SLOTS,
                       "traffic": measured_traffic("demod_interp_coef16" if k.endswith("+coef16") else f"demod_{kernel}",
-                                                  traffic_key)}
+                                                  traffic_key)[0]}
                   for k, v in results.items()},
         "kernels": kernels,
         "toplist": toplist,
         "semicoherent": semi,
         "batch": batch,
+        # per demodulation pass: all launches of the kernel in one step (the
+        # library may split the SFT loop into several), timed together
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12, "unit": "TOP/s",
-                     "frac": achieved / PEAK_SLOTS, "traffic": measured_traffic(f"demod_{kernel}", traffic_key),
+                     "frac": achieved / PEAK_SLOTS, "traffic": traffic, "launches_per_pass": launches,
                      "kernel": f"demod_{kernel}", "slots_per_pair": slots_per_pair(kernel, w.dterms),
                      "kernel_ms": r["kernel_ms"]},
     }
