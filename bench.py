@@ -62,11 +62,22 @@ def slots_per_pair(kernel: str, dterms: int, nfd: int = 8) -> float:
     raise ValueError(kernel)
 
 
+def strip_comments(src: str) -> str:
+    """C++ source without comments and blank lines (string literals in these
+    sources hold no comment markers)."""
+    import re
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", "", src)
+    return "\n".join(l.rstrip() for l in src.splitlines() if l.strip())
+
+
 def kernel_source_hash() -> str:
+    """Hash of the kernel sources' code (comments excluded), which ties a
+    counter summary to the kernels it was taken on."""
     h = hashlib.sha256()
     for f in ("fstat_kernels.hip", "fstat_internal.h"):
-        with open(os.path.join(ROOT, "paper_0904_1826_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_0904_1826_amd", "csrc", f), encoding="utf-8") as fh:
+            h.update(strip_comments(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

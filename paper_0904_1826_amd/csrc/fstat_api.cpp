@@ -317,9 +317,9 @@ std::string class_key(const fstat_plan* p, const fstat_wu* w) {
 // by up to |dfdot| (NFD-1) max|tau| T Tdot more; plus slack, rounded to 4.
 // Lanes whose window falls outside the slice read their coefficients from
 // global memory instead, so a narrower slice costs speed, not correctness;
-// the slice is capped at what the staging runs fill: 5 NT / 4 bins (40 KB of
-// LDS, double-buffered, for 256 threads) or 3 NT / 2 bins with FP16
-// coefficients (24 KB).
+// the slice is capped at the LDS row length: NT + NT / 8 + 8 bins (296 for
+// 256 threads: 37 KB of LDS, double-buffered) or 3 NT / 2 bins with FP16
+// coefficients (384: 24 KB).
 int interp_seg_tau(const fstat_wu* w, int nfd, int threads, bool c16, double max_abs_tau) {
   const double tdot = 1.001;
   const double nt = threads;

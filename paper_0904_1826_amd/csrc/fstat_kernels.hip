@@ -753,12 +753,12 @@ __device__ __forceinline__ v4f lds_load_v(LdsPtr p, int i) { return p[i]; }
 
 // Demodulation over SFTs [al_begin, al_end) for tiles of (sky s, NFD
 // spindowns, NT frequencies), sky point fastest, one tile per work-group.
-// The host may split the SFT loop into launches of a few dozen SFTs: the
-// work-groups of one launch then share the coefficient slices of a few dozen
-// SFTs (the same frequency tile, offset by each sky point's Doppler shift),
-// which stay in L2; Fa, Fb carry over between launches in `acc`.  Within a
-// launch the slices (one SFT each) are double-buffered in LDS: the loads of
-// SFT k+1 are in flight in registers while SFT k is evaluated, with one
+// The host may split the SFT loop into launches of a few hundred SFTs: the
+// work-groups resident at once then stay on nearby SFTs and share their
+// coefficient slices (the same frequency tile, offset by each sky point's
+// Doppler shift) in L2; Fa, Fb carry over between launches in `acc`.  Within
+// a launch the slices (one SFT each) are double-buffered in LDS: the loads of
+// SFT k+1 go straight to the idle buffer while SFT k is evaluated, with one
 // barrier per SFT.  The per-SFT values shared by the
 // work-group are prepared S SFTs at a time by all threads, one group ahead.
 // Each thread owns one frequency at NFD spindowns: per SFT it forms
