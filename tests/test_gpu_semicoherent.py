@@ -13,7 +13,7 @@ import pytest
 import oracle
 import synth
 from synth.device import to_device, alloc_output, host_values
-from tests._helpers import twoF_error
+from tests._helpers import twoF_error, replace
 
 pytestmark = pytest.mark.gpu
 
@@ -184,3 +184,47 @@ def test_semicoherent_full_size_20_segments(torch_cuda, coef):
         assert peak > 80 + 0.5 * 20 * x.snr ** 2, (x, peak)
     _say(f"  sampled max 2F-sum error {worst:.2e}")
     assert worst <= (5e-3 if coef == "f16" else 1e-4)
+
+
+def test_semicoherent_from_device_detector_inputs(torch_cuda):
+    """The whole chain on the device: each segment's detector positions,
+    velocities and antenna patterns from fstat_detector_inputs (orbit model
+    with the diurnal term), then the semi-coherent sum; against the oracle's
+    detector inputs and the oracle's sum on them."""
+    import math
+    import synth.workloads as sw
+    import paper_0904_1826_amd as P
+    torch = torch_cuda
+    earth = dict(t0=sw.EPOCH, orbit_radius=sw.ORBIT_R, orbit_rate=sw.ORBIT_OMEGA, orbit_phase=0.3,
+                 obliquity=sw.OBLIQUITY, earth_radius=6378137.0 / 299792458.0, sidereal_rate=sw.SIDEREAL_OMEGA,
+                 sidereal_phase=0.7)
+    sites = [tuple(math.radians(x) for x in (lat, lon, az)) + (math.radians(az + 90.0),) for lat, lon, az in sw.SITES]
+    segs = _segments(3, 77, injections=[])
+    dev = lambda x, dt: torch.from_numpy(np.ascontiguousarray(x, dtype=dt)).cuda()
+    segs2, segs_ref = [], []
+    with P.Plan(max_sft=max(w.n_sft for w in segs), max_bins=max(w.n_bins for w in segs), max_sky=segs[0].n_sky,
+                max_fd=segs[0].n_fd, max_f=segs[0].n_f) as p:
+        for w in segs:
+            t_mid = w.t_start + 0.5 * w.t_sft
+            idx = np.zeros(w.n_sft, np.int32)
+            idx[w.det_offset[1]:] = 1
+            pos = torch.empty((w.n_sft, 3), dtype=torch.float64, device="cuda")
+            vel = torch.empty_like(pos)
+            a = torch.empty((w.n_sky, w.n_sft), dtype=torch.float32, device="cuda")
+            b = torch.empty_like(a)
+            p.detector_inputs(earth, sites, dev(t_mid, np.float64), dev(idx, np.int32), dev(w.sky, np.float64),
+                              pos, vel, a, b)
+            torch.cuda.synchronize()
+            segs2.append(replace(w, pos=pos.cpu().numpy(), vel=vel.cpu().numpy(), a=a.cpu().numpy(),
+                                 b=b.cpu().numpy()))
+            rp, rv, ra, rb = oracle.detector_inputs(earth, sites, t_mid, idx, w.sky)
+            segs_ref.append(replace(w, pos=rp, vel=rv, a=ra.astype(np.float32), b=rb.astype(np.float32)))
+        devs = [to_device(w)[0] for w in segs2]
+        out = alloc_output(segs2[0])
+        p.semicoherent(devs, out)
+        torch.cuda.synchronize()
+    got = out.twoF.cpu().numpy().ravel().astype(np.float64)
+    e = twoF_error(got, oracle.semicoherent(segs2)["twoF"])
+    e_ref = twoF_error(got, oracle.semicoherent(segs_ref)["twoF"])
+    _say(f"device detector inputs + semi-coherent sum: max error {e.max():.2e} (oracle inputs: {e_ref.max():.2e})")
+    assert e.max() <= 1e-4 and e_ref.max() <= 1e-4
