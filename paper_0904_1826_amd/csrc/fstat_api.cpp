@@ -248,8 +248,12 @@ double host_sinc(double x) { return x == 0.0 ? 1.0 : sin(M_PI * x) / (M_PI * x);
 // projection of sinc(kappa + m) on kappa in [0, 1], for m = -D .. D-1:
 // Chebyshev coefficients from 64 Chebyshev nodes (discrete cosine sums), the
 // three-term recurrence T_{j+1} = 2u T_j - T_{j-1} to monomials of
-// u = 2 kappa - 1, then the binomial expansion of (2 kappa - 1)^q.
-std::vector<double> sinc_poly_table(int D) {
+// u = 2 kappa - 1, then the binomial expansion of (2 kappa - 1)^q, or, for
+// the FP16 form (centred), monomials of v = kappa - 1/2 = u / 2: its
+// polynomials are evaluated in FP16, where |v| <= 1/2 rounds to half the
+// absolute error of kappa and the centred basis has the smaller coefficient
+// sums.
+std::vector<double> sinc_poly_table(int D, bool centred) {
   const int N = 64, P = fstat::kCoef;
   std::vector<double> tab((size_t)2 * D * P, 0.0);
   std::vector<std::vector<double>> Tm(P, std::vector<double>(P, 0.0));
@@ -272,6 +276,10 @@ std::vector<double> sinc_poly_table(int D) {
     for (int j = 0; j < P; ++j)
       for (int q = 0; q < P; ++q) cu[q] += a[j] * Tm[j][q];
     double* row = &tab[(size_t)(m + D) * P];
+    if (centred) {                    // cu[q] u^q = cu[q] 2^q v^q
+      for (int q = 0; q < P; ++q) row[q] = cu[q] * ldexp(1.0, q);
+      continue;
+    }
     for (int q = 0; q < P; ++q) {     // cu[q] (2 kappa - 1)^q = cu[q] sum_r C(q,r) 2^r kappa^r (-1)^(q-r)
       double binom = 1.0;
       for (int r = 0; r <= q; ++r) {
@@ -285,7 +293,7 @@ std::vector<double> sinc_poly_table(int D) {
 
 int ensure_ctab(fstat_plan* p, int D) {
   if (p->ctab.count(D)) return FSTAT_OK;
-  std::vector<double> tab = sinc_poly_table(D);
+  std::vector<double> tab = sinc_poly_table(D, coef16(p));
   void* d = nullptr;
   size_t have = 0;
   int rc = dev_alloc(p, &d, &have, tab.size() * sizeof(double), "polynomial table");

@@ -25,7 +25,8 @@ struct WuDev {
   int32_t* cexp;           // coef16: per-SFT exponent e, coefficients stored times 2^-e
   double csum;             // coef16: max_p sum_m |t[m][p]| of the table (bounds |c_p| / max|x|)
   int32_t coef16;
-  const double* ctab;      // interp kernel: [2D][kCoef] polynomial coefficients of sinc(kappa+m)
+  const double* ctab;      // interp kernel: [2D][kCoef] polynomial coefficients of sinc(kappa+m), in
+                           // kappa, or in kappa - 1/2 for the FP16 form
   float4* acc;             // interp kernel scratch: running (Fa, Fb) per template between SFT blocks
   // toplist: templates with 2F >= threshold are appended to cand (2F bits,
   // 0, linear index lo, hi) through the counter cand_count; NULL: no toplist

@@ -489,8 +489,9 @@ __global__ __launch_bounds__(256) void coef_batch_kernel(const BatchEntry* __res
 }
 
 // Per-SFT exponent of the FP16 coefficient form: e = (binary exponent of
-// max|x| csum) - 15, max over the SFT's bins of max(|re|, |im|), so that every
-// stored coefficient |c 2^-e| <= 2^15 < 65504 (the FP16 range).  An all-zero
+// max|x| csum) - 12, max over the SFT's bins of max(|re|, |im|), so that every
+// stored coefficient |c 2^-e| <= 2^12 and the Horner partial sums of a bin's
+// eight coefficients stay below 2^15 < 65504 (the FP16 range).  An all-zero
 // SFT gets 0; e is clamped to [-120, 120].
 __device__ __forceinline__ void cexp_sft(const WuDev& w, int64_t al, float* red) {
   float mx = 0.f;
@@ -507,7 +508,7 @@ __device__ __forceinline__ void cexp_sft(const WuDev& w, int64_t al, float* red)
     if (m > 0.0) {
       int ex = 121;
       if (m < 1e300) (void)frexp(m, &ex);
-      e = ex - 15;
+      e = ex - 12;
       e = e < -120 ? -120 : (e > 120 ? 120 : e);
     }
     w.cexp[al] = e;
@@ -725,24 +726,33 @@ __device__ __forceinline__ void interp_accumulate(float4 c01, float4 c23, float4
 }
 
 // The same with the FP16 coefficient form: two float4-sized rows hold c0..c3
-// and c4..c7 as FP16 (re, im) pairs; each Horner step is one FP32 fused
-// multiply-add whose addend is read as FP16.
+// and c4..c7 as FP16 (re, im) pairs of the polynomial in v = kappa - 1/2.
+// The Horner steps run in packed FP16 (one v_pk_fma_f16 per step for the
+// real and imaginary parts, v rounded to FP16); the rotation reads the FP16
+// result directly in mixed FP32 fused multiply-adds, and Fa, Fb accumulate in
+// FP32.  The per-SFT scale 2^-e keeps every partial sum of the Horner scheme
+// below 2^15 (no FP16 overflow).
 __device__ __forceinline__ void interp_accumulate16(v4f r0, v4f r1, float u, float cf, float sf, float2 eq, float a,
                                                     float b, float& far, float& fai, float& fbr, float& fbi) {
   // whole rows are reinterpreted (bit-casting single vector elements is not
   // reliable): lo[2p], lo[2p+1] = re, im of c_p, hi likewise for c_{p+4}
   const h8v lo = __builtin_bit_cast(h8v, r0), hi = __builtin_bit_cast(h8v, r1);
-  float gr = __builtin_fmaf((float)hi[6], u, (float)hi[4]), gi = __builtin_fmaf((float)hi[7], u, (float)hi[5]);
-  gr = __builtin_fmaf(gr, u, (float)hi[2]); gi = __builtin_fmaf(gi, u, (float)hi[3]);
-  gr = __builtin_fmaf(gr, u, (float)hi[0]); gi = __builtin_fmaf(gi, u, (float)hi[1]);
-  gr = __builtin_fmaf(gr, u, (float)lo[6]); gi = __builtin_fmaf(gi, u, (float)lo[7]);
-  gr = __builtin_fmaf(gr, u, (float)lo[4]); gi = __builtin_fmaf(gi, u, (float)lo[5]);
-  gr = __builtin_fmaf(gr, u, (float)lo[2]); gi = __builtin_fmaf(gi, u, (float)lo[3]);
-  gr = __builtin_fmaf(gr, u, (float)lo[0]); gi = __builtin_fmaf(gi, u, (float)lo[1]);
+  const _Float16 k16 = (_Float16)(u - 0.5f);
+  const h2v k = {k16, k16};
+  h2v g = {hi[6], hi[7]};
+  g = __builtin_elementwise_fma(g, k, (h2v){hi[4], hi[5]});
+  g = __builtin_elementwise_fma(g, k, (h2v){hi[2], hi[3]});
+  g = __builtin_elementwise_fma(g, k, (h2v){hi[0], hi[1]});
+  g = __builtin_elementwise_fma(g, k, (h2v){lo[6], lo[7]});
+  g = __builtin_elementwise_fma(g, k, (h2v){lo[4], lo[5]});
+  g = __builtin_elementwise_fma(g, k, (h2v){lo[2], lo[3]});
+  g = __builtin_elementwise_fma(g, k, (h2v){lo[0], lo[1]});
+  const float gr = (float)g.x, gi = (float)g.y;
   const float er = __builtin_fmaf(cf, eq.x, sf * eq.y);
   const float ei = __builtin_fmaf(cf, eq.y, -sf * eq.x);
-  const float zr = __builtin_fmaf(gr, er, -gi * ei);
-  const float zi = __builtin_fmaf(gr, ei, gi * er);
+  // written as fused multiply-adds so that the FP16 operands stay unconverted
+  const float zr = __builtin_fmaf(gr, er, __builtin_fmaf(gi, -ei, 0.0f));
+  const float zi = __builtin_fmaf(gr, ei, __builtin_fmaf(gi, er, 0.0f));
   far = __builtin_fmaf(a, zr, far);
   fai = __builtin_fmaf(a, zi, fai);
   fbr = __builtin_fmaf(b, zr, fbr);
