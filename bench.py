@@ -43,10 +43,12 @@ HBM_PEAK = 8.0e12
 METRIC = "templates\u00b7SFTs/s for 2F (plain vs mixed-precision) at 2F rel err \u22641e-4; % roofline"
 
 
-def slots_per_pair(kernel: str, dterms: int, nfd: int = 8) -> float:
+def slots_per_pair(kernel: str, dterms: int, nfd: int = 8, coef16: bool = False) -> float:
     """Algorithmic VALU slots per (template, SFT) pair of each kernel's
     formulation (instruction count of the arithmetic the method needs; no
-    addressing, staging or loop control)."""
+    addressing, staging or loop control).  With FP16 coefficients the Horner
+    steps are packed FP16 FMAs (real and imaginary part in one slot) and v is
+    rounded to FP16 once."""
     if kernel == "direct":
         # FP64 Dphi (fma), k*, kappa, 1 - kappa and phase: 10; sign 3;
         # central weights 12 (sin and two reciprocals at 2 slots) and their
@@ -58,7 +60,7 @@ def slots_per_pair(kernel: str, dterms: int, nfd: int = 8) -> float:
         # complex Horner 14, phase factor product 4 + rotation 4, Fa/Fb 4;
         # frac(tau f) and its sin/cos (3 + 2 x 2) shared by the nfd spindowns
         # of a thread
-        return 30 + 7.0 / nfd
+        return (30 + 7.0 / nfd) if not coef16 else (30 - 7 + 1 + 7.0 / nfd)
     raise ValueError(kernel)
 
 
@@ -270,7 +272,8 @@ def main():
                 el = time.perf_counter() - t_start
             semi["coef16" if coef == "f16" else "plain"] = {
                 "value": 2 * spairs / el, "ms_per_step": 1e3 * el / 2, "kernel_ms": float(np.mean(kms)),
-                "roofline_frac": slots_per_pair(kernel, segs[0].dterms) * spairs / (np.mean(kms) * 1e-3) / PEAK_SLOTS,
+                "roofline_frac": slots_per_pair(kernel, segs[0].dterms, coef16=coef == "f16") * spairs
+                / (np.mean(kms) * 1e-3) / PEAK_SLOTS,
                 "err_bound": 5e-3 if coef == "f16" else 1e-4}
         print(f"[bench] semi-coherent ({gen_s:.1f} s to generate): {semi}", file=sys.stderr, flush=True)
         del devs, out
@@ -296,8 +299,9 @@ def main():
             lanes8 = x.n_fd if rem > 4 else x.n_fd - rem
             nfd_mix[8] += x.n_sky * lanes8 * x.n_f * x.n_sft
             nfd_mix[4] += x.n_sky * (x.n_fd - lanes8) * x.n_f * x.n_sft
-        slots_b = (slots_per_pair(kernel, 8, 8) * nfd_mix[8] + slots_per_pair(kernel, 8, 4) * nfd_mix[4]) / bpairs
         for coef in ("f32", "f16"):
+            c16 = coef == "f16"
+            slots_b = (slots_per_pair(kernel, 8, 8, c16) * nfd_mix[8] + slots_per_pair(kernel, 8, 4, c16) * nfd_mix[4]) / bpairs
             with P.Plan(max_sft=max(x.n_sft for x in bws), max_bins=max(x.n_bins for x in bws),
                         max_sky=max(x.n_sky for x in bws), max_fd=max(x.n_fd for x in bws),
                         max_f=max(x.n_f for x in bws), max_dterms=16, storage=storage, coef=coef) as plan:
@@ -311,18 +315,19 @@ def main():
                 el = (time.perf_counter() - t_start) / reps
             key = "coef16" if coef == "f16" else "plain"
             batch[key] = {"value": bpairs / el, "s_per_step": el, "kernel_s": float(np.mean(kms)) / 1e3,
+                          "slots_per_pair": slots_b,
                           "roofline_frac": slots_b * bpairs / (np.mean(kms) * 1e-3) / PEAK_SLOTS,
                           "err_bound": 5e-3 if (coef == "f16" or storage != "c64") else 1e-4}
             print(f"[bench] batch {key}: {batch[key]}", file=sys.stderr, flush=True)
         batch["coef16_vs_plain"] = batch["coef16"]["value"] / batch["plain"]["value"]
-        batch["slots_per_pair"] = slots_b
         del bdevs, bouts
         torch.cuda.empty_cache()
     traffic_key = "semicoherent" if semi_main else "config1"
-    traffic, launches = measured_traffic(f"demod_{kernel}", traffic_key)
     main_form = forms[0]
     r = results[main_form]
-    slots = slots_per_pair(kernel, w.dterms) * pairs
+    main_c16 = main_form.endswith("+coef16")
+    traffic, launches = measured_traffic("demod_interp_coef16" if main_c16 else f"demod_{kernel}", traffic_key)
+    slots = slots_per_pair(kernel, w.dterms, coef16=main_c16) * pairs
     achieved = slots / (r["kernel_ms"] * 1e-3)
     line = {
         "metric": METRIC,
@@ -344,7 +349,8 @@ def main():
         "forms": {k: {"value": v["value"], "ms_per_step": v["ms_per_step"], "kernel_ms": v["kernel_ms"],
                       "err_bound": v["err_bound"],
                       "vs_plain": v["value"] / results[main_form]["value"],
-                      "roofline_frac": slots_per_pair(kernel, w.dterms) * pairs / (v["kernel_ms"] * 1e-3) / PEAK_SLOTS,
+                      "roofline_frac": slots_per_pair(kernel, w.dterms, coef16=k.endswith("+coef16")) * pairs
+                      / (v["kernel_ms"] * 1e-3) / PEAK_SLOTS,
                       "traffic": measured_traffic("demod_interp_coef16" if k.endswith("+coef16") else f"demod_{kernel}",
                                                   traffic_key)[0]}
                   for k, v in results.items()},
@@ -356,7 +362,7 @@ def main():
         # library may split the SFT loop into several), timed together
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12, "unit": "TOP/s",
                      "frac": achieved / PEAK_SLOTS, "traffic": traffic, "launches_per_pass": launches,
-                     "kernel": f"demod_{kernel}", "slots_per_pair": slots_per_pair(kernel, w.dterms),
+                     "kernel": f"demod_{kernel}", "slots_per_pair": slots_per_pair(kernel, w.dterms, coef16=main_c16),
                      "kernel_ms": r["kernel_ms"]},
     }
     if not args.no_cpu_baseline and not semi_main:
