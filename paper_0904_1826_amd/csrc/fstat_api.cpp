@@ -347,12 +347,13 @@ Tile default_tile(const fstat_plan* p, const fstat_wu* w) {
     // 5 to 7 spindowns: one partial block of 8 costs no more lanes than two of 4
     const int nfd = w->n_fd >= 5 ? 8 : (w->n_fd >= 3 ? 4 : (w->n_fd >= 2 ? 2 : 1));
     // measured on the work-unit-shaped case: 8 spindowns per thread with room
-    // for 4 waves per SIMD is fastest.  Splitting the SFT loop into launches
+    // for 4 waves per SIMD (5 with FP16 coefficients, whose slices and packed
+    // FP16 polynomials take fewer registers and less LDS) is fastest.  Splitting the SFT loop into launches
     // keeps the resident work-groups on nearby SFTs, so their slices stay in
     // L2: with FP32 coefficients launches of 512 SFTs took the case from 125.1
     // to 122.7 ms (L2 hit rate 0.62 -> 0.91); with fewer spindowns per thread
     // the staged slices are reused less and shorter launches pay more
-    const int minw = nfd == 8 ? 4 : 3;
+    const int minw = nfd == 8 ? (coef16(p) ? 5 : 4) : 3;
     const int sb = nfd < 4 ? 256 : (nfd == 8 && !coef16(p) && w->n_sft > 1024 ? 512 : 0);
     return Tile{nfd, minw, 0, sb, fstat::kThreads};
   }
@@ -925,8 +926,9 @@ static bool valid_tile(const fstat_plan* p, const Tile& t) {
   if (t.sblock < 0) return false;
   if (resolved_kernel(p) == fstat::KERNEL_INTERP) {
     const bool nf_ok = t.nf_reg == 8 || t.nf_reg == 4 || t.nf_reg == 2 || t.nf_reg == 1;
-    // 4 waves per SIMD: 256-thread tiles with 8 spindowns per thread
-    const bool w_ok = t.chunk == 2 || t.chunk == 3 || (t.chunk == 4 && t.nf_reg == 8 && t.threads == 256);
+    // 4 (FP16 coefficients: 4 or 5) waves per SIMD: 256-thread tiles with 8 spindowns per thread
+    const bool wide = t.nf_reg == 8 && t.threads == 256 && (t.chunk == 4 || (t.chunk == 5 && coef16(p)));
+    const bool w_ok = t.chunk == 2 || t.chunk == 3 || wide;
     if (coef16(p))   // 256-thread tiles
       return nf_ok && w_ok && t.threads == 256;
     return nf_ok && w_ok && (t.threads == 256 || (t.threads == 64 && t.nf_reg >= 4));
@@ -1005,7 +1007,7 @@ int fstat_autotune(fstat_plan* p, const fstat_wu* wu, const fstat_out* out, void
   if (resolved_kernel(p) == fstat::KERNEL_INTERP) {
     for (int nt : {256, 64})
       for (int nfd : {8, 4, 2, 1})
-        for (int minw : {2, 3, 4})
+        for (int minw : {2, 3, 4, 5})
           for (int sb : {64, 256, 512, 0}) {
             const Tile t{nfd, minw, 0, sb, nt};
             if ((nfd <= 2 * wu->n_fd || nfd == 1) && (nfd == 8 || minw == 3) && valid_tile(p, t)) cands.push_back(t);

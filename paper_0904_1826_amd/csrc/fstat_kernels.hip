@@ -954,7 +954,7 @@ __global__ __launch_bounds__(NT, MINW) void demod_interp_kernel(WuDev w, int W, 
 // thread), so that each specialisation keeps the registers, and hence the
 // occupancy, of the single-unit kernel.
 template <int NFD, bool C16>
-__global__ __launch_bounds__(kThreads, NFD == 8 ? 4 : 3) void demod_interp_batch_kernel(
+__global__ __launch_bounds__(kThreads, NFD == 8 ? (C16 ? 5 : 4) : 3) void demod_interp_batch_kernel(
     const BatchEntry* __restrict__ ents, int n_ent, int64_t total_tiles, unsigned long long* counter) {
   using F = SliceForm<kThreads, C16>;
   constexpr int S = C16 ? 16 : 8;                  // per-SFT values per group: four work-groups' LDS fits a CU
@@ -1226,7 +1226,8 @@ static hipError_t launch_interp_range(const WuDev& w, const Tile& t, hipStream_t
   if (w.coef16) {
     if (t.threads == 64) return hipErrorInvalidValue;
     switch (t.nf_reg) {
-      case 8: return t.chunk >= 4 ? launch_interp_t<8, 16, 4, 4, kThreads, true>(w, t, st, fd0, fd1)
+      case 8: return t.chunk >= 5 ? launch_interp_t<8, 16, 5, 4, kThreads, true>(w, t, st, fd0, fd1)
+                   : t.chunk >= 4 ? launch_interp_t<8, 16, 4, 4, kThreads, true>(w, t, st, fd0, fd1)
                      : w3         ? launch_interp_t<8, 16, 3, 4, kThreads, true>(w, t, st, fd0, fd1)
                                   : launch_interp_t<8, 16, 2, 4, kThreads, true>(w, t, st, fd0, fd1);
       case 4: return w3 ? launch_interp_t<4, 16, 3, 4, kThreads, true>(w, t, st, fd0, fd1)
