@@ -72,11 +72,12 @@ extern "C" {
 /* fstat_desc.flags */
 #define FSTAT_FLAG_NO_GRAPH 1     /* batched: launch directly, no hipGraph */
 /* Mixed-precision form of the interp kernel: the per-bin window polynomials
- * (see fstat_compute) are stored as FP16 with a per-SFT power-of-two scale
- * and evaluated with FP32 arithmetic; half the coefficient bytes per
- * (template, SFT) pair.  2F agrees with the FP64 oracle to a relative error of
- * 5e-3 instead of 1e-4.  Not available with FSTAT_KERNEL_DIRECT
- * (FSTAT_E_UNSUPPORTED at plan creation). */
+ * (see fstat_compute), written in kappa - 1/2, are stored as FP16 with a
+ * per-SFT power-of-two scale and evaluated in packed FP16 arithmetic; the
+ * phase rotation and the sums over SFTs stay FP32.  Half the coefficient
+ * bytes and fewer vector instructions per (template, SFT) pair.  2F agrees
+ * with the FP64 oracle to a relative error of 5e-3 instead of 1e-4.  Not
+ * available with FSTAT_KERNEL_DIRECT (FSTAT_E_UNSUPPORTED at plan creation). */
 #define FSTAT_FLAG_COEF16 2
 
 /* --------------------------------------------------------- structures --- */
