@@ -677,6 +677,9 @@ __device__ __forceinline__ void slice_load_lds(const WuDev& w, int64_t al, int l
   const uint64_t au = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(a >> 32)) << 32) |
                       (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)a);
   const int nb = __builtin_amdgcn_readfirstlane((int)w.n_bins);
+  // raw buffer: stride 0, size in bytes (offsets at or past it read 0), and
+  // the descriptor's last word with a 32-bit data format (0x00020000), as
+  // the buffer instructions of this architecture expect for untyped loads
   const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
       reinterpret_cast<void*>(au), (short)0, (int)(((F::rows - 1) * nb + F::cap) * (int)sizeof(float4)), 0x00020000);
 #pragma unroll
