@@ -32,6 +32,7 @@ struct fstat_plan {
   fstat::GeoStatus* status_d = nullptr;
   fstat::GeoStatus* status_h = nullptr;  // pinned
   double max_abs_tau = 0.0;               // from the last geometry pass
+  double max_p = 0.0;                     // max Tdot T, from the last geometry pass
   // interp kernel: coefficient scratch and per-Dterms polynomial tables
   void* coef = nullptr;
   size_t coef_bytes = 0;
@@ -74,7 +75,9 @@ struct fstat_plan {
   size_t ents_cap = 0;
   unsigned long long* counter = nullptr;
   hipStream_t cap_stream = nullptr;
-  int batch_grid = 0, batch_grid4 = 0;   // persistent grids of the 8- and 4-spindown batch kernels
+  // persistent grids of the 8- and 4-spindown batch kernels, with [1] and
+  // without [0] the global-memory fallback
+  int batch_grid[2] = {0, 0}, batch_grid4[2] = {0, 0};
   std::map<std::vector<int64_t>, hipGraphExec_t> graphs;
   // fault injection (host-side forcing of error paths)
   long fail_malloc_at = -1, fail_launch_at = -1;
@@ -328,18 +331,25 @@ std::string class_key(const fstat_plan* p, const fstat_wu* w) {
 // the slice is capped at the LDS row length: NT + NT / 8 + 8 bins (296 for
 // 256 threads: 37 KB of LDS, double-buffered) or 3 NT / 2 bins with FP16
 // coefficients (384: 24 KB).
-int interp_seg_tau(const fstat_wu* w, int nfd, int threads, bool c16, double max_abs_tau) {
-  const double tdot = 1.001;
+//
+// With max_p = max Tdot T of the geometry pass, D-hat-phi varies over a tile
+// by at most `spread` bins, so k* by at most spread + 1; the slice starts one
+// bin below the tile's lowest k* and every window lies in it when
+// W >= spread + 3.  W >= spread + 4 here whenever the cap did not bind, and
+// *fits reports that: the kernel without the global-memory fallback may run.
+int interp_seg_tau(const fstat_wu* w, int nfd, int threads, bool c16, double max_abs_tau, double max_p,
+                   bool* fits) {
   const double nt = threads;
-  const double spread = ((nt - 1.0) * w->df + fabs(w->dfdot) * (nfd - 1) * max_abs_tau) * w->t_sft * tdot;
+  const double spread = ((nt - 1.0) * w->df + fabs(w->dfdot) * (nfd - 1) * max_abs_tau) * max_p;
   const double width = nt + 6.0 + ceil(spread - (nt - 1.0) > 0 ? spread - (nt - 1.0) : 0.0);
   const int cap = fstat::interp_max_seg(threads, c16);
-  int W = width > cap ? cap : (int)width;
+  if (fits) *fits = std::isfinite(width) && width <= cap;
+  int W = !(width <= cap) ? cap : (int)width;
   return W & ~3;
 }
 
-int interp_seg(const fstat_plan* p, const fstat_wu* w, int nfd, int threads) {
-  return interp_seg_tau(w, nfd, threads, coef16(p), p->max_abs_tau);
+int interp_seg(const fstat_plan* p, const fstat_wu* w, int nfd, int threads, bool* fits) {
+  return interp_seg_tau(w, nfd, threads, coef16(p), p->max_abs_tau, p->max_p, fits);
 }
 
 Tile default_tile(const fstat_plan* p, const fstat_wu* w) {
@@ -364,10 +374,12 @@ Tile pick_tile(const fstat_plan* p, const fstat_wu* w) {
   auto it = p->tiles.find(class_key(p, w));
   Tile t = it != p->tiles.end() ? it->second : default_tile(p, w);
   if (resolved_kernel(p) == fstat::KERNEL_INTERP) {
-    t.seg = interp_seg(p, w, t.nf_reg, t.threads);
+    bool fits = false, fits4 = true;
+    t.seg = interp_seg(p, w, t.nf_reg, t.threads, &fits);
     // 8 spindowns per thread and 1 to 4 left over: those run 4 per thread
     const int64_t rem = w->n_fd % 8;
-    t.seg4 = (t.nf_reg == 8 && w->n_fd > 8 && rem >= 1 && rem <= 4) ? interp_seg(p, w, 4, t.threads) : 0;
+    t.seg4 = (t.nf_reg == 8 && w->n_fd > 8 && rem >= 1 && rem <= 4) ? interp_seg(p, w, 4, t.threads, &fits4) : 0;
+    t.fast = fits && fits4;
   }
   return t;
 }
@@ -413,6 +425,8 @@ int run_geometry(fstat_plan* p, const WuDev& v, hipStream_t st, int idx) {
   const int st_bits = p->status_h->flags;
   unsigned long long tb = p->status_h->max_abs_tau_bits;
   memcpy(&p->max_abs_tau, &tb, sizeof tb);
+  tb = p->status_h->max_p_bits;
+  memcpy(&p->max_p, &tb, sizeof tb);
   char tag[32] = "";
   if (idx >= 0) snprintf(tag, sizeof tag, "work unit %d: ", idx);
   if (st_bits & 1) return set_err(p, FSTAT_E_BAND, "%sa Dirichlet window [k*-D+1, k*+D] leaves the stored band", tag);
@@ -514,6 +528,12 @@ double status_tau(const fstat::GeoStatus& g) {
   return t;
 }
 
+double status_p(const fstat::GeoStatus& g) {
+  double t;
+  memcpy(&t, &g.max_p_bits, sizeof t);
+  return t;
+}
+
 // Batched interp path: work units are grouped so that one group's scratch
 // (geometry, A,B,C, coefficients) fits the budget; per group the geometry is
 // computed and checked, the work-unit table is uploaded, and the coefficient
@@ -563,9 +583,11 @@ int batch_interp(fstat_plan* p, const fstat_wu* wus, int n, const fstat_out* out
                    "toplist counters");
     if (rc) return rc;
   }
-  if (!p->batch_grid) {
-    p->batch_grid = fstat::interp_batch_grid(coef16(p), 8);
-    p->batch_grid4 = fstat::interp_batch_grid(coef16(p), 4);
+  if (!p->batch_grid[0]) {
+    for (int sf = 0; sf < 2; ++sf) {
+      p->batch_grid[sf] = fstat::interp_batch_grid(coef16(p), 8, sf == 0);
+      p->batch_grid4[sf] = fstat::interp_batch_grid(coef16(p), 4, sf == 0);
+    }
   }
   // every work unit is checked before anything is demodulated
   if (groups.size() > 1) {
@@ -622,6 +644,7 @@ int batch_interp(fstat_plan* p, const fstat_wu* wus, int n, const fstat_out* out
     }
     int m8 = 0, m4 = 0;
     int64_t tiles8 = 0, tiles4 = 0;
+    bool fast8 = true, fast4 = true;      // every entry of the table holds its windows in the slice
     for (int nfd : {8, 4}) {
       for (int q = 0; q < m; ++q) {
         const int k = order[q];
@@ -634,7 +657,11 @@ int batch_interp(fstat_plan* p, const fstat_wu* wus, int n, const fstat_out* out
         e.nfd = nfd;
         e.fd_begin = (int32_t)lo;
         e.fd_end = (int32_t)hi;
-        e.seg = interp_seg_tau(&wus[k], nfd, fstat::kThreads, coef16(p), status_tau(p->bstat_h[k]));
+        bool fits = false;
+        e.seg = interp_seg_tau(&wus[k], nfd, fstat::kThreads, coef16(p), status_tau(p->bstat_h[k]),
+                               status_p(p->bstat_h[k]), &fits);
+        e.fast = fits ? 1 : 0;
+        (nfd == 8 ? fast8 : fast4) &= fits;
         e.n_tiles = fstat::interp_tiles(e.w, nfd, lo, hi);
         int64_t& tiles = nfd == 8 ? tiles8 : tiles4;
         e.tile_begin = tiles;
@@ -662,11 +689,12 @@ int batch_interp(fstat_plan* p, const fstat_wu* wus, int n, const fstat_out* out
       }
       rc = check_launch(p, fstat::launch_coef_batch(ed, m, blocks, c16, st), "coefficient kernel");
       if (rc) return rc;
-      rc = check_launch(p, fstat::launch_interp_batch(ed + m, m8, tiles8, p->counter, p->batch_grid, c16, 8, st),
+      rc = check_launch(p, fstat::launch_interp_batch(ed + m, m8, tiles8, p->counter, p->batch_grid[fast8 ? 0 : 1],
+                                                      c16, 8, fast8, st),
                         "batch kernel");
       if (rc) return rc;
-      rc = check_launch(p, fstat::launch_interp_batch(ed + m + m8, m4, tiles4, p->counter + 1, p->batch_grid4, c16, 4,
-                                                      st),
+      rc = check_launch(p, fstat::launch_interp_batch(ed + m + m8, m4, tiles4, p->counter + 1,
+                                                      p->batch_grid4[fast4 ? 0 : 1], c16, 4, fast4, st),
                         "batch kernel");
       if (rc) return rc;
       rc = check_launch(p, fstat::launch_top_select_batch(ed, m, gcand, p->cand_cap, max_top_k, st),
@@ -674,7 +702,7 @@ int batch_interp(fstat_plan* p, const fstat_wu* wus, int n, const fstat_out* out
       if (rc) return rc;
       continue;
     }
-    const std::vector<int64_t> sig = {(int64_t)(intptr_t)ed, m, m8, m4, blocks, tiles8, tiles4, p->batch_grid, sfts,
+    const std::vector<int64_t> sig = {(int64_t)(intptr_t)ed, m, m8, m4, blocks, tiles8, tiles4, fast8, fast4, sfts,
                                       max_top_k};
     auto it = p->graphs.find(sig);
     if (it == p->graphs.end()) {
@@ -687,10 +715,11 @@ int batch_interp(fstat_plan* p, const fstat_wu* wus, int n, const fstat_out* out
       hipError_t e0 = max_top_k > 0 ? fstat::launch_fill_int((int*)gcount, 0, 2 * m, p->cap_stream) : hipSuccess;
       if (e0 == hipSuccess && c16) e0 = fstat::launch_cexp_batch(ed, m, sfts, p->cap_stream);
       hipError_t e1 = e0 != hipSuccess ? e0 : fstat::launch_coef_batch(ed, m, blocks, c16, p->cap_stream);
-      hipError_t e2 = fstat::launch_interp_batch(ed + m, m8, tiles8, p->counter, p->batch_grid, c16, 8, p->cap_stream);
+      hipError_t e2 = fstat::launch_interp_batch(ed + m, m8, tiles8, p->counter, p->batch_grid[fast8 ? 0 : 1], c16, 8,
+                                                 fast8, p->cap_stream);
       if (e2 == hipSuccess)
-        e2 = fstat::launch_interp_batch(ed + m + m8, m4, tiles4, p->counter + 1, p->batch_grid4, c16, 4,
-                                        p->cap_stream);
+        e2 = fstat::launch_interp_batch(ed + m + m8, m4, tiles4, p->counter + 1, p->batch_grid4[fast4 ? 0 : 1], c16,
+                                        4, fast4, p->cap_stream);
       if (e2 == hipSuccess)
         e2 = fstat::launch_top_select_batch(ed, m, gcand, p->cand_cap, max_top_k, p->cap_stream);
       hipGraph_t graph = nullptr;
@@ -1018,7 +1047,11 @@ int fstat_autotune(fstat_plan* p, const fstat_wu* wu, const fstat_out* out, void
   float best = 1e30f;
   Tile best_t = default_tile(p, wu);
   for (Tile t : cands) {
-    if (resolved_kernel(p) == fstat::KERNEL_INTERP) t.seg = interp_seg(p, wu, t.nf_reg, t.threads);
+    if (resolved_kernel(p) == fstat::KERNEL_INTERP) {
+      bool fits = false;
+      t.seg = interp_seg(p, wu, t.nf_reg, t.threads, &fits);
+      t.fast = fits;
+    }
     float ms_sum = 0.f;
     for (int rep = 0; rep < 2; ++rep) {
       rc = run_demod(p, v, t, st);

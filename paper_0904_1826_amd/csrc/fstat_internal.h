@@ -54,6 +54,8 @@ struct Tile {
   int32_t threads;  // interp: work-group size, 64 or 256
   int32_t seg4;     // interp with nf_reg 8: if > 0, spindowns past the last multiple of 8 (1 to 4 of them) run
                     // in a second launch with 4 per thread and this slice width
+  int32_t fast;     // interp: 1 if the slice holds every window of every SFT (seg and seg4 were not capped), so
+                    // the kernel without the global-memory fallback may run
 };
 
 enum Kernel : int32_t { KERNEL_DIRECT = 1, KERNEL_INTERP = 2 };
@@ -88,6 +90,8 @@ struct BatchEntry {
   int32_t seg;
   int32_t nfd;
   int32_t fd_begin, fd_end;
+  int32_t fast;         // the slice holds every window (see Tile::fast)
+  int32_t pad;
   int64_t tile_begin;   // first tile in the concatenated tile list
   int64_t n_tiles;
   int64_t coef_begin;   // first block of the batched coefficient pass
@@ -99,6 +103,7 @@ struct GeoStatus {
   int flags;                  // bit 1: window outside the band; bit 2: AB - C^2 <= 0
   int pad;
   unsigned long long max_abs_tau_bits;   // max |tau| over (sky, SFT), as FP64 bits
+  unsigned long long max_p_bits;         // max Tdot T over (sky, SFT), as FP64 bits
 };
 
 constexpr int kThreads = 256;          // work-group size of the demodulation kernels
@@ -119,8 +124,8 @@ int64_t interp_tiles(const WuDev& w, int nfd, int64_t fd0, int64_t fd1);
 int64_t coef_blocks(const WuDev& w);
 hipError_t launch_coef_batch(const BatchEntry* ents_dev, int n_ent, int64_t total_blocks, bool c16, hipStream_t s);
 hipError_t launch_interp_batch(const BatchEntry* ents_dev, int n_ent, int64_t total_tiles,
-                               unsigned long long* counter, int grid, bool c16, int nfd, hipStream_t s);
-int interp_batch_grid(bool c16, int nfd);
+                               unsigned long long* counter, int grid, bool c16, int nfd, bool fast, hipStream_t s);
+int interp_batch_grid(bool c16, int nfd, bool fast);
 hipError_t launch_bins(const WuDev& w, int64_t n, const int32_t* i_sky, const int32_t* i_fd, const int32_t* i_f,
                        const int32_t* i_sft, int64_t* kstar, double* kappa, double* phi_frac, hipStream_t s);
 int interp_max_seg(int threads, bool c16);

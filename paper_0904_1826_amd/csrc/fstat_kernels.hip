@@ -121,20 +121,21 @@ __device__ __forceinline__ double warp_sum(double v) {
 // grid leaves the band, bit 2 if AB - C^2 <= 0.  k* is monotone in f and in
 // fdot (every rounding step is monotone), so the grid corners bound it.
 __global__ __launch_bounds__(256) void geometry_kernel(WuDev w, GeoStatus* status) {
-  __shared__ double red[4][4];
+  __shared__ double red[5][4];
   const double T = w.t_sft;
   const double f_lo = template_f(w, 0), f_hi = template_f(w, w.n_f - 1);
   const double fd_a = template_fd(w, 0), fd_b = template_fd(w, w.n_fd - 1);
   const double band_lo = (double)w.k_first, band_hi = (double)(w.k_first + w.n_bins - 1);
   const int D = w.dterms;
   for (int64_t s = blockIdx.x; s < w.n_sky; s += gridDim.x) {
-    double A = 0.0, B = 0.0, C = 0.0, tmax = 0.0;
+    double A = 0.0, B = 0.0, C = 0.0, tmax = 0.0, pmax = 0.0;
     int bad = 0;
     for (int64_t al = threadIdx.x; al < w.n_sft; al += blockDim.x) {
       double tau, tdot;
       sft_geometry(w, s, al, tau, tdot);
       tmax = fmax(tmax, fabs(tau));
       const double P = bin_scale(tdot, T);
+      pmax = fmax(pmax, P);
       w.geo[s * w.n_sft + al] = make_double2(tau, P);
       const double a = w.a[s * w.n_sft + al], b = w.b[s * w.n_sft + al];
       A += a * a;
@@ -154,8 +155,9 @@ __global__ __launch_bounds__(256) void geometry_kernel(WuDev w, GeoStatus* statu
     B = warp_sum(B);
     C = warp_sum(C);
     for (int o = 32; o > 0; o >>= 1) tmax = fmax(tmax, __shfl_xor(tmax, o, 64));
+    for (int o = 32; o > 0; o >>= 1) pmax = fmax(pmax, __shfl_xor(pmax, o, 64));
     const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
-    if (ln == 0) { red[0][wv] = A; red[1][wv] = B; red[2][wv] = C; red[3][wv] = tmax; }
+    if (ln == 0) { red[0][wv] = A; red[1][wv] = B; red[2][wv] = C; red[3][wv] = tmax; red[4][wv] = pmax; }
     const int any_bad = __syncthreads_or(bad);
     if (threadIdx.x == 0) {
       A = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
@@ -168,6 +170,8 @@ __global__ __launch_bounds__(256) void geometry_kernel(WuDev w, GeoStatus* statu
       if (flags) atomicOr(&status->flags, flags);
       const double tm = fmax(fmax(red[3][0], red[3][1]), fmax(red[3][2], red[3][3]));
       atomicMax(&status->max_abs_tau_bits, (unsigned long long)__double_as_longlong(tm));
+      const double pm = fmax(fmax(red[4][0], red[4][1]), fmax(red[4][2], red[4][3]));
+      atomicMax(&status->max_p_bits, (unsigned long long)__double_as_longlong(pm));   // P > 0: bits order as values
     }
     __syncthreads();
   }
@@ -301,7 +305,6 @@ __global__ __launch_bounds__(kThreads) void demod_direct_kernel(WuDev w) {
   const int64_t ft = bid / w.n_fd;
   const int tid = threadIdx.x;
   const int64_t j0 = ft * (kThreads * NF);
-  const double T = w.t_sft;
   const double fd = template_fd(w, i);
   const double hfd = 0.5 * fd;
   const double f_first = template_f(w, j0);
@@ -784,7 +787,7 @@ __device__ __forceinline__ v4f lds_load_v(LdsPtr p, int i) { return p[i]; }
 // The tile covers spindowns [fd0, fd1) of the work unit in blocks of NFD
 // (the last block of a range may be partial: its missing spindowns repeat
 // the range's last one and are not written).
-template <int NFD, int S, int G, int NT, bool C16>
+template <int NFD, int S, int G, int NT, bool C16, bool SAFE>
 __device__ __forceinline__ void interp_tile(const WuDev& w, int W, int64_t tile, int64_t al_begin, int64_t al_end,
                                             float4* cbuf0, float4* cbuf1, GroupMeta<NFD, S>* meta, int64_t fd0,
                                             int64_t fd1) {
@@ -868,6 +871,13 @@ __device__ __forceinline__ void interp_tile(const WuDev& w, int W, int64_t tile,
     // shift-and-add per pair rather than folding the sign into a subtraction)
     uint32_t boff = __builtin_amdgcn_readfirstlane(lds_address(seg) - 16u * (uint32_t)(k_first + m.lo[kk]));
     __asm__ volatile("" : "+s"(boff));
+    // SAFE: an SFT whose windows are not all in the slice reads its
+    // coefficients from global memory.  Otherwise the host has shown that
+    // the slice holds every window (the flag is always set), and without a
+    // second arithmetic path the accumulators keep their registers through
+    // the loop (with one, the compiler copies them at every other SFT).  The
+    // flag stays a run-time branch: with the test folded away the compiler
+    // schedules across SFTs and spills.
     if (__builtin_amdgcn_readfirstlane(m.fast[kk])) {
 #pragma unroll
       for (int r = 0; r < NFD; ++r) {
@@ -882,7 +892,7 @@ __device__ __forceinline__ void interp_tile(const WuDev& w, int W, int64_t tile,
                             m.e[kk][r], a, b, far[r], fai[r], fbr[r], fbi[r]);
         if (r % G == G - 1) __builtin_amdgcn_sched_barrier(0);   // bounds the coefficient registers in flight
       }
-    } else {
+    } else if constexpr (SAFE) {
 #pragma unroll
       for (int r = 0; r < NFD; ++r) {
         const double dphi = bin_position(f, m.g[kk][r], g.y);
@@ -935,14 +945,14 @@ __device__ __forceinline__ void interp_tile(const WuDev& w, int W, int64_t tile,
 }
 
 // One tile per work-group (see interp_tile) over spindowns [fd0, fd1).
-template <int NFD, int S, int MINW, int G, int NT, bool C16>
+template <int NFD, int S, int MINW, int G, int NT, bool C16, bool SAFE>
 __global__ __launch_bounds__(NT, MINW) void demod_interp_kernel(WuDev w, int W, int64_t al_begin, int64_t al_end,
                                                                  int64_t fd0, int64_t fd1) {
   using F = SliceForm<NT, C16>;
   __shared__ GroupMeta<NFD, S> meta[2];
   __shared__ float4 cbuf0[F::rows * F::cap];
   __shared__ float4 cbuf1[F::rows * F::cap];
-  interp_tile<NFD, S, G, NT, C16>(w, W, blockIdx.x, al_begin, al_end, cbuf0, cbuf1, meta, fd0, fd1);
+  interp_tile<NFD, S, G, NT, C16, SAFE>(w, W, blockIdx.x, al_begin, al_end, cbuf0, cbuf1, meta, fd0, fd1);
 }
 
 // Many work units in one persistent launch: the grid holds as many
@@ -956,7 +966,7 @@ __global__ __launch_bounds__(NT, MINW) void demod_interp_kernel(WuDev w, int W, 
 // One launch serves the work units of one spindown block size (8 or 4 per
 // thread), so that each specialisation keeps the registers, and hence the
 // occupancy, of the single-unit kernel.
-template <int NFD, bool C16>
+template <int NFD, bool C16, bool SAFE>
 __global__ __launch_bounds__(kThreads, NFD == 8 ? (C16 ? 5 : 4) : 3) void demod_interp_batch_kernel(
     const BatchEntry* __restrict__ ents, int n_ent, int64_t total_tiles, unsigned long long* counter) {
   using F = SliceForm<kThreads, C16>;
@@ -980,7 +990,7 @@ __global__ __launch_bounds__(kThreads, NFD == 8 ? (C16 ? 5 : 4) : 3) void demod_
     const WuDev& w = ents[lo].w;                  // fields read from the table as needed, not copied
     const int W = ents[lo].seg;
     const int64_t local = tile - ents[lo].tile_begin;
-    interp_tile<NFD, S, 4, kThreads, C16>(w, W, local, 0, w.n_sft, cbuf0, cbuf1, meta, ents[lo].fd_begin,
+    interp_tile<NFD, S, 4, kThreads, C16, SAFE>(w, W, local, 0, w.n_sft, cbuf0, cbuf1, meta, ents[lo].fd_begin,
                                            ents[lo].fd_end);
     __syncthreads();                                 // LDS free for the next tile
   }
@@ -1153,41 +1163,44 @@ int64_t interp_tiles(const WuDev& w, int nfd, int64_t fd0, int64_t fd1) {
   return ((w.n_f + kThreads - 1) / kThreads) * ((fd1 - fd0 + nfd - 1) / nfd) * w.n_sky;
 }
 
-template <int NFD, bool C16>
+template <int NFD, bool C16, bool SAFE>
 static int batch_grid_t(int cus) {
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, demod_interp_batch_kernel<NFD, C16>, kThreads, 0) !=
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, demod_interp_batch_kernel<NFD, C16, SAFE>, kThreads, 0) !=
           hipSuccess ||
       per_cu < 1)
     per_cu = 1;
   return per_cu * cus;
 }
 
-int interp_batch_grid(bool c16, int nfd) {
+int interp_batch_grid(bool c16, int nfd, bool fast) {
   int dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     cus = 256;
-  if (nfd == 8) return c16 ? batch_grid_t<8, true>(cus) : batch_grid_t<8, false>(cus);
-  return c16 ? batch_grid_t<4, true>(cus) : batch_grid_t<4, false>(cus);
+  if (fast) {
+    if (nfd == 8) return c16 ? batch_grid_t<8, true, false>(cus) : batch_grid_t<8, false, false>(cus);
+    return c16 ? batch_grid_t<4, true, false>(cus) : batch_grid_t<4, false, false>(cus);
+  }
+  if (nfd == 8) return c16 ? batch_grid_t<8, true, true>(cus) : batch_grid_t<8, false, true>(cus);
+  return c16 ? batch_grid_t<4, true, true>(cus) : batch_grid_t<4, false, true>(cus);
 }
 
 hipError_t launch_interp_batch(const BatchEntry* ents_dev, int n_ent, int64_t total_tiles,
-                               unsigned long long* counter, int grid, bool c16, int nfd, hipStream_t st) {
+                               unsigned long long* counter, int grid, bool c16, int nfd, bool fast, hipStream_t st) {
   if (n_ent <= 0 || total_tiles <= 0) return hipSuccess;
   hipError_t e = launch_fill_int((int*)counter, 0, 2, st);   // kernel, not memset: safe under capture
   if (e != hipSuccess) return e;
   const dim3 g((unsigned)grid), b(kThreads);
+#define FSTAT_BATCH_LAUNCH(N, C, SF) \
+  hipLaunchKernelGGL((demod_interp_batch_kernel<N, C, SF>), g, b, 0, st, ents_dev, n_ent, total_tiles, counter)
   if (nfd == 8) {
-    if (c16)
-      hipLaunchKernelGGL((demod_interp_batch_kernel<8, true>), g, b, 0, st, ents_dev, n_ent, total_tiles, counter);
-    else
-      hipLaunchKernelGGL((demod_interp_batch_kernel<8, false>), g, b, 0, st, ents_dev, n_ent, total_tiles, counter);
+    if (c16) { if (fast) FSTAT_BATCH_LAUNCH(8, true, false); else FSTAT_BATCH_LAUNCH(8, true, true); }
+    else { if (fast) FSTAT_BATCH_LAUNCH(8, false, false); else FSTAT_BATCH_LAUNCH(8, false, true); }
   } else {
-    if (c16)
-      hipLaunchKernelGGL((demod_interp_batch_kernel<4, true>), g, b, 0, st, ents_dev, n_ent, total_tiles, counter);
-    else
-      hipLaunchKernelGGL((demod_interp_batch_kernel<4, false>), g, b, 0, st, ents_dev, n_ent, total_tiles, counter);
+    if (c16) { if (fast) FSTAT_BATCH_LAUNCH(4, true, false); else FSTAT_BATCH_LAUNCH(4, true, true); }
+    else { if (fast) FSTAT_BATCH_LAUNCH(4, false, false); else FSTAT_BATCH_LAUNCH(4, false, true); }
   }
+#undef FSTAT_BATCH_LAUNCH
   return hipGetLastError();
 }
 
@@ -1196,7 +1209,7 @@ int interp_launches(const WuDev& w, const Tile& t) {
   return (int)((w.n_sft + sb - 1) / sb);
 }
 
-template <int NFD, int S, int MINW, int G, int NT, bool C16>
+template <int NFD, int S, int MINW, int G, int NT, bool C16, bool SAFE = true>
 static hipError_t launch_interp_t(const WuDev& w, const Tile& t, hipStream_t st, int64_t fd0, int64_t fd1) {
   const int W = t.seg;
   const int64_t n_ft = (w.n_f + NT - 1) / NT;
@@ -1207,8 +1220,8 @@ static hipError_t launch_interp_t(const WuDev& w, const Tile& t, hipStream_t st,
   if (sb < w.n_sft && !w.acc) return hipErrorInvalidValue;
   for (int64_t al = 0; al < w.n_sft; al += sb) {
     const int64_t end = al + sb < w.n_sft ? al + sb : w.n_sft;
-    hipLaunchKernelGGL((demod_interp_kernel<NFD, S, MINW, G, NT, C16>), dim3((unsigned)n_tiles), dim3(NT), 0, st, w,
-                       W, al, end, fd0, fd1);
+    hipLaunchKernelGGL((demod_interp_kernel<NFD, S, MINW, G, NT, C16, SAFE>), dim3((unsigned)n_tiles), dim3(NT), 0, st,
+                       w, W, al, end, fd0, fd1);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -1229,11 +1242,13 @@ static hipError_t launch_interp_range(const WuDev& w, const Tile& t, hipStream_t
   if (w.coef16) {
     if (t.threads == 64) return hipErrorInvalidValue;
     switch (t.nf_reg) {
-      case 8: return t.chunk >= 5 ? launch_interp_t<8, 16, 5, 4, kThreads, true>(w, t, st, fd0, fd1)
+      case 8: return t.chunk >= 5 ? (t.fast ? launch_interp_t<8, 16, 5, 4, kThreads, true, false>(w, t, st, fd0, fd1)
+                                            : launch_interp_t<8, 16, 5, 4, kThreads, true>(w, t, st, fd0, fd1))
                    : t.chunk >= 4 ? launch_interp_t<8, 16, 4, 4, kThreads, true>(w, t, st, fd0, fd1)
                      : w3         ? launch_interp_t<8, 16, 3, 4, kThreads, true>(w, t, st, fd0, fd1)
                                   : launch_interp_t<8, 16, 2, 4, kThreads, true>(w, t, st, fd0, fd1);
-      case 4: return w3 ? launch_interp_t<4, 16, 3, 4, kThreads, true>(w, t, st, fd0, fd1)
+      case 4: return w3 ? (t.fast ? launch_interp_t<4, 16, 3, 4, kThreads, true, false>(w, t, st, fd0, fd1)
+                                  : launch_interp_t<4, 16, 3, 4, kThreads, true>(w, t, st, fd0, fd1))
                         : launch_interp_t<4, 16, 2, 4, kThreads, true>(w, t, st, fd0, fd1);
       case 2: return launch_interp_t<2, 16, 3, 4, kThreads, true>(w, t, st, fd0, fd1);
       case 1: return launch_interp_t<1, 16, 3, 4, kThreads, true>(w, t, st, fd0, fd1);
@@ -1253,10 +1268,12 @@ static hipError_t launch_interp_range(const WuDev& w, const Tile& t, hipStream_t
   switch (t.nf_reg) {
     // 4 waves per SIMD: per-SFT values for 8 SFTs at a time, so that four
     // work-groups' LDS fits a CU
-    case 8: return t.chunk >= 4 ? launch_interp_t<8, 8, 4, 4, kThreads, false>(w, t, st, fd0, fd1)
+    case 8: return t.chunk >= 4 ? (t.fast ? launch_interp_t<8, 8, 4, 4, kThreads, false, false>(w, t, st, fd0, fd1)
+                                          : launch_interp_t<8, 8, 4, 4, kThreads, false>(w, t, st, fd0, fd1))
                    : w3         ? launch_interp_t<8, 16, 3, 4, kThreads, false>(w, t, st, fd0, fd1)
                                 : launch_interp_t<8, 16, 2, 4, kThreads, false>(w, t, st, fd0, fd1);
-    case 4: return w3 ? launch_interp_t<4, 16, 3, 4, kThreads, false>(w, t, st, fd0, fd1)
+    case 4: return w3 ? (t.fast ? launch_interp_t<4, 16, 3, 4, kThreads, false, false>(w, t, st, fd0, fd1)
+                                : launch_interp_t<4, 16, 3, 4, kThreads, false>(w, t, st, fd0, fd1))
                       : launch_interp_t<4, 16, 2, 4, kThreads, false>(w, t, st, fd0, fd1);
     case 2: return launch_interp_t<2, 16, 3, 4, kThreads, false>(w, t, st, fd0, fd1);
     case 1: return launch_interp_t<1, 16, 3, 4, kThreads, false>(w, t, st, fd0, fd1);
@@ -1275,7 +1292,7 @@ static hipError_t launch_interp(const WuDev& w, const Tile& t, hipStream_t st) {
   if (e != hipSuccess) return e;
   Tile t4 = t;
   t4.nf_reg = 4;
-  t4.seg = t.seg4;
+  t4.seg = t.seg4;          // t.fast covers both slices
   t4.chunk = t.chunk > 3 ? 3 : t.chunk;
   return launch_interp_range(w, t4, st, split, w.n_fd);
 }
