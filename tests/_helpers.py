@@ -34,3 +34,28 @@ def kernel_power_loss(kappa, dterms):
     kappa = np.asarray(kappa, dtype=np.float64)
     s2 = np.sin(np.pi * kappa) ** 2 / np.pi ** 2
     return s2 * (polygamma(1, kappa + dterms) + polygamma(1, dterms + 1.0 - kappa))
+
+
+def slice_edge_workload(coef, side):
+    """A spindown step chosen so that the bound on how far D-hat-phi moves
+    across a tile of 256 frequencies x 8 spindowns sits at the LDS slice's
+    capacity (296 bins with FP32 coefficients, 384 with FP16): `in` about 5
+    bins inside, where the kernel without the global-memory path runs and
+    every window must still be in its slice; `out` half a bin beyond, where
+    the kernel with that path runs and almost every SFT still takes the LDS
+    path.  tau and Tdot follow their definitions (arrival-time offset and its
+    derivative at the SFT midpoints)."""
+    base = dict(n_det=2, slots=23, keep=0.85, n_sky=3, n_f=700, dterms=8, injections=((1, 5, 333, 15.0),))
+    w = small_workload(310, n_fd=12, fdot_lo=-1e-9, **base)
+    tau = (w.t_start + 0.5 * w.t_sft - w.t_ref)[None, :] + w.sky @ w.pos.T
+    p = (1.0 + w.sky @ w.vel.T) * w.t_sft
+    max_tau, max_p = float(np.abs(tau).max()), float(p.max())
+    cap = 384 if coef == "f16" else 296
+    spread = cap - 9 + 0.01 if side == "in" else cap - 7 + 0.5
+    dfdot = (spread / max_p - 255 * w.df) / (7 * max_tau)
+    assert dfdot > 0
+    w = small_workload(310, n_fd=12, fdot_lo=-11 * dfdot, **base)
+    assert math.isclose(w.dfdot, dfdot, rel_tol=1e-9)
+    width = 262 + math.ceil(spread - 255)
+    assert (width <= cap) == (side == "in")
+    return w

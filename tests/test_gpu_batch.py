@@ -9,7 +9,7 @@ import pytest
 
 import synth
 from synth.device import to_device, alloc_output
-from tests._helpers import small_workload, replace, twoF_error
+from tests._helpers import small_workload, replace, twoF_error, slice_edge_workload
 
 pytestmark = pytest.mark.gpu
 
@@ -178,3 +178,23 @@ def test_batch_16bit_storage(torch_cuda, oracle_lib, storage):
         ref = oracle_lib.fstat(w, (s, i, j), sft=devs[k][1])["twoF"]
         e = twoF_error(outs[k].twoF.cpu().numpy()[s, i, j], ref)
         assert e.max() <= 1e-4, (k, e.max())
+
+
+@pytest.mark.parametrize("mix", ["in", "in+out"])
+@pytest.mark.parametrize("coef", ["f32", "f16"])
+def test_batch_slice_capacity_edge(torch_cuda, oracle_lib, coef, mix):
+    """Work units whose slice bound sits just inside the LDS slice's capacity
+    (a batch of them runs the kernel without the global-memory path) or just
+    beyond it (a batch holding one runs the kernel with that path, and the
+    entries that fit take the LDS path in it); every template against the
+    oracle."""
+    torch = torch_cuda
+    ws = [slice_edge_workload(coef, side) for side in mix.split("+")]
+    _say(f"batch slice edge {coef} {mix}:", [(w.n_sft, w.n_bins, w.dfdot) for w in ws])
+    outs, _ = _batch(torch, ws, coef=coef)
+    for k, w in enumerate(ws):
+        r = oracle_lib.fstat(w)
+        s, i, j = r["templates"]
+        e = twoF_error(outs[k].twoF.cpu().numpy()[s, i, j], r["twoF"])
+        _say(f"  wu {k}: max_e={e.max():.2e}")
+        assert e.max() <= (1e-4 if coef == "f32" else 5e-3)

@@ -9,7 +9,7 @@ import pytest
 
 import synth
 from synth.device import to_device, alloc_output
-from tests._helpers import small_workload, replace, twoF_error
+from tests._helpers import small_workload, replace, twoF_error, slice_edge_workload
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-4
@@ -115,6 +115,22 @@ def test_parity_ragged_tiles(torch_cuda, oracle_lib, dterms, kernel):
 
 INTERP_TILES = [(8, 4, 0, 256), (8, 4, 7, 256), (8, 3, 0, 256), (8, 2, 0, 256), (8, 3, 7, 256), (4, 3, 0, 256),
                 (4, 2, 7, 256), (2, 3, 0, 256), (1, 3, 7, 256), (8, 3, 0, 64), (8, 2, 7, 64), (4, 3, 0, 64)]
+
+
+@pytest.mark.parametrize("side", ["in", "out"])
+@pytest.mark.parametrize("coef", ["f32", "f16"])
+def test_slice_capacity_edge(torch_cuda, oracle_lib, coef, side):
+    """Parity of every template where the slice bound is tightest, for the
+    8-spindown tiles and the 4-spindown remainder (12 spindowns)."""
+    torch = torch_cuda
+    w = slice_edge_workload(coef, side)
+    _say(f"slice edge {coef} {side}: n_sft={w.n_sft} n_bins={w.n_bins} dfdot={w.dfdot:.4e}")
+    wu, _ = to_device(w)
+    out = alloc_output(w)
+    with _plan(w, kernel="interp", max_dterms=8, coef=coef) as p:
+        p.compute(wu, out)
+        torch.cuda.synchronize()
+    _compare(oracle_lib, w, out, tol=TOL if coef == "f32" else 5e-3)
 
 
 @pytest.mark.parametrize("tile", INTERP_TILES, ids=lambda t: "nf%d_w%d_sb%d_t%d" % t)
