@@ -48,7 +48,7 @@ struct WuDev {
 // Tile shape of the demodulation kernels.
 struct Tile {
   int32_t nf_reg;   // direct: frequency templates per thread (1, 2 or 4); interp: spindowns per thread
-  int32_t chunk;    // SFTs staged in LDS per pass
+  int32_t chunk;    // direct: SFTs staged in LDS per pass; interp: waves per SIMD the registers must allow (2 to 5)
   int32_t seg;      // interp: LDS segment width in bins (0: derived)
   int32_t sblock;   // interp: SFTs per launch (the SFT loop is split into launches of this many SFTs)
   int32_t threads;  // interp: work-group size, 64 or 256

@@ -782,7 +782,9 @@ __device__ __forceinline__ v4f lds_load_v(LdsPtr p, int i) { return p[i]; }
 // k*, kappa, the degree-7 polynomial in kappa, the rotation and the
 // a/b accumulation in registers.  An SFT whose windows are not all inside
 // the slice (only possible for slices narrower than the tile's spread) takes
-// the same arithmetic with coefficients read from global memory.
+// the same arithmetic with coefficients read from global memory; with SAFE
+// false (the host has shown that the slice holds every window) that path is
+// not compiled.
 //
 // The tile covers spindowns [fd0, fd1) of the work unit in blocks of NFD
 // (the last block of a range may be partial: its missing spindowns repeat
@@ -1234,9 +1236,11 @@ int interp_max_seg(int threads, bool c16) {
 }
 
 // Tile: nf_reg = spindowns per thread, chunk = minimum waves per SIMD the
-// compiler must leave room for (2 or 3), threads = work-group size (64: one
+// compiler must leave room for (2 to 5), threads = work-group size (64: one
 // wave per work-group, no barrier between waves; 256: four waves share one
-// staged slice; the FP16 coefficient form has 256-thread tiles only).
+// staged slice; the FP16 coefficient form has 256-thread tiles only),
+// fast = the variant without the global-memory path may run (the default
+// shapes have one).
 static hipError_t launch_interp_range(const WuDev& w, const Tile& t, hipStream_t st, int64_t fd0, int64_t fd1) {
   const bool w3 = t.chunk >= 3;
   if (w.coef16) {
