@@ -577,10 +577,17 @@ int batch_interp(fstat_plan* p, const fstat_wu* wus, int n, const fstat_out* out
   bool any_top = false;
   for (int k = 0; k < n; ++k) any_top = any_top || outs[k].top_k > 0;
   if (any_top) {   // one candidate segment and counter per work unit
-    rc = dev_alloc(p, &p->bcand, &p->bcand_bytes, (size_t)n * p->cand_cap * sizeof(uint4), "toplist candidates");
+    const size_t cand_need = (size_t)n * p->cand_cap * sizeof(uint4);
+    const size_t count_need = align256((size_t)n * sizeof(unsigned long long));
+    if (p->bcand_bytes < cand_need || p->bcount_bytes < count_need) {
+      // the captured graphs hold these buffers' addresses
+      (void)hipDeviceSynchronize();
+      for (auto& kv : p->graphs) (void)hipGraphExecDestroy(kv.second);
+      p->graphs.clear();
+    }
+    rc = dev_alloc(p, &p->bcand, &p->bcand_bytes, cand_need, "toplist candidates");
     if (rc) return rc;
-    rc = dev_alloc(p, &p->bcount, &p->bcount_bytes, align256((size_t)n * sizeof(unsigned long long)),
-                   "toplist counters");
+    rc = dev_alloc(p, &p->bcount, &p->bcount_bytes, count_need, "toplist counters");
     if (rc) return rc;
   }
   if (!p->batch_grid[0]) {
@@ -702,8 +709,9 @@ int batch_interp(fstat_plan* p, const fstat_wu* wus, int n, const fstat_out* out
       if (rc) return rc;
       continue;
     }
-    const std::vector<int64_t> sig = {(int64_t)(intptr_t)ed, m, m8, m4, blocks, tiles8, tiles4, fast8, fast4, sfts,
-                                      max_top_k};
+    // everything a captured graph holds by value: addresses, counts, kernel variants
+    const std::vector<int64_t> sig = {(int64_t)(intptr_t)ed, (int64_t)(intptr_t)gcand, (int64_t)(intptr_t)gcount,
+                                      m, m8, m4, blocks, tiles8, tiles4, fast8, fast4, sfts, max_top_k};
     auto it = p->graphs.find(sig);
     if (it == p->graphs.end()) {
       if (!p->cap_stream) {

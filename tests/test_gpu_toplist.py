@@ -183,3 +183,34 @@ def test_toplist_work_unit_shaped_case(torch_cuda):
     assert np.array_equal(got, idx)
     for x in w.injections:
         assert (x.sky_index * w.n_fd + x.fdot_index) * w.n_f + x.f_index in set(got)
+
+
+def test_batch_graphs_follow_reallocated_toplist_buffers(torch_cuda):
+    """Batched calls on one plan of 8 units without toplists, 4 with, 8 with
+    (which grows the toplist buffers), and the same 4 again: the last call has
+    the shapes of the second, and must not replay the second's graph, which
+    holds the old buffers' addresses.  Its toplists equal the second call's
+    and the single-unit calls'."""
+    import paper_0904_1826_amd as P
+    torch = torch_cuda
+    ws = [_workload(910 + k, n_sky=2, n_fd=3, n_f=300, injections=((1, 2, 150, 14.0),)) for k in range(8)]
+    devs = [to_device(w)[0] for w in ws]
+    tops = lambda sel: [alloc_output(ws[k], top_k=20, threshold=8.0, full=False) for k in sel]
+    with _plan(ws) as p:
+        p.batch_compute(devs, [alloc_output(w) for w in ws])
+        second = tops(range(4))
+        p.batch_compute(devs[:4], second)
+        p.batch_compute(devs, tops(range(8)))
+        fourth = tops(range(4))
+        p.batch_compute(devs[:4], fourth)
+        torch.cuda.synchronize()
+    for k in range(4):
+        single = alloc_output(ws[k], top_k=20, threshold=8.0, full=False)
+        with _plan([ws[k]]) as p:
+            p.compute(devs[k], single)
+            torch.cuda.synchronize()
+        a, b, c = P.toplist(second[k]), P.toplist(fourth[k]), P.toplist(single)
+        _say(f"unit {k}: n_above {a[4]} / {b[4]} / {c[4]}")
+        assert a[4] == b[4] == c[4] > 0
+        for x, y, z in zip(a[:4], b[:4], c[:4]):
+            assert np.array_equal(x, y) and np.array_equal(x, z)
