@@ -460,16 +460,19 @@ int run_demod(fstat_plan* p, const WuDev& v, const Tile& t, hipStream_t st) {
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct WuScratch {
-  size_t geo, abcd, coef, cexp, total;
+  size_t geo, abcd, coef, cexp, acc, total;
 };
 
+// Batched form: geometry, A,B,C,D, coefficients, FP16 exponents and, for a
+// unit of more than one SFT block, Fa, Fb between the blocks' launches.
 WuScratch wu_scratch(const fstat_plan* p, const fstat_wu* w) {
   WuScratch r;
   r.geo = align256((size_t)w->n_sky * w->n_sft * sizeof(double2));
   r.abcd = align256((size_t)w->n_sky * sizeof(double4));
   r.coef = align256(coef_bytes(p, w));
   r.cexp = coef16(p) ? align256((size_t)w->n_sft * sizeof(int32_t)) : 0;
-  r.total = r.geo + r.abcd + r.coef + r.cexp;
+  r.acc = w->n_sft > fstat::kBatchSftBlock ? align256((size_t)w->n_sky * w->n_fd * w->n_f * sizeof(float4)) : 0;
+  r.total = r.geo + r.abcd + r.coef + r.cexp + r.acc;
   return r;
 }
 
@@ -634,7 +637,7 @@ int batch_interp(fstat_plan* p, const fstat_wu* wus, int n, const fstat_out* out
       v.abcd = (double4*)(base + sc.geo);
       v.coef = (float4*)(base + sc.geo + sc.abcd);
       v.cexp = sc.cexp ? (int32_t*)(base + sc.geo + sc.abcd + sc.coef) : nullptr;
-      v.acc = nullptr;
+      v.acc = sc.acc ? (float4*)(base + sc.geo + sc.abcd + sc.coef + sc.cexp) : nullptr;
       if (outs[k].top_k > 0) {                         // segment q of the group's candidates
         v.cand = gcand + (size_t)q * p->cand_cap;
         v.cand_count = gcount + q;
@@ -685,6 +688,33 @@ int batch_interp(fstat_plan* p, const fstat_wu* wus, int n, const fstat_out* out
       first = false;
     }
     const bool c16 = coef16(p);
+    // The SFT loop in blocks of kBatchSftBlock: block b runs the entries with
+    // more than b blocks' SFTs, a prefix of each table (most SFTs first),
+    // whose tiles are the first tile_begin of the first entry left out.
+    const int64_t B = fstat::kBatchSftBlock;
+    const int64_t n_blocks = (wus[order[0]].n_sft + B - 1) / B;
+    std::vector<int64_t> bplan;             // per block: entries and tiles of the 8- and the 4-table
+    for (int64_t b = 0; b < n_blocks; ++b) {
+      int n8 = 0, n4 = 0;
+      while (n8 < m8 && eh[m + n8].w.n_sft > b * B) ++n8;
+      while (n4 < m4 && eh[m + m8 + n4].w.n_sft > b * B) ++n4;
+      bplan.insert(bplan.end(), {n8, n8 < m8 ? eh[m + n8].tile_begin : tiles8, n4,
+                                 n4 < m4 ? eh[m + m8 + n4].tile_begin : tiles4});
+    }
+    auto launch_demod_blocks = [&](hipStream_t s, bool counted) -> int {
+      for (int64_t b = 0; b < n_blocks; ++b) {
+        const int64_t* q = &bplan[4 * b];
+        hipError_t e8 = fstat::launch_interp_batch(ed + m, (int)q[0], q[1], p->counter, p->batch_grid[fast8 ? 0 : 1],
+                                                   c16, 8, fast8, b * B, (b + 1) * B, s);
+        int r = counted ? check_launch(p, e8, "batch kernel") : (e8 == hipSuccess ? FSTAT_OK : hip_err(p, e8, "graph capture"));
+        if (r) return r;
+        hipError_t e4 = fstat::launch_interp_batch(ed + m + m8, (int)q[2], q[3], p->counter + 1,
+                                                   p->batch_grid4[fast4 ? 0 : 1], c16, 4, fast4, b * B, (b + 1) * B, s);
+        r = counted ? check_launch(p, e4, "batch kernel") : (e4 == hipSuccess ? FSTAT_OK : hip_err(p, e4, "graph capture"));
+        if (r) return r;
+      }
+      return FSTAT_OK;
+    };
     if (p->d.flags & FSTAT_FLAG_NO_GRAPH) {
       if (max_top_k > 0) {
         rc = check_launch(p, fstat::launch_fill_int((int*)gcount, 0, 2 * m, st), "toplist counter reset");
@@ -696,13 +726,7 @@ int batch_interp(fstat_plan* p, const fstat_wu* wus, int n, const fstat_out* out
       }
       rc = check_launch(p, fstat::launch_coef_batch(ed, m, blocks, c16, st), "coefficient kernel");
       if (rc) return rc;
-      rc = check_launch(p, fstat::launch_interp_batch(ed + m, m8, tiles8, p->counter, p->batch_grid[fast8 ? 0 : 1],
-                                                      c16, 8, fast8, st),
-                        "batch kernel");
-      if (rc) return rc;
-      rc = check_launch(p, fstat::launch_interp_batch(ed + m + m8, m4, tiles4, p->counter + 1,
-                                                      p->batch_grid4[fast4 ? 0 : 1], c16, 4, fast4, st),
-                        "batch kernel");
+      rc = launch_demod_blocks(st, true);
       if (rc) return rc;
       rc = check_launch(p, fstat::launch_top_select_batch(ed, m, gcand, p->cand_cap, max_top_k, st),
                         "toplist selection");
@@ -710,8 +734,9 @@ int batch_interp(fstat_plan* p, const fstat_wu* wus, int n, const fstat_out* out
       continue;
     }
     // everything a captured graph holds by value: addresses, counts, kernel variants
-    const std::vector<int64_t> sig = {(int64_t)(intptr_t)ed, (int64_t)(intptr_t)gcand, (int64_t)(intptr_t)gcount,
-                                      m, m8, m4, blocks, tiles8, tiles4, fast8, fast4, sfts, max_top_k};
+    std::vector<int64_t> sig = {(int64_t)(intptr_t)ed, (int64_t)(intptr_t)gcand, (int64_t)(intptr_t)gcount,
+                                m, m8, m4, blocks, tiles8, tiles4, fast8, fast4, sfts, max_top_k, n_blocks};
+    sig.insert(sig.end(), bplan.begin(), bplan.end());
     auto it = p->graphs.find(sig);
     if (it == p->graphs.end()) {
       if (!p->cap_stream) {
@@ -723,17 +748,15 @@ int batch_interp(fstat_plan* p, const fstat_wu* wus, int n, const fstat_out* out
       hipError_t e0 = max_top_k > 0 ? fstat::launch_fill_int((int*)gcount, 0, 2 * m, p->cap_stream) : hipSuccess;
       if (e0 == hipSuccess && c16) e0 = fstat::launch_cexp_batch(ed, m, sfts, p->cap_stream);
       hipError_t e1 = e0 != hipSuccess ? e0 : fstat::launch_coef_batch(ed, m, blocks, c16, p->cap_stream);
-      hipError_t e2 = fstat::launch_interp_batch(ed + m, m8, tiles8, p->counter, p->batch_grid[fast8 ? 0 : 1], c16, 8,
-                                                 fast8, p->cap_stream);
-      if (e2 == hipSuccess)
-        e2 = fstat::launch_interp_batch(ed + m + m8, m4, tiles4, p->counter + 1, p->batch_grid4[fast4 ? 0 : 1], c16,
-                                        4, fast4, p->cap_stream);
-      if (e2 == hipSuccess)
+      const int rd = e1 == hipSuccess ? launch_demod_blocks(p->cap_stream, false) : FSTAT_OK;
+      hipError_t e2 = hipSuccess;
+      if (e1 == hipSuccess && rd == FSTAT_OK)
         e2 = fstat::launch_top_select_batch(ed, m, gcand, p->cand_cap, max_top_k, p->cap_stream);
       hipGraph_t graph = nullptr;
       e = hipStreamEndCapture(p->cap_stream, &graph);
-      if (e1 != hipSuccess || e2 != hipSuccess || e != hipSuccess) {
+      if (e1 != hipSuccess || rd != FSTAT_OK || e2 != hipSuccess || e != hipSuccess) {
         if (graph) (void)hipGraphDestroy(graph);
+        if (rd != FSTAT_OK) return rd;
         return hip_err(p, e1 != hipSuccess ? e1 : (e2 != hipSuccess ? e2 : e), "graph capture");
       }
       hipGraphExec_t exec = nullptr;

@@ -967,10 +967,14 @@ __global__ __launch_bounds__(NT, MINW) void demod_interp_kernel(WuDev w, int W, 
 // differ between work units: the window is folded into the coefficients.
 // One launch serves the work units of one spindown block size (8 or 4 per
 // thread), so that each specialisation keeps the registers, and hence the
-// occupancy, of the single-unit kernel.
+// occupancy, of the single-unit kernel, and SFTs [al0, al1) of each: the
+// host runs the SFT loop as a sequence of such launches (Fa, Fb carried in
+// `acc`), because over thousands of SFTs the work-groups sharing a slice
+// drift apart and L2 no longer holds it for all of them.
 template <int NFD, bool C16, bool SAFE>
 __global__ __launch_bounds__(kThreads, NFD == 8 ? (C16 ? 5 : 4) : 3) void demod_interp_batch_kernel(
-    const BatchEntry* __restrict__ ents, int n_ent, int64_t total_tiles, unsigned long long* counter) {
+    const BatchEntry* __restrict__ ents, int n_ent, int64_t total_tiles, unsigned long long* counter, int64_t al0,
+    int64_t al1) {
   using F = SliceForm<kThreads, C16>;
   constexpr int S = C16 ? 16 : 8;                  // per-SFT values per group: four work-groups' LDS fits a CU
   __shared__ GroupMeta<NFD, S> meta[2];
@@ -992,7 +996,8 @@ __global__ __launch_bounds__(kThreads, NFD == 8 ? (C16 ? 5 : 4) : 3) void demod_
     const WuDev& w = ents[lo].w;                  // fields read from the table as needed, not copied
     const int W = ents[lo].seg;
     const int64_t local = tile - ents[lo].tile_begin;
-    interp_tile<NFD, S, 4, kThreads, C16, SAFE>(w, W, local, 0, w.n_sft, cbuf0, cbuf1, meta, ents[lo].fd_begin,
+    const int64_t al_end = w.n_sft < al1 ? w.n_sft : al1;
+    interp_tile<NFD, S, 4, kThreads, C16, SAFE>(w, W, local, al0, al_end, cbuf0, cbuf1, meta, ents[lo].fd_begin,
                                            ents[lo].fd_end);
     __syncthreads();                                 // LDS free for the next tile
   }
@@ -1188,13 +1193,16 @@ int interp_batch_grid(bool c16, int nfd, bool fast) {
 }
 
 hipError_t launch_interp_batch(const BatchEntry* ents_dev, int n_ent, int64_t total_tiles,
-                               unsigned long long* counter, int grid, bool c16, int nfd, bool fast, hipStream_t st) {
+                               unsigned long long* counter, int grid, bool c16, int nfd, bool fast, int64_t al0,
+                               int64_t al1, hipStream_t st) {
   if (n_ent <= 0 || total_tiles <= 0) return hipSuccess;
+  if (al0 < 0 || al1 <= al0) return hipErrorInvalidValue;
   hipError_t e = launch_fill_int((int*)counter, 0, 2, st);   // kernel, not memset: safe under capture
   if (e != hipSuccess) return e;
   const dim3 g((unsigned)grid), b(kThreads);
 #define FSTAT_BATCH_LAUNCH(N, C, SF) \
-  hipLaunchKernelGGL((demod_interp_batch_kernel<N, C, SF>), g, b, 0, st, ents_dev, n_ent, total_tiles, counter)
+  hipLaunchKernelGGL((demod_interp_batch_kernel<N, C, SF>), g, b, 0, st, ents_dev, n_ent, total_tiles, counter, \
+                     al0, al1)
   if (nfd == 8) {
     if (c16) { if (fast) FSTAT_BATCH_LAUNCH(8, true, false); else FSTAT_BATCH_LAUNCH(8, true, true); }
     else { if (fast) FSTAT_BATCH_LAUNCH(8, false, false); else FSTAT_BATCH_LAUNCH(8, false, true); }

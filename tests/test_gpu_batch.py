@@ -198,3 +198,30 @@ def test_batch_slice_capacity_edge(torch_cuda, oracle_lib, coef, mix):
         e = twoF_error(outs[k].twoF.cpu().numpy()[s, i, j], r["twoF"])
         _say(f"  wu {k}: max_e={e.max():.2e}")
         assert e.max() <= (1e-4 if coef == "f32" else 5e-3)
+
+
+@pytest.mark.parametrize("coef", ["f32", "f16"])
+def test_batch_sft_blocks(torch_cuda, oracle_lib, coef):
+    """Units of about 1100, 600 and 300 SFTs: the batched SFT loop runs in
+    launches of 512 SFTs, Fa and Fb carried between them, and each launch
+    serves only the units with SFTs left.  Every template against the oracle,
+    and bit for bit against single-unit calls (the carried sums are exact
+    FP32 values, so the split changes no rounding)."""
+    torch = torch_cuda
+    ws = [small_workload(700 + k, n_det=2, slots=s, keep=1.0, n_sky=2, n_fd=9, n_f=300, dterms=8,
+                         injections=((1, 4, 150, 12.0),)) for k, s in enumerate([550, 300, 150])]
+    _say("sft blocks:", [w.n_sft for w in ws])
+    assert ws[0].n_sft > 1024 and 512 < ws[1].n_sft <= 1024 and ws[2].n_sft <= 512
+    outs, devs = _batch(torch, ws, coef=coef)
+    for k, w in enumerate(ws):
+        single = alloc_output(w)
+        with _plan_for([w], coef=coef) as p:
+            p.compute(devs[k][0], single)
+            torch.cuda.synchronize()
+        a = outs[k].twoF.cpu().numpy()
+        assert np.array_equal(a, single.twoF.cpu().numpy()), k
+        r = oracle_lib.fstat(w)
+        s, i, j = r["templates"]
+        e = twoF_error(a[s, i, j], r["twoF"])
+        _say(f"  wu {k}: n_sft={w.n_sft} max_e={e.max():.2e}")
+        assert e.max() <= (1e-4 if coef == "f32" else 5e-3)
