@@ -225,3 +225,27 @@ def test_batch_sft_blocks(torch_cuda, oracle_lib, coef):
         e = twoF_error(a[s, i, j], r["twoF"])
         _say(f"  wu {k}: n_sft={w.n_sft} max_e={e.max():.2e}")
         assert e.max() <= (1e-4 if coef == "f32" else 5e-3)
+
+
+def test_batch_sft_blocks_toplists(torch_cuda):
+    """Toplists of units that span 3, 2 and 1 SFT blocks: candidates are
+    taken in each unit's last block only, and equal the single-unit calls'."""
+    import paper_0904_1826_amd as P
+    torch = torch_cuda
+    ws = [small_workload(700 + k, n_det=2, slots=s, keep=1.0, n_sky=2, n_fd=9, n_f=300, dterms=8,
+                         injections=((1, 4, 150, 12.0),)) for k, s in enumerate([550, 300, 150])]
+    devs = [to_device(w)[0] for w in ws]
+    outs = [alloc_output(w, top_k=30, threshold=8.0, full=False) for w in ws]
+    with _plan_for(ws) as p:
+        p.batch_compute(devs, outs)
+        torch.cuda.synchronize()
+    for k, w in enumerate(ws):
+        single = alloc_output(w, top_k=30, threshold=8.0, full=False)
+        with _plan_for([w]) as p:
+            p.compute(devs[k], single)
+            torch.cuda.synchronize()
+        a, b = P.toplist(outs[k]), P.toplist(single)
+        _say(f"  wu {k}: n_sft={w.n_sft} n_above {a[4]} / {b[4]}")
+        assert a[4] == b[4] > 30
+        for x, y in zip(a[:4], b[:4]):
+            assert np.array_equal(x, y)
