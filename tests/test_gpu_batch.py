@@ -9,7 +9,7 @@ import pytest
 
 import synth
 from synth.device import to_device, alloc_output
-from tests._helpers import small_workload, replace, twoF_error, slice_edge_workload
+from tests._helpers import small_workload, replace, twoF_error, slice_edge_workload, sft_block_workloads
 
 pytestmark = pytest.mark.gpu
 
@@ -208,8 +208,7 @@ def test_batch_sft_blocks(torch_cuda, oracle_lib, coef):
     and bit for bit against single-unit calls (the carried sums are exact
     FP32 values, so the split changes no rounding)."""
     torch = torch_cuda
-    ws = [small_workload(700 + k, n_det=2, slots=s, keep=1.0, n_sky=2, n_fd=9, n_f=300, dterms=8,
-                         injections=((1, 4, 150, 12.0),)) for k, s in enumerate([550, 300, 150])]
+    ws = sft_block_workloads()
     _say("sft blocks:", [w.n_sft for w in ws])
     assert ws[0].n_sft > 1024 and 512 < ws[1].n_sft <= 1024 and ws[2].n_sft <= 512
     outs, devs = _batch(torch, ws, coef=coef)
@@ -232,8 +231,7 @@ def test_batch_sft_blocks_toplists(torch_cuda):
     taken in each unit's last block only, and equal the single-unit calls'."""
     import paper_0904_1826_amd as P
     torch = torch_cuda
-    ws = [small_workload(700 + k, n_det=2, slots=s, keep=1.0, n_sky=2, n_fd=9, n_f=300, dterms=8,
-                         injections=((1, 4, 150, 12.0),)) for k, s in enumerate([550, 300, 150])]
+    ws = sft_block_workloads()
     devs = [to_device(w)[0] for w in ws]
     outs = [alloc_output(w, top_k=30, threshold=8.0, full=False) for w in ws]
     with _plan_for(ws) as p:
