@@ -191,13 +191,20 @@ int fstat_plan_create(fstat_plan** out, const fstat_desc* d);
 int fstat_compute(fstat_plan* p, const fstat_wu* wu, const fstat_out* out, void* stream);
 
 /* 2F of many work units with uneven SFT counts, bands and template grids in
- * one persistent launch (the "several clients per system" idea of the Cell
- * port, Section 5, done on one device).  All work units are validated and
- * band-checked before anything is launched; on failure the index of the first
- * failing work unit is in fstat_last_error.  The launch sequence is captured
- * once in a hipGraph per (n_wu, tile) signature and replayed; the work-unit
- * table lives in device memory, so a replay may change every pointer and
- * size.  outs[i] belongs to wus[i]. */
+ * persistent launches shared by all of them (the "several clients per
+ * system" idea of the Cell port, Section 5, done on one device): one pair of
+ * launches per block of 512 SFTs, each over the units with SFTs left.  All
+ * work units are validated and band-checked before anything is launched; on
+ * failure the index of the first failing work unit is in fstat_last_error.
+ * The launch sequence is captured once in a hipGraph per signature (table
+ * address and shape, SFT blocks, kernel variants, toplist buffers) and
+ * replayed; the work-unit table lives in device memory, so a replay may
+ * change every pointer and size of the units.  Plan scratch per unit:
+ * geometry (16 B per sky point and SFT), coefficients (64 B per SFT and bin,
+ * 32 B with FP16 coefficients) and, for units of more than 512 SFTs, the
+ * carried Fa, Fb (16 B per template); units are processed in groups whose
+ * scratch fits 64 GB (FSTAT_BATCH_SCRATCH_GB overrides).  outs[i] belongs to
+ * wus[i]. */
 int fstat_batch_compute(fstat_plan* p, const fstat_wu* wus, int32_t n_wu, const fstat_out* outs,
                         void* stream);
 
