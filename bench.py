@@ -145,7 +145,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the F-statistic shards by work unit or sky point with no exchange, "
-              "and this build runs and reports a single MI355X only (use --gpus 1).", file=sys.stderr)
+              "and this benchmark runs and reports a single MI355X only (use --gpus 1).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
