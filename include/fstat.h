@@ -22,10 +22,12 @@
  * Frequency templates are f_j = f0 + j*df, spindowns fdot_i = fdot0 + i*dfdot.
  * Dphi and k* are evaluated in IEEE binary64 in exactly the order written
  * above (no fused multiply-add), so k* is reproducible bit for bit; the window
- * sums and Fa, Fb are accumulated in FP32.  The data arrays follow the
- * "data arrays plus offset arrays" layout the paper's GPU port adopted
- * (Section 7): flat contiguous arrays, ragged detector blocks addressed by
- * offsets.
+ * sums and Fa, Fb are accumulated in FP32.  The data arrays follow the flat
+ * layout the paper's GPU port adopted (Section 7): the SFTs of all detectors
+ * are concatenated along one axis and every per-SFT array (t_start, pos,
+ * vel, a, b) is indexed the same way, so detector blocks of any length need
+ * no offset array here (the sum over detectors is coherent; a caller's
+ * offsets only say which rows belong to which detector).
  *
  * Memory: every array pointer in fstat_wu / fstat_out is a DEVICE pointer on
  * the plan's device, owned by the caller, which must keep it alive until the
