@@ -125,7 +125,17 @@ def load_library(path: str = LIB_PATH):
 
 
 def _ptr(t) -> Optional[int]:
-    return None if t is None else t.data_ptr()
+    """Address of a tensor for the C-ABI, which takes device pointers only: a
+    host tensor or a strided view is refused here, before a kernel could read
+    it as device memory.  None passes through (the library reports a missing
+    required array itself)."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError(f"the library takes device tensors only, got one on {t.device}")
+    if not t.is_contiguous():
+        raise ValueError("the library takes contiguous tensors only")
+    return t.data_ptr()
 
 
 def _stream_handle(stream) -> Optional[int]:

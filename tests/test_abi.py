@@ -60,3 +60,15 @@ def test_null_plan_and_null_arguments(lib):
     h = ctypes.c_void_p(1)
     assert lib.fstat_plan_create(ctypes.byref(h), None) == P.FSTAT_E_ARG
     assert not h.value
+
+
+def test_binding_refuses_host_tensors():
+    """The binding hands the library device addresses only: a host tensor (or
+    a strided view of one) is refused before any call, and None passes
+    through for the library to report."""
+    import torch
+    import paper_0904_1826_amd as P
+    assert P._ptr(None) is None
+    for t in (torch.zeros(4), torch.zeros(4, 3).t()):
+        with pytest.raises(ValueError, match="device tensors"):
+            P._ptr(t)
