@@ -11,7 +11,8 @@
  *
  *   tau    = (t_start + T/2 - t_ref) + r . n      r: SSB position, light-s
  *   Tdot   = 1 + v . n                            v: velocity, units of c
- *   Dphi   = ((f + fdot * tau) * Tdot) * T        frequency in SFT bins
+ *   P      = Tdot * T,   q = (fdot * tau) * P
+ *   Dphi   = fma(f, P, q)                         (f + fdot tau) Tdot T: frequency in SFT bins
  *   k*     = floor(Dphi),   kappa = Dphi - k*
  *   phi    = tau * (f + (fdot/2) * tau)           phase in cycles
  *   z      = exp(-2 pi i frac(phi)) * sum_{m=-D}^{D-1} (-1)^(k*-m) x[k*-m] sinc(kappa+m)
@@ -20,9 +21,13 @@
  *   A = sum a^2, B = sum b^2, C = sum a b,  sinc(x) = sin(pi x)/(pi x)
  *
  * Frequency templates are f_j = f0 + j*df, spindowns fdot_i = fdot0 + i*dfdot.
- * Dphi and k* are evaluated in IEEE binary64 in exactly the order written
- * above (no fused multiply-add), so k* is reproducible bit for bit; the window
- * sums and Fa, Fb are accumulated in FP32.  The data arrays follow the flat
+ * Dphi and k* are evaluated in IEEE binary64, round to nearest, in exactly the
+ * order written above: t_mid = t_start + 0.5 * T, r . n = (r0 n0 + r1 n1) + r2 n2
+ * (v . n likewise), tau, Tdot, P and q are each rounded operation by
+ * operation, and Dphi is one fused multiply-add f * P + q with a single
+ * rounding; nothing else is fused.  So k* and kappa are reproducible bit for
+ * bit by any IEEE evaluation of the same sequence.  The window sums and Fa,
+ * Fb are accumulated in FP32.  The data arrays follow the flat
  * layout the paper's GPU port adopted (Section 7): the SFTs of all detectors
  * are concatenated along one axis and every per-SFT array (t_start, pos,
  * vel, a, b) is indexed the same way, so detector blocks of any length need
@@ -230,7 +235,8 @@ int fstat_bins(fstat_plan* p, const fstat_wu* wu, int64_t n, const int32_t* i_sk
                void* stream);
 
 /* Detector inputs of a work unit, computed on the device (the step before
- * the demodulation; the per-SFT data are computed on the fly, Section 4):
+ * the demodulation; the paper's Cell port notes that most of the data the
+ * demodulation reads is produced while the client runs, Section 5):
  * for SFT al with midpoint t_mid[al] taken at site site_of_sft[al] (an index
  * into the host array sites[n_sites], n_sites <= FSTAT_MAX_SITES), the
  * detector position pos[al][3] (light-s) and velocity vel[al][3] (units of c)
@@ -256,6 +262,22 @@ int fstat_detector_inputs(fstat_plan* p, const fstat_earth* earth, int32_t n_sit
  * kernel); lines naming a tile the library does not implement are ignored. */
 int fstat_autotune(fstat_plan* p, const fstat_wu* wu, const fstat_out* out, void* stream,
                    const char* cache_path);
+
+/* Width in bins of the coefficient slice the interp kernel stages in LDS per
+ * SFT for a tile of `threads` (256 or 64) frequency templates x nfd
+ * spindowns, for a work unit with frequency step df and spindown step dfdot
+ * whose (sky, SFT) pairs have at most max_abs_tau = max |tau| (s) and
+ * max_p = max Tdot T (s): the bins k* can move across such a tile
+ * ((threads - 1) df + |dfdot| (nfd - 1) max_abs_tau) max_p, plus slack,
+ * rounded down to a multiple of 4 and capped at the LDS row (296 bins, or 384
+ * with coef16 != 0, for 256 threads).  *fits (may be NULL) is 1 when the cap
+ * did not bind: then every window of every tile lies in its slice and the
+ * kernel variant without a global-memory path runs.  Should that ever be
+ * false for some tile and SFT, the tile's outputs are NaN and the next call
+ * on the plan returns FSTAT_E_DEVICE saying how many tiles were affected.
+ * A host function: no device, plan or allocation involved. */
+int32_t fstat_interp_slice(double df, double dfdot, int32_t nfd, int32_t threads, int32_t coef16, double max_abs_tau,
+                           double max_p, int32_t* fits);
 
 /* Duration in milliseconds of the last demodulation kernel of the last
  * fstat_compute / fstat_batch_compute call (after fstat_semicoherent: the

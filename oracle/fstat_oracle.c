@@ -212,8 +212,9 @@ int oracle_fstat(const oracle_wu* w, int n_tmpl, const int* tsky, const int* tfd
 }
 
 /*
- * Detector inputs of the demodulation (the step before it: the paper notes
- * that such per-SFT data are computed on the fly, Section 4): for each SFT
+ * Detector inputs of the demodulation (the step before it; the paper's Cell
+ * port notes that most of the data the demodulation reads is produced while
+ * the client runs rather than read from the work unit, Section 5): for each SFT
  * the detector position r and velocity v in the solar-system frame
  * (equatorial axes, light-seconds and units of c) and, for each sky direction
  * n, the antenna-pattern factors a, b at the SFT midpoint.

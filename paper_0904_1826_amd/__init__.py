@@ -44,7 +44,7 @@ PHASES = {"fp64": FSTAT_PHASE_FP64, "split": FSTAT_PHASE_SPLIT_FP32}
 # Every entry point include/fstat.h declares.
 EXPORTS = ("fstat_plan_create", "fstat_compute", "fstat_batch_compute", "fstat_bins", "fstat_autotune",
            "fstat_last_kernel_ms", "fstat_plan_destroy", "fstat_strerror", "fstat_last_error",
-           "fstat_detector_inputs", "fstat_semicoherent")
+           "fstat_detector_inputs", "fstat_semicoherent", "fstat_interp_slice")
 
 
 class FstatError(RuntimeError):
@@ -86,6 +86,12 @@ class fstat_out(ctypes.Structure):
 
 
 _lib = None
+_PLAN_STORAGE = {}        # plan handle value -> SFT storage of its descriptor
+
+
+def _storage_of(plan) -> Optional[str]:
+    v = getattr(plan, "value", plan)
+    return _PLAN_STORAGE.get(v)
 
 
 def load_library(path: str = LIB_PATH):
@@ -101,6 +107,9 @@ def load_library(path: str = LIB_PATH):
     lib.fstat_plan_create.restype = ctypes.c_int
     lib.fstat_compute.argtypes = [P, ctypes.POINTER(fstat_wu), ctypes.POINTER(fstat_out), P]
     lib.fstat_compute.restype = ctypes.c_int
+    lib.fstat_interp_slice.argtypes = [ctypes.c_double, ctypes.c_double, I32, I32, I32, ctypes.c_double,
+                                       ctypes.c_double, ctypes.POINTER(I32)]
+    lib.fstat_interp_slice.restype = I32
     lib.fstat_batch_compute.argtypes = [P, ctypes.POINTER(fstat_wu), I32, ctypes.POINTER(fstat_out), P]
     lib.fstat_batch_compute.restype = ctypes.c_int
     lib.fstat_semicoherent.argtypes = [P, ctypes.POINTER(fstat_wu), I32, ctypes.POINTER(fstat_out), P]
@@ -125,17 +134,90 @@ def load_library(path: str = LIB_PATH):
 
 
 def _ptr(t) -> Optional[int]:
-    """Address of a tensor for the C-ABI, which takes device pointers only: a
-    host tensor or a strided view is refused here, before a kernel could read
-    it as device memory.  None passes through (the library reports a missing
-    required array itself)."""
+    """Address of a tensor for the C-ABI, which takes contiguous device arrays
+    only: a strided view or a host tensor is refused here, before a kernel
+    could read it as device memory.  None passes through (the library reports
+    a missing required array itself)."""
     if t is None:
         return None
-    if not t.is_cuda:
-        raise ValueError(f"the library takes device tensors only, got one on {t.device}")
     if not t.is_contiguous():
         raise ValueError("the library takes contiguous tensors only")
+    if not t.is_cuda:
+        raise ValueError(f"the library takes device tensors only, got one on {t.device}")
     return t.data_ptr()
+
+
+# ------------------------------------------------------------ array checks
+# The kernels index every array by the sizes of the work unit, so each array's
+# element type and element count are checked against those sizes before any
+# call: a short or mistyped array would otherwise be read or written out of
+# bounds on the device.  The checks look only at dtype and shape.
+_ELEM = {"f32": ("float32",), "f64": ("float64",), "i32": ("int32",), "i64": ("int64",),
+         "u16pair": ("int16", "uint16")}
+
+
+def _dtype_name(t) -> str:
+    return str(t.dtype).replace("torch.", "")
+
+
+def _numel(t) -> int:
+    n = 1
+    for d in t.shape:
+        n *= int(d)
+    return n
+
+
+def check_array(name: str, t, kind: str, numel: int, *, at_least: bool = False) -> None:
+    """Raise ValueError unless `t` has element type `kind` ("f32", "f64", "i32",
+    "i64", "u16pair") and exactly `numel` elements (at least, if at_least).
+    None passes: the library reports a missing required array itself."""
+    if t is None:
+        return
+    dt = _dtype_name(t)
+    if dt not in _ELEM[kind]:
+        raise ValueError(f"{name}: element type {dt}, expected {' or '.join(_ELEM[kind])}")
+    n = _numel(t)
+    if (n < numel) if at_least else (n != numel):
+        raise ValueError(f"{name}: {n} elements, expected {'at least ' if at_least else ''}{numel}")
+
+
+def check_work_unit(w, storage: str = "c64") -> None:
+    """Element types and counts of a work unit's arrays against its sizes:
+    n_sft and n_bins from sft.shape[:2], n_sky from sky.shape[0].  Scalars
+    and missing arrays are left to the library's own checks."""
+    if len(w.sft.shape) < 2:
+        raise ValueError("sft: expected [n_sft, n_bins, 2] or [n_sft, n_bins]")
+    n_sft, n_bins, n_sky = int(w.sft.shape[0]), int(w.sft.shape[1]), int(w.sky.shape[0])
+    if storage == "c64":
+        if _dtype_name(w.sft) == "complex64":            # [n_sft, n_bins] complex
+            if _numel(w.sft) != n_sft * n_bins:
+                raise ValueError(f"sft: {_numel(w.sft)} complex elements, expected {n_sft * n_bins}")
+        else:                                            # [n_sft, n_bins, 2] float32
+            check_array("sft", w.sft, "f32", 2 * n_sft * n_bins)
+        if w.sft_scale is not None:
+            check_array("sft_scale", w.sft_scale, "f32", n_sft)
+    else:
+        check_array("sft", w.sft, "u16pair", 2 * n_sft * n_bins)
+        check_array("sft_scale", w.sft_scale, "f32", n_sft)
+    check_array("t_start", w.t_start, "f64", n_sft)
+    check_array("pos", w.pos, "f64", 3 * n_sft)
+    check_array("vel", w.vel, "f64", 3 * n_sft)
+    check_array("sky", w.sky, "f64", 3 * n_sky)
+    check_array("a", w.a, "f32", n_sky * n_sft)
+    check_array("b", w.b, "f32", n_sky * n_sft)
+
+
+def check_output(w, o) -> None:
+    """Element types and counts of the outputs against the template count
+    n_sky * n_fd * n_f of work unit w."""
+    n = int(w.sky.shape[0]) * int(w.n_fd) * int(w.n_f)
+    top_k = int(getattr(o, "top_k", 0))
+    check_array("twoF", o.twoF, "f32", n)
+    check_array("fa", getattr(o, "fa", None), "f32", 2 * n)
+    check_array("fb", getattr(o, "fb", None), "f32", 2 * n)
+    if top_k > 0:
+        check_array("top", getattr(o, "top", None), "i32", 4 * top_k, at_least=True)
+        check_array("n_above", getattr(o, "n_above", None), "i64", 1, at_least=True)
 
 
 def _stream_handle(stream) -> Optional[int]:
@@ -227,6 +309,11 @@ def fstat_detector_inputs(plan, earth: dict, sites, t_mid, site_of_sft, sky, pos
     e = fstat_earth(*[float(earth[k]) for k, _ in fstat_earth._fields_])
     st = (fstat_site * len(sites))(*[fstat_site(*map(float, x)) for x in sites])
     n_sft, n_sky = int(t_mid.shape[0]), int(sky.shape[0])
+    for name, t, kind, n in (("t_mid", t_mid, "f64", n_sft), ("site_of_sft", site_of_sft, "i32", n_sft),
+                             ("sky", sky, "f64", 3 * n_sky), ("pos", pos, "f64", 3 * n_sft),
+                             ("vel", vel, "f64", 3 * n_sft), ("a", a, "f32", n_sky * n_sft),
+                             ("b", b, "f32", n_sky * n_sft)):
+        check_array(name, t, kind, n)
     _check(plan, load_library().fstat_detector_inputs(plan, ctypes.byref(e), len(sites), st, n_sft, _ptr(t_mid),
                                                       _ptr(site_of_sft), n_sky, _ptr(sky), _ptr(pos), _ptr(vel),
                                                       _ptr(a), _ptr(b), _stream_handle(stream)))
@@ -261,16 +348,30 @@ def fstat_plan_create(*, max_sft, max_bins, max_sky, max_fd, max_f, max_dterms=1
     h = ctypes.c_void_p()
     rc = lib.fstat_plan_create(ctypes.byref(h), ctypes.byref(d))
     _check(None, rc)
+    _PLAN_STORAGE[h.value] = {v: k for k, v in STORAGE.items()}.get(d.storage, "c64")
     return h
 
 
 def fstat_plan_destroy(plan) -> None:
     if plan:
+        _PLAN_STORAGE.pop(getattr(plan, "value", plan), None)
         load_library().fstat_plan_destroy(plan)
 
 
+def _checked(plan, wu, out=None):
+    """fstat_wu / fstat_out structs of a work unit and its output, after the
+    array checks against the work unit's sizes and the plan's storage."""
+    st = _storage_of(plan)
+    if st is None:                                   # plan of unknown storage: either layout
+        st = "c64" if _dtype_name(wu.sft) in ("float32", "complex64") else "bf16"
+    check_work_unit(wu, st)
+    if out is not None:
+        check_output(wu, out)
+    return _wu_struct(wu), (_out_struct(out) if out is not None else None)
+
+
 def fstat_compute(plan, wu, out, stream=None) -> None:
-    s, o = _wu_struct(wu), _out_struct(out)
+    s, o = _checked(plan, wu, out)
     _check(plan, load_library().fstat_compute(plan, ctypes.byref(s), ctypes.byref(o), _stream_handle(stream)))
 
 
@@ -278,27 +379,43 @@ def fstat_batch_compute(plan, wus: Sequence, outs: Sequence, stream=None) -> Non
     n = len(wus)
     if len(outs) != n:
         raise ValueError("one output per work unit")
-    ws = (fstat_wu * max(n, 1))(*[_wu_struct(w) for w in wus])
-    os_ = (fstat_out * max(n, 1))(*[_out_struct(o) for o in outs])
+    pairs = [_checked(plan, w, o) for w, o in zip(wus, outs)]
+    ws = (fstat_wu * max(n, 1))(*[x[0] for x in pairs])
+    os_ = (fstat_out * max(n, 1))(*[x[1] for x in pairs])
     _check(plan, load_library().fstat_batch_compute(plan, ws, n, os_, _stream_handle(stream)))
 
 
 def fstat_semicoherent(plan, segs: Sequence, out, stream=None) -> None:
     n = len(segs)
-    ws = (fstat_wu * max(n, 1))(*[_wu_struct(w) for w in segs])
+    ws = (fstat_wu * max(n, 1))(*[_checked(plan, w)[0] for w in segs])
+    if n:
+        check_output(segs[0], out)
     o = _out_struct(out)
     _check(plan, load_library().fstat_semicoherent(plan, ws, n, ctypes.byref(o), _stream_handle(stream)))
 
 
 def fstat_bins(plan, wu, i_sky, i_fd, i_f, i_sft, kstar, kappa, phi_frac, stream=None) -> None:
-    s = _wu_struct(wu)
-    n = int(i_sky.numel())
+    s, _ = _checked(plan, wu)
+    n = _numel(i_sky)
+    for name, t, kind in (("i_sky", i_sky, "i32"), ("i_fd", i_fd, "i32"), ("i_f", i_f, "i32"), ("i_sft", i_sft, "i32"),
+                          ("kstar", kstar, "i64"), ("kappa", kappa, "f64"), ("phi_frac", phi_frac, "f64")):
+        check_array(name, t, kind, n)
     _check(plan, load_library().fstat_bins(plan, ctypes.byref(s), n, _ptr(i_sky), _ptr(i_fd), _ptr(i_f), _ptr(i_sft),
                                            _ptr(kstar), _ptr(kappa), _ptr(phi_frac), _stream_handle(stream)))
 
 
+def fstat_interp_slice(df: float, dfdot: float, nfd: int, threads: int, coef16: bool, max_abs_tau: float,
+                       max_p: float):
+    """(slice width in bins, fits) of the interp kernel's LDS slice for a tile
+    (a host computation; see include/fstat.h)."""
+    fits = ctypes.c_int32(0)
+    w = load_library().fstat_interp_slice(float(df), float(dfdot), int(nfd), int(threads), int(bool(coef16)),
+                                          float(max_abs_tau), float(max_p), ctypes.byref(fits))
+    return int(w), bool(fits.value)
+
+
 def fstat_autotune(plan, wu, out, stream=None, cache_path: Optional[str] = None) -> None:
-    s, o = _wu_struct(wu), _out_struct(out)
+    s, o = _checked(plan, wu, out)
     path = cache_path.encode() if cache_path else None
     _check(plan, load_library().fstat_autotune(plan, ctypes.byref(s), ctypes.byref(o), _stream_handle(stream), path))
 

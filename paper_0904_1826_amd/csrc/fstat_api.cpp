@@ -23,7 +23,7 @@ struct fstat_plan {
   fstat_desc d{};
   int device = 0;
   int cu_count = 0;
-  std::string err;
+  char err[512] = "";
   // scratch (device)
   void* geo = nullptr;
   size_t geo_bytes = 0;
@@ -79,21 +79,27 @@ struct fstat_plan {
   // without [0] the global-memory fallback
   int batch_grid[2] = {0, 0}, batch_grid4[2] = {0, 0};
   std::map<std::vector<int64_t>, hipGraphExec_t> graphs;
-  // fault injection (host-side forcing of error paths)
+  // fault injection (host-side forcing of error paths); force_seg > 0 runs the
+  // interp kernels without the global-memory path at that slice width
   long fail_malloc_at = -1, fail_launch_at = -1;
   long n_malloc = 0, n_launch = 0;
+  int force_seg = 0;
+  // the demodulation's count of tiles that met an SFT outside their slice, copied to status_h
+  // (single unit) or bstat_h[0, drop_units) (batched) after each call and
+  // checked when the next call starts
+  hipEvent_t ev_drop = nullptr;
+  bool drop_pending = false;
+  int drop_units = 0;
 };
 
 namespace {
 
 int set_err(fstat_plan* p, int code, const char* fmt, ...) {
   if (p) {
-    char buf[512];
     va_list ap;
     va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
+    vsnprintf(p->err, sizeof p->err, fmt, ap);
     va_end(ap);
-    p->err = buf;
   }
   return code;
 }
@@ -109,7 +115,9 @@ void read_fault_env(fstat_plan* p) {
   long n = 0;
   if (sscanf(e, "malloc:%ld", &n) == 1) p->fail_malloc_at = n;
   if (sscanf(e, "launch:%ld", &n) == 1) p->fail_launch_at = n;
+  if (sscanf(e, "narrow:%ld", &n) == 1 && n >= 8 && n <= 4096) p->force_seg = (int)(n & ~3L);
 }
+
 
 int dev_alloc(fstat_plan* p, void** ptr, size_t* have, size_t need, const char* what) {
   if (*have >= need && *ptr) return FSTAT_OK;
@@ -134,6 +142,53 @@ int check_launch(fstat_plan* p, hipError_t e, const char* what) {
   if (++p->n_launch == p->fail_launch_at) return set_err(p, FSTAT_E_DEVICE, "%s: injected launch failure", what);
   if (e != hipSuccess) return hip_err(p, e, what);
   return FSTAT_OK;
+}
+
+// The previous call's tiles that met an SFT outside their slice, once the copy has landed:
+// an error naming them (their templates' outputs are NaN), else FSTAT_OK.
+int check_prev_drops(fstat_plan* p) {
+  if (!p->drop_pending) return FSTAT_OK;
+  p->drop_pending = false;
+  if (hipEventSynchronize(p->ev_drop) != hipSuccess) return set_err(p, FSTAT_E_DEVICE, "previous call did not complete");
+  unsigned long long n = 0;
+  int unit = -1;
+  if (p->drop_units == 0) {
+    n = p->status_h->dropped;
+  } else {
+    for (int k = 0; k < p->drop_units; ++k)
+      if (p->bstat_h[k].dropped) {
+        n += p->bstat_h[k].dropped;
+        if (unit < 0) unit = k;
+      }
+  }
+  if (n == 0) return FSTAT_OK;
+  if (unit >= 0)
+    return set_err(p, FSTAT_E_DEVICE,
+                   "the previous call met %llu tiles with an SFT whose windows were outside the LDS slice, first in "
+                   "work unit %d; the outputs of those tiles are NaN",
+                   n, unit);
+  return set_err(p, FSTAT_E_DEVICE,
+                 "the previous call met %llu tiles with an SFT whose windows were outside the LDS slice; the "
+                 "outputs of those tiles are NaN",
+                 n);
+}
+
+// Copies the drop count(s) of this call's demodulation to the host, to be
+// checked when the next call starts.
+void queue_drop_check(fstat_plan* p, fstat::GeoStatus* src_d, fstat::GeoStatus* dst_h, int n_units, hipStream_t st) {
+  const size_t n = n_units > 0 ? (size_t)n_units : 1;
+  if (hipMemcpyAsync(dst_h, src_d, n * sizeof(fstat::GeoStatus), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipEventRecord(p->ev_drop, st) != hipSuccess) {
+    (void)hipGetLastError();
+    return;
+  }
+  p->drop_pending = true;
+  p->drop_units = n_units;
+}
+
+// Resets the drop counter of a single-unit call.
+int reset_drops(fstat_plan* p, fstat::GeoStatus* status_d, hipStream_t st) {
+  return check_launch(p, fstat::launch_fill_int((int*)&status_d->dropped, 0, 2, st), "status reset");
 }
 
 bool finite(double x) { return std::isfinite(x); }
@@ -196,6 +251,7 @@ WuDev make_dev(const fstat_plan* p, const fstat_wu* w, const fstat_out* o) {
   v.csum = is != p->csum.end() ? is->second : 0.0;
   v.coef16 = (p->d.flags & FSTAT_FLAG_COEF16) ? 1 : 0;
   v.cexp = (int32_t*)p->cexp;
+  v.dropped = p->status_d ? &p->status_d->dropped : nullptr;
   v.cand = nullptr;
   v.cand_count = nullptr;
   v.cand_cap = p->cand_cap;
@@ -370,9 +426,10 @@ Tile default_tile(const fstat_plan* p, const fstat_wu* w) {
   return Tile{4, 4, 0, 0, 0};   // fastest direct tile on the work-unit-shaped case
 }
 
-Tile pick_tile(const fstat_plan* p, const fstat_wu* w) {
-  auto it = p->tiles.find(class_key(p, w));
-  Tile t = it != p->tiles.end() ? it->second : default_tile(p, w);
+// Slice widths of a tile for this work unit (the 8-spindown blocks and, for
+// 1 to 4 spindowns left over, the 4-spindown launch) and whether the variant
+// without the global-memory path may run.
+Tile complete_tile(const fstat_plan* p, const fstat_wu* w, Tile t) {
   if (resolved_kernel(p) == fstat::KERNEL_INTERP) {
     bool fits = false, fits4 = true;
     t.seg = interp_seg(p, w, t.nf_reg, t.threads, &fits);
@@ -380,8 +437,18 @@ Tile pick_tile(const fstat_plan* p, const fstat_wu* w) {
     const int64_t rem = w->n_fd % 8;
     t.seg4 = (t.nf_reg == 8 && w->n_fd > 8 && rem >= 1 && rem <= 4) ? interp_seg(p, w, 4, t.threads, &fits4) : 0;
     t.fast = fits && fits4;
+    if (p->force_seg > 0) {          // fault injection: a slice narrower than the windows need
+      t.seg = p->force_seg;
+      t.seg4 = t.seg4 > 0 ? p->force_seg : 0;
+      t.fast = 1;
+    }
   }
   return t;
+}
+
+Tile pick_tile(const fstat_plan* p, const fstat_wu* w) {
+  auto it = p->tiles.find(class_key(p, w));
+  return complete_tile(p, w, it != p->tiles.end() ? it->second : default_tile(p, w));
 }
 
 int ensure_toplist(fstat_plan* p, const fstat_out* o) {
@@ -411,14 +478,14 @@ int ensure_scratch(fstat_plan* p, const fstat_wu* w) {
   return rc;
 }
 
-// Geometry + band check; waits for the check.  Returns FSTAT_OK or an error.
-int run_geometry(fstat_plan* p, const WuDev& v, hipStream_t st, int idx) {
-  int rc = check_launch(p, fstat::launch_fill_int((int*)p->status_d, 0, sizeof(fstat::GeoStatus) / sizeof(int), st),
-                        "status reset");
+// Geometry + band check into the status record status_d; waits for the
+// check.  Returns FSTAT_OK or an error.
+int run_geometry_at(fstat_plan* p, const WuDev& v, fstat::GeoStatus* status_d, hipStream_t st, int idx) {
+  int rc = check_launch(p, fstat::launch_fill_int((int*)status_d, 0, fstat::kGeoResetInts, st), "status reset");
   if (rc) return rc;
-  rc = check_launch(p, fstat::launch_geometry(v, p->status_d, st), "geometry kernel");
+  rc = check_launch(p, fstat::launch_geometry(v, status_d, st), "geometry kernel");
   if (rc) return rc;
-  hipError_t e = hipMemcpyAsync(p->status_h, p->status_d, sizeof(fstat::GeoStatus), hipMemcpyDeviceToHost, st);
+  hipError_t e = hipMemcpyAsync(p->status_h, status_d, sizeof(fstat::GeoStatus), hipMemcpyDeviceToHost, st);
   if (e != hipSuccess) return hip_err(p, e, "status copy");
   e = hipStreamSynchronize(st);
   if (e != hipSuccess) return hip_err(p, e, "geometry kernel");
@@ -432,6 +499,10 @@ int run_geometry(fstat_plan* p, const WuDev& v, hipStream_t st, int idx) {
   if (st_bits & 1) return set_err(p, FSTAT_E_BAND, "%sa Dirichlet window [k*-D+1, k*+D] leaves the stored band", tag);
   if (st_bits & 2) return set_err(p, FSTAT_E_ARG, "%santenna-pattern matrix is singular (A B - C^2 <= 0)", tag);
   return FSTAT_OK;
+}
+
+int run_geometry(fstat_plan* p, const WuDev& v, hipStream_t st, int idx) {
+  return run_geometry_at(p, v, p->status_d, st, idx);
 }
 
 int run_demod(fstat_plan* p, const WuDev& v, const Tile& t, hipStream_t st) {
@@ -646,6 +717,7 @@ int batch_interp(fstat_plan* p, const fstat_wu* wus, int n, const fstat_out* out
         v.cand = nullptr;
         v.cand_count = nullptr;
       }
+      v.dropped = &p->bstat_d[k].dropped;
       e.w = v;
       e.coef_begin = blocks;
       e.sft_begin = sfts;
@@ -670,6 +742,10 @@ int batch_interp(fstat_plan* p, const fstat_wu* wus, int n, const fstat_out* out
         bool fits = false;
         e.seg = interp_seg_tau(&wus[k], nfd, fstat::kThreads, coef16(p), status_tau(p->bstat_h[k]),
                                status_p(p->bstat_h[k]), &fits);
+        if (p->force_seg > 0) {          // fault injection: a slice narrower than the windows need
+          e.seg = p->force_seg;
+          fits = true;
+        }
         e.fast = fits ? 1 : 0;
         (nfd == 8 ? fast8 : fast4) &= fits;
         e.n_tiles = fstat::interp_tiles(e.w, nfd, lo, hi);
@@ -771,6 +847,7 @@ int batch_interp(fstat_plan* p, const fstat_wu* wus, int n, const fstat_out* out
   }
   (void)hipEventRecord(p->ev1, st);
   p->timed = true;
+  queue_drop_check(p, p->bstat_d, p->bstat_h, n, st);
   return FSTAT_OK;
 }
 
@@ -824,7 +901,8 @@ int fstat_plan_create(fstat_plan** out, const fstat_desc* d) {
   }
   if (hipMalloc((void**)&p->status_d, sizeof(fstat::GeoStatus)) != hipSuccess ||
       hipHostMalloc((void**)&p->status_h, sizeof(fstat::GeoStatus), hipHostMallocDefault) != hipSuccess ||
-      hipEventCreate(&p->ev0) != hipSuccess || hipEventCreate(&p->ev1) != hipSuccess) {
+      hipEventCreate(&p->ev0) != hipSuccess || hipEventCreate(&p->ev1) != hipSuccess ||
+      hipEventCreateWithFlags(&p->ev_drop, hipEventDisableTiming) != hipSuccess) {
     (void)hipGetLastError();
     fstat_plan_destroy(p);
     return FSTAT_E_NOMEM;
@@ -860,16 +938,19 @@ void fstat_plan_destroy(fstat_plan* p) {
   if (p->status_h) (void)hipHostFree(p->status_h);
   if (p->ev0) (void)hipEventDestroy(p->ev0);
   if (p->ev1) (void)hipEventDestroy(p->ev1);
+  if (p->ev_drop) (void)hipEventDestroy(p->ev_drop);
   (void)hipGetLastError();
   delete p;
 }
 
 int fstat_compute(fstat_plan* p, const fstat_wu* wu, const fstat_out* out, void* stream) {
   if (!p) return FSTAT_E_ARG;
-  p->err.clear();
+  p->err[0] = 0;
   p->timed = false;
   p->ms_prev = 0.0;
-  int rc = validate_wu(p, wu, out, -1);
+  int rc = check_prev_drops(p);
+  if (rc) return rc;
+  rc = validate_wu(p, wu, out, -1);
   if (rc) return rc;
   if (hipSetDevice(p->device) != hipSuccess) return set_err(p, FSTAT_E_DEVICE, "hipSetDevice failed");
   hipStream_t st = (hipStream_t)stream;
@@ -877,17 +958,23 @@ int fstat_compute(fstat_plan* p, const fstat_wu* wu, const fstat_out* out, void*
   if (rc) return rc;
   rc = ensure_toplist(p, out);
   if (rc) return rc;
+  rc = reset_drops(p, p->status_d, st);
+  if (rc) return rc;
   WuDev v = make_dev(p, wu, out);
   rc = run_geometry(p, v, st, -1);
   if (rc) return rc;
-  return run_demod(p, v, pick_tile(p, wu), st);
+  rc = run_demod(p, v, pick_tile(p, wu), st);
+  if (rc == FSTAT_OK) queue_drop_check(p, p->status_d, p->status_h, 0, st);
+  return rc;
 }
 
 int fstat_batch_compute(fstat_plan* p, const fstat_wu* wus, int32_t n_wu, const fstat_out* outs, void* stream) {
   if (!p) return FSTAT_E_ARG;
-  p->err.clear();
+  p->err[0] = 0;
   p->timed = false;
   p->ms_prev = 0.0;
+  int rc0 = check_prev_drops(p);
+  if (rc0) return rc0;
   if (n_wu < 0 || (n_wu > 0 && (!wus || !outs))) return set_err(p, FSTAT_E_ARG, "bad work-unit list");
   for (int k = 0; k < n_wu; ++k) {
     int rc = validate_wu(p, &wus[k], &outs[k], k);
@@ -898,8 +985,10 @@ int fstat_batch_compute(fstat_plan* p, const fstat_wu* wus, int32_t n_wu, const 
   if (n_wu == 0) return FSTAT_OK;
   if (resolved_kernel(p) == fstat::KERNEL_INTERP) return batch_interp(p, wus, n_wu, outs, st);
   // direct kernel: one work unit after the other
+  int rc = reset_drops(p, p->status_d, st);
+  if (rc) return rc;
   for (int k = 0; k < n_wu; ++k) {
-    int rc = ensure_scratch(p, &wus[k]);
+    rc = ensure_scratch(p, &wus[k]);
     if (rc) return rc;
     rc = ensure_toplist(p, &outs[k]);
     if (rc) return rc;
@@ -909,14 +998,17 @@ int fstat_batch_compute(fstat_plan* p, const fstat_wu* wus, int32_t n_wu, const 
     rc = run_demod(p, v, pick_tile(p, &wus[k]), st);
     if (rc) return rc;
   }
+  queue_drop_check(p, p->status_d, p->status_h, 0, st);
   return FSTAT_OK;
 }
 
 int fstat_semicoherent(fstat_plan* p, const fstat_wu* segs, int32_t n_seg, const fstat_out* out, void* stream) {
   if (!p) return FSTAT_E_ARG;
-  p->err.clear();
+  p->err[0] = 0;
   p->timed = false;
   p->ms_prev = 0.0;
+  int rc0 = check_prev_drops(p);
+  if (rc0) return rc0;
   if (n_seg < 1 || !segs || !out) return set_err(p, FSTAT_E_ARG, "semi-coherent: need n_seg >= 1 segments and an output");
   if (!out->twoF) return set_err(p, FSTAT_E_ARG, "semi-coherent: the twoF output holds the sum and is required");
   if (out->fa || out->fb) return set_err(p, FSTAT_E_UNSUPPORTED, "semi-coherent: no Fa/Fb outputs");
@@ -932,6 +1024,8 @@ int fstat_semicoherent(fstat_plan* p, const fstat_wu* segs, int32_t n_seg, const
   if (hipSetDevice(p->device) != hipSuccess) return set_err(p, FSTAT_E_DEVICE, "hipSetDevice failed");
   hipStream_t st = (hipStream_t)stream;
   int rc = ensure_toplist(p, out);
+  if (rc) return rc;
+  rc = reset_drops(p, p->status_d, st);
   if (rc) return rc;
   fstat_out o = *out;
   o.top_k = 0;                       // the toplist is taken of the sum, after the last segment
@@ -961,6 +1055,7 @@ int fstat_semicoherent(fstat_plan* p, const fstat_wu* segs, int32_t n_seg, const
     if (rc) return rc;
     rc = check_launch(p, fstat::launch_top_select(v, st), "toplist selection");
   }
+  if (rc == FSTAT_OK) queue_drop_check(p, p->status_d, p->status_h, 0, st);
   return rc;
 }
 
@@ -968,7 +1063,7 @@ int fstat_bins(fstat_plan* p, const fstat_wu* wu, int64_t n, const int32_t* i_sk
                const int32_t* i_f, const int32_t* i_sft, int64_t* kstar, double* kappa, double* phi_frac,
                void* stream) {
   if (!p) return FSTAT_E_ARG;
-  p->err.clear();
+  p->err[0] = 0;
   if (!wu || !wu->t_start || !wu->pos || !wu->vel || !wu->sky) return set_err(p, FSTAT_E_ARG, "null geometry input");
   if (n < 0) return set_err(p, FSTAT_E_ARG, "n < 0");
   if (wu->n_sft < 1 || wu->n_sky < 1 || wu->n_f < 1 || wu->n_fd < 1 || !(wu->t_sft > 0))
@@ -1001,7 +1096,7 @@ int fstat_detector_inputs(fstat_plan* p, const fstat_earth* earth, int32_t n_sit
                           int64_t n_sft, const double* t_mid, const int32_t* site_of_sft, int64_t n_sky,
                           const double* sky, double* pos, double* vel, float* a, float* b, void* stream) {
   if (!p) return FSTAT_E_ARG;
-  p->err.clear();
+  p->err[0] = 0;
   if (!earth || !sites) return set_err(p, FSTAT_E_ARG, "null earth model or site list");
   if (n_sites < 1 || n_sites > FSTAT_MAX_SITES) return set_err(p, FSTAT_E_ARG, "n_sites %d outside [1, 8]", n_sites);
   if (n_sft < 1 || n_sky < 1) return set_err(p, FSTAT_E_ARG, "sizes must be >= 1");
@@ -1038,8 +1133,10 @@ int fstat_detector_inputs(fstat_plan* p, const fstat_earth* earth, int32_t n_sit
 
 int fstat_autotune(fstat_plan* p, const fstat_wu* wu, const fstat_out* out, void* stream, const char* cache_path) {
   if (!p) return FSTAT_E_ARG;
-  p->err.clear();
-  int rc = validate_wu(p, wu, out, -1);
+  p->err[0] = 0;
+  int rc = check_prev_drops(p);
+  if (rc) return rc;
+  rc = validate_wu(p, wu, out, -1);
   if (rc) return rc;
   const std::string key = class_key(p, wu);
   if (cache_path) {
@@ -1060,6 +1157,8 @@ int fstat_autotune(fstat_plan* p, const fstat_wu* wu, const fstat_out* out, void
   if (rc) return rc;
   rc = ensure_toplist(p, out);
   if (rc) return rc;
+  rc = reset_drops(p, p->status_d, st);
+  if (rc) return rc;
   WuDev v = make_dev(p, wu, out);
   rc = run_geometry(p, v, st, -1);
   if (rc) return rc;
@@ -1077,12 +1176,8 @@ int fstat_autotune(fstat_plan* p, const fstat_wu* wu, const fstat_out* out, void
   }
   float best = 1e30f;
   Tile best_t = default_tile(p, wu);
-  for (Tile t : cands) {
-    if (resolved_kernel(p) == fstat::KERNEL_INTERP) {
-      bool fits = false;
-      t.seg = interp_seg(p, wu, t.nf_reg, t.threads, &fits);
-      t.fast = fits;
-    }
+  for (Tile t0 : cands) {
+    const Tile t = complete_tile(p, wu, t0);      // as pick_tile runs it
     float ms_sum = 0.f;
     for (int rep = 0; rep < 2; ++rep) {
       rc = run_demod(p, v, t, st);
@@ -1102,6 +1197,7 @@ int fstat_autotune(fstat_plan* p, const fstat_wu* wu, const fstat_out* out, void
     }
   }
   p->tiles[key] = best_t;
+  queue_drop_check(p, p->status_d, p->status_h, 0, st);
   if (cache_path) {
     if (FILE* f = fopen(cache_path, "a")) {
       fprintf(f, "%s %d %d %d %d\n", key.c_str(), best_t.nf_reg, best_t.chunk, best_t.sblock, best_t.threads);
@@ -1109,6 +1205,17 @@ int fstat_autotune(fstat_plan* p, const fstat_wu* wu, const fstat_out* out, void
     }
   }
   return FSTAT_OK;
+}
+
+int32_t fstat_interp_slice(double df, double dfdot, int32_t nfd, int32_t threads, int32_t coef16, double max_abs_tau,
+                           double max_p, int32_t* fits) {
+  fstat_wu w{};
+  w.df = df;
+  w.dfdot = dfdot;
+  bool f = false;
+  const int W = interp_seg_tau(&w, nfd, threads == 64 ? 64 : fstat::kThreads, coef16 != 0, max_abs_tau, max_p, &f);
+  if (fits) *fits = f ? 1 : 0;
+  return W;
 }
 
 double fstat_last_kernel_ms(fstat_plan* p) {
@@ -1132,6 +1239,6 @@ const char* fstat_strerror(int code) {
   }
 }
 
-const char* fstat_last_error(const fstat_plan* p) { return p ? p->err.c_str() : ""; }
+const char* fstat_last_error(const fstat_plan* p) { return p ? p->err : ""; }
 
 }  // extern "C"

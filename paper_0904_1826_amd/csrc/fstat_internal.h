@@ -38,6 +38,10 @@ struct WuDev {
   int4* top;               // [top_k] (2F bits, sky, fdot, f)
   unsigned long long* n_above;
   int32_t accumulate;      // 1: the epilogue adds 2F to twoF (semi-coherent sum) instead of storing it
+  // interp kernels compiled without the global-memory path: tiles (per launch)
+  // with an SFT whose windows were not all inside the LDS slice are counted
+  // here, and their outputs set to NaN; NULL: not counted
+  unsigned long long* dropped;
   int64_t n_sft, n_bins, k_first, n_sky, n_f, n_fd;
   double t_sft, f0, df, fdot0, dfdot, t_ref;
   int32_t dterms;
@@ -98,13 +102,18 @@ struct BatchEntry {
   int64_t sft_begin;    // first SFT in the concatenated SFT list (coef16 exponent pass)
 };
 
-// Geometry pass results read back by the host.
+// Geometry pass results read back by the host, and the demodulation's count
+// of tiles that met a slice too narrow for an SFT's windows (reset once per
+// call, not by each geometry pass).
 struct GeoStatus {
   int flags;                  // bit 1: window outside the band; bit 2: AB - C^2 <= 0
   int pad;
   unsigned long long max_abs_tau_bits;   // max |tau| over (sky, SFT), as FP64 bits
   unsigned long long max_p_bits;         // max Tdot T over (sky, SFT), as FP64 bits
+  unsigned long long dropped;            // demodulation: tiles with an SFT outside the slice
 };
+// The geometry pass resets the first kGeoResetInts ints (not `dropped`).
+constexpr int kGeoResetInts = 6;
 
 constexpr int kThreads = 256;          // work-group size of the demodulation kernels
 constexpr int kMaxDterms = 64;

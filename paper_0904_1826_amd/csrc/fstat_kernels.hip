@@ -834,6 +834,7 @@ __device__ __forceinline__ void interp_tile(const WuDev& w, int W, int64_t tile,
   // waves whose frequencies all lie beyond the band's last template only
   // help stage slices
   const bool wave_live = __builtin_amdgcn_readfirstlane((int)(j0 + (tid & ~63) < w.n_f));
+  bool dropped_any = false;                        // (not SAFE) an SFT left its slice: outputs become NaN
   group_meta<NFD, S, NT>(w, geo, arow, brow, al_begin, n < S ? n : S, i0, i_last, f_first, f_last, W, meta[0]);
   __syncthreads();
   const uint32_t lane16 = lane_bytes16();
@@ -908,6 +909,10 @@ __device__ __forceinline__ void interp_tile(const WuDev& w, int W, int64_t tile,
                             fbi[r]);
         }
       }
+    } else {
+      // no global-memory path: an SFT whose windows leave the slice cannot be
+      // evaluated; the tile is counted and its outputs set to NaN (below)
+      dropped_any = true;
     }
     }
     lds_dma_wait();
@@ -925,6 +930,12 @@ __device__ __forceinline__ void interp_tile(const WuDev& w, int W, int64_t tile,
     }
   }
   if (!jvalid) return;
+  if (!SAFE && dropped_any) {
+    if (tid == 0 && w.dropped) atomicAdd(w.dropped, 1ull);
+    const float nan = __builtin_nanf("");
+#pragma unroll
+    for (int r = 0; r < NFD; ++r) far[r] = fai[r] = fbr[r] = fbi[r] = nan;
+  }
   const bool last = al_end == w.n_sft;
   const double4 abcd = w.abcd[s];
 #pragma unroll

@@ -66,3 +66,18 @@ def sft_block_workloads():
     in the batched form) with 9 spindowns (a block of 8 and a remainder)."""
     return [small_workload(700 + k, n_det=2, slots=s, keep=1.0, n_sky=2, n_fd=9, n_f=300, dterms=8,
                            injections=((1, 4, 150, 12.0),)) for k, s in enumerate([550, 300, 150])]
+
+
+def kappa_edge_workload(edge, seed=820, n_fd=9):
+    """A work unit whose every (template, SFT) pair sits at an edge of the
+    Dirichlet offset: kappa = 0 exactly (edge "zero") or kappa = 1 - 2^-34
+    (edge "one").  T_sft = 1024 s and df = 1/1024 Hz are powers of two, the
+    detector velocity is zero (Tdot = 1, so P = T exactly) and every spindown
+    is 0 (q = 0), so Dphi = 1024 f0 + j exactly: f0 = 400 Hz makes it an
+    integer, and f0 one ulp of 400 below 400 (2^-44 Hz) puts it 2^-34 below
+    one.  The positions stay on the orbit (the phase is generic)."""
+    f0 = 400.0 if edge == "zero" else 400.0 - 2.0 ** -44
+    w = synth.make_workload(f"kappa-{edge}", seed=seed, n_det=2, slots_per_det=12, keep_frac=1.0, jitter=60.0,
+                            t_sft=1024.0, f0=f0, n_f=300, n_sky=3, n_fd=n_fd, fdot_lo=0.0, fdot_hi=0.0, dterms=8,
+                            injections=())
+    return replace(w, vel=np.zeros_like(w.vel))

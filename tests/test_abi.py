@@ -62,13 +62,80 @@ def test_null_plan_and_null_arguments(lib):
     assert not h.value
 
 
-def test_binding_refuses_host_tensors():
-    """The binding hands the library device addresses only: a host tensor (or
-    a strided view of one) is refused before any call, and None passes
-    through for the library to report."""
+def test_binding_refuses_host_tensors_and_strided_views():
+    """The binding hands the library contiguous device arrays only: a strided
+    view is refused first (whatever its device), then a host tensor; None
+    passes through for the library to report."""
     import torch
-    import paper_0904_1826_amd as P
     assert P._ptr(None) is None
-    for t in (torch.zeros(4), torch.zeros(4, 3).t()):
-        with pytest.raises(ValueError, match="device tensors"):
-            P._ptr(t)
+    with pytest.raises(ValueError, match="contiguous"):
+        P._ptr(torch.zeros(4, 3).t())
+    with pytest.raises(ValueError, match="device tensors"):
+        P._ptr(torch.zeros(4))
+
+
+def _host_wu(n_sft=5, n_bins=40, n_sky=2, n_fd=3, n_f=7, storage="c64"):
+    """A work unit of CPU tensors with the right element types and counts (the
+    array checks look only at dtype and shape)."""
+    import torch
+    from types import SimpleNamespace
+    sft = torch.zeros(n_sft, n_bins, 2, dtype=torch.float32 if storage == "c64" else torch.int16)
+    return SimpleNamespace(n_det=1, sft=sft, sft_scale=None if storage == "c64" else torch.ones(n_sft),
+                           k_first=100, t_sft=1800.0, t_start=torch.zeros(n_sft, dtype=torch.float64),
+                           pos=torch.zeros(n_sft, 3, dtype=torch.float64), vel=torch.zeros(n_sft, 3, dtype=torch.float64),
+                           sky=torch.zeros(n_sky, 3, dtype=torch.float64), a=torch.zeros(n_sky, n_sft),
+                           b=torch.zeros(n_sky, n_sft), f0=100.0, df=1 / 1800, n_f=n_f, fdot0=0.0, dfdot=0.0,
+                           n_fd=n_fd, t_ref=0.0, dterms=8)
+
+
+def test_array_checks_accept_a_consistent_work_unit():
+    import torch
+    from types import SimpleNamespace
+    for storage in ("c64", "bf16"):
+        w = _host_wu(storage=storage)
+        P.check_work_unit(w, storage)
+        n = 2 * 3 * 7
+        P.check_output(w, SimpleNamespace(twoF=torch.zeros(2, 3, 7), fa=torch.zeros(n, 2), fb=None, top_k=0))
+        P.check_output(w, SimpleNamespace(twoF=None, top_k=5, top=torch.zeros(5, 4, dtype=torch.int32),
+                                          n_above=torch.zeros(1, dtype=torch.int64)))
+
+
+@pytest.mark.parametrize("field,bad,msg", [
+    ("a", ("float64", (2, 5)), "element type"),
+    ("b", ("float32", (2, 4)), "elements"),
+    ("t_start", ("float32", (5,)), "element type"),
+    ("pos", ("float64", (5, 2)), "elements"),
+    ("vel", ("float64", (4, 3)), "elements"),
+    ("sky", ("float32", (2, 3)), "element type"),
+])
+def test_array_checks_refuse_mistyped_or_short_inputs(field, bad, msg):
+    import torch
+    w = _host_wu()
+    setattr(w, field, torch.zeros(bad[1], dtype=getattr(torch, bad[0])))
+    with pytest.raises(ValueError, match=msg):
+        P.check_work_unit(w, "c64")
+
+
+def test_array_checks_refuse_storage_mismatch_and_bad_outputs():
+    import torch
+    from types import SimpleNamespace
+    w = _host_wu()
+    with pytest.raises(ValueError, match="element type"):
+        P.check_work_unit(w, "bf16")                    # float32 bins under 16-bit storage
+    w16 = _host_wu(storage="bf16")
+    w16.sft_scale = None
+    P.check_work_unit(w16, "bf16")                  # a missing array is the library's to report
+    bad_outputs = [
+        (dict(twoF=torch.zeros(2, 3, 6), top_k=0), "elements"),
+        (dict(twoF=torch.zeros(42, dtype=torch.float64), top_k=0), "element type"),
+        (dict(twoF=torch.zeros(42), fa=torch.zeros(42), top_k=0), "elements"),
+        (dict(twoF=None, top_k=5, top=torch.zeros(4, 4, dtype=torch.int32),
+              n_above=torch.zeros(1, dtype=torch.int64)), "at least"),
+        (dict(twoF=None, top_k=5, top=torch.zeros(5, 4, dtype=torch.int32),
+              n_above=torch.zeros(1, dtype=torch.int32)), "element type"),
+    ]
+    for kw, msg in bad_outputs:
+        with pytest.raises(ValueError, match=msg):
+            P.check_output(w, SimpleNamespace(**kw))
+
+

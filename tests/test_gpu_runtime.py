@@ -87,14 +87,18 @@ def test_host_side_argument_errors(torch_cuda, wl):
     wu, _ = to_device(wl)
     out = alloc_output(wl)
     with _plan(wl) as p:
+        import dataclasses
         bad = [dict(dterms=0), dict(dterms=17), dict(a=None), dict(t_start=None), dict(f0=-1.0), dict(df=0.0),
                dict(t_sft=float("nan")), dict(n_f=wl.n_f + 1)]
         for kw in bad:
-            import dataclasses
             w2 = dataclasses.replace(wu, **kw)
+            o2 = alloc_output(dataclasses.replace(wl, n_f=w2.n_f))      # outputs sized for the unit
             with pytest.raises(P.FstatError) as e:
-                p.compute(w2, out)
+                p.compute(w2, o2)
             assert e.value.code in (P.FSTAT_E_ARG, P.FSTAT_E_SIZE), kw
+        # arrays that do not match the unit's sizes are refused by the binding
+        with pytest.raises(ValueError, match="elements"):
+            p.compute(dataclasses.replace(wu, n_f=wl.n_f - 1), out)
         with pytest.raises(P.FstatError):
             p.compute(wu, P.Output(twoF=None))
 
@@ -137,3 +141,50 @@ def test_non_default_stream(torch_cuda, oracle_lib, wl):
         assert p.last_kernel_ms() > 0
     ref = oracle_lib.fstat(wl)["twoF"]
     assert twoF_error(out.twoF.cpu().numpy().ravel(), ref).max() <= 1e-4
+
+
+def test_forced_narrow_slice_is_reported_not_silent(torch_cuda, wl, monkeypatch):
+    """With the slice forced narrower than the tile's windows (fault injection
+    from the host: the variant without the global-memory path at 64 bins),
+    every tile meets SFTs it cannot evaluate: its outputs are NaN, never a
+    2F with terms missing, and the next call on the plan returns
+    FSTAT_E_DEVICE saying so; the call after that runs (and drops) again."""
+    import paper_0904_1826_amd as P
+    torch = torch_cuda
+    monkeypatch.setenv("FSTAT_FAULT", "narrow:64")
+    wu, _ = to_device(wl)
+    out = alloc_output(wl)
+    with _plan(wl, kernel="interp") as p:
+        p.compute(wu, out)
+        torch.cuda.synchronize()
+        assert np.all(np.isnan(out.twoF.cpu().numpy()))      # both frequency tiles span > 64 bins
+        with pytest.raises(P.FstatError) as e:
+            p.compute(wu, out)
+        assert e.value.code == P.FSTAT_E_DEVICE and "outside the LDS slice" in p.last_error()
+        p.compute(wu, out)                                  # runs (and drops) again
+        torch.cuda.synchronize()
+
+
+def test_forced_narrow_slice_in_batch(torch_cuda, monkeypatch):
+    import paper_0904_1826_amd as P
+    torch = torch_cuda
+    ws = synth.make_batch(3, n_wu=3, scale=0.05, seed=22)
+    devs = [to_device(w)[0] for w in ws]
+    ref = [alloc_output(w) for w in ws]
+    outs = [alloc_output(w) for w in ws]
+    mk = lambda: P.Plan(max_sft=max(w.n_sft for w in ws), max_bins=max(w.n_bins for w in ws),
+                        max_sky=max(w.n_sky for w in ws), max_fd=16, max_f=max(w.n_f for w in ws), max_dterms=16)
+    with mk() as p:
+        p.batch_compute(devs, ref)
+    monkeypatch.setenv("FSTAT_FAULT", "narrow:64")
+    with mk() as p:
+        p.batch_compute(devs, outs)
+        torch.cuda.synchronize()
+        for o, r in zip(outs, ref):
+            # tiles of up to 64 frequencies fit the narrow slice and are
+            # evaluated as usual; every other output is NaN
+            a, b = o.twoF.cpu().numpy(), r.twoF.cpu().numpy()
+            assert np.all(np.isnan(a) | (a == b)) and np.isnan(a).mean() > 0.5
+        with pytest.raises(P.FstatError) as e:
+            p.batch_compute(devs, outs)
+        assert e.value.code == P.FSTAT_E_DEVICE and "work unit" in p.last_error()

@@ -32,3 +32,17 @@ def test_sft_block_workloads_span_three_blocks():
     ws = sft_block_workloads()
     assert [(w.n_sft + 511) // 512 for w in ws] == [3, 2, 1]
     assert all(w.n_fd % 8 == 1 for w in ws)          # a 4-spindown remainder table as well
+
+
+@pytest.mark.parametrize("edge,kappa", [("zero", 0.0), ("one", 1.0 - 2.0 ** -34)])
+def test_kappa_edge_workloads_sit_on_the_edge(oracle_lib, edge, kappa):
+    """Every (template, SFT) pair of the kappa-edge work units has exactly the
+    stated offset (the oracle's canonical FP64 bin position), and the windows
+    stay inside the band."""
+    from tests._helpers import kappa_edge_workload
+    w = kappa_edge_workload(edge)
+    k, kap, _, dphi = oracle_lib.bins(w, oracle_lib.all_templates(w))
+    assert np.all(kap == kappa), (kap.min(), kap.max())
+    assert np.all(dphi - k == kappa)
+    assert k.min() - w.dterms + 1 >= w.k_first and k.max() + w.dterms <= w.k_first + w.n_bins - 1
+    oracle_lib.fstat(w, oracle_lib.all_templates(w, [0]))      # band check passes
