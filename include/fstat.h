@@ -197,6 +197,25 @@ int fstat_plan_create(fstat_plan** out, const fstat_desc* d);
  * asynchronously.  Returns after (2) is enqueued. */
 int fstat_compute(fstat_plan* p, const fstat_wu* wu, const fstat_out* out, void* stream);
 
+/* fstat_compute for callers that cannot allocate device memory (code under
+ * stream capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and results as fstat_compute on the same plan, with every
+ * piece of device scratch (geometry, coefficients, status record, toplist
+ * buffer) in one static device array of FSTAT_NOALLOC_SCRATCH_BYTES that
+ * each GPU using the library holds until the process ends.  The call itself
+ * allocates nothing, device or pinned; create the plan beforehand.  The work
+ * unit must fit the array: about 16 B per (sky point, SFT) plus, for the
+ * interp kernel, 64 B per (SFT, bin) (32 B with FSTAT_FLAG_COEF16) must stay
+ * within FSTAT_NOALLOC_SCRATCH_BYTES less 2 MiB + 4 KiB (the tables, status
+ * record and toplist buffer), and top_k within 65536;
+ * otherwise FSTAT_E_SIZE with the sizes in fstat_last_error, before anything
+ * is launched.  Every call on one GPU shares that GPU's array: calls that
+ * overlap in time on one GPU (other threads, other streams, other plans) race
+ * and give wrong results; serialise them.  Inputs, outputs, errors and the
+ * wait for the band check are as for fstat_compute. */
+#define FSTAT_NOALLOC_SCRATCH_BYTES (128u << 20)
+int fstat_compute_noalloc(fstat_plan* p, const fstat_wu* wu, const fstat_out* out, void* stream);
+
 /* 2F of many work units with uneven SFT counts, bands and template grids in
  * persistent launches shared by all of them (the "several clients per
  * system" idea of the Cell port, Section 5, done on one device): one pair of

@@ -44,7 +44,8 @@ PHASES = {"fp64": FSTAT_PHASE_FP64, "split": FSTAT_PHASE_SPLIT_FP32}
 # Every entry point include/fstat.h declares.
 EXPORTS = ("fstat_plan_create", "fstat_compute", "fstat_batch_compute", "fstat_bins", "fstat_autotune",
            "fstat_last_kernel_ms", "fstat_plan_destroy", "fstat_strerror", "fstat_last_error",
-           "fstat_detector_inputs", "fstat_semicoherent", "fstat_interp_slice")
+           "fstat_detector_inputs", "fstat_semicoherent", "fstat_compute_noalloc", "fstat_interp_slice")
+NOALLOC_SCRATCH_BYTES = 128 << 20     # FSTAT_NOALLOC_SCRATCH_BYTES
 
 
 class FstatError(RuntimeError):
@@ -107,6 +108,8 @@ def load_library(path: str = LIB_PATH):
     lib.fstat_plan_create.restype = ctypes.c_int
     lib.fstat_compute.argtypes = [P, ctypes.POINTER(fstat_wu), ctypes.POINTER(fstat_out), P]
     lib.fstat_compute.restype = ctypes.c_int
+    lib.fstat_compute_noalloc.argtypes = [P, ctypes.POINTER(fstat_wu), ctypes.POINTER(fstat_out), P]
+    lib.fstat_compute_noalloc.restype = ctypes.c_int
     lib.fstat_interp_slice.argtypes = [ctypes.c_double, ctypes.c_double, I32, I32, I32, ctypes.c_double,
                                        ctypes.c_double, ctypes.POINTER(I32)]
     lib.fstat_interp_slice.restype = I32
@@ -375,6 +378,13 @@ def fstat_compute(plan, wu, out, stream=None) -> None:
     _check(plan, load_library().fstat_compute(plan, ctypes.byref(s), ctypes.byref(o), _stream_handle(stream)))
 
 
+def fstat_compute_noalloc(plan, wu, out, stream=None) -> None:
+    """fstat_compute with the library's static device scratch: allocates no
+    device memory (see include/fstat.h)."""
+    s, o = _checked(plan, wu, out)
+    _check(plan, load_library().fstat_compute_noalloc(plan, ctypes.byref(s), ctypes.byref(o), _stream_handle(stream)))
+
+
 def fstat_batch_compute(plan, wus: Sequence, outs: Sequence, stream=None) -> None:
     n = len(wus)
     if len(outs) != n:
@@ -432,6 +442,9 @@ class Plan:
 
     def compute(self, wu, out, stream=None):
         fstat_compute(self.handle, wu, out, stream)
+
+    def compute_noalloc(self, wu, out, stream=None):
+        fstat_compute_noalloc(self.handle, wu, out, stream)
 
     def batch_compute(self, wus, outs, stream=None):
         fstat_batch_compute(self.handle, wus, outs, stream)

@@ -10,6 +10,7 @@
 #include <cstring>
 #include <algorithm>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -371,6 +372,51 @@ int ensure_ctab(fstat_plan* p, int D) {
   }
   p->csum[D] = mx;
   return FSTAT_OK;
+}
+
+// ------------------------------------------------ static scratch (no alloc)
+// fstat_compute_noalloc keeps all its device memory in one static device
+// array per GPU (fstat_kernels.hip).  Once per device, with that device
+// current, the array's device address is taken (the host-side name of the
+// array is not a device address and is never used) and the polynomial
+// tables of every Dterms, in both bases, are copied to its start.
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+char* g_static_base[kMaxDevices] = {};
+int g_static_state[kMaxDevices] = {};                    // 0: not set up, 1: ready, -1: failed
+size_t g_tab_off[2][fstat::kMaxDterms + 1] = {};         // byte offset of the table of [centred][D]
+double g_tab_csum[2][fstat::kMaxDterms + 1] = {};        // its max_p sum_m |t[m][p]|
+
+void static_setup(int dev) {
+  std::lock_guard<std::mutex> lock(g_static_mu);
+  if (dev < 0 || dev >= kMaxDevices || g_static_state[dev] != 0) return;
+  g_static_state[dev] = -1;
+  void* base = nullptr;
+  if (fstat::static_scratch_address(&base) != hipSuccess || !base) {
+    (void)hipGetLastError();
+    return;
+  }
+  std::vector<double> all;
+  for (int c = 0; c < 2; ++c)
+    for (int D = 1; D <= fstat::kMaxDterms; ++D) {
+      const std::vector<double> tab = sinc_poly_table(D, c == 1);
+      g_tab_off[c][D] = all.size() * sizeof(double);
+      double mx = 0.0;
+      for (int q = 0; q < fstat::kCoef; ++q) {
+        double sum = 0.0;
+        for (int m = 0; m < 2 * D; ++m) sum += fabs(tab[(size_t)m * fstat::kCoef + q]);
+        mx = sum > mx ? sum : mx;
+      }
+      g_tab_csum[c][D] = mx;
+      all.insert(all.end(), tab.begin(), tab.end());
+    }
+  static_assert(2 * 16 * (64 * 65 / 2) * sizeof(double) <= fstat::kStaticTabBytes, "tables fit their region");
+  if (hipMemcpy(base, all.data(), all.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipGetLastError();
+    return;
+  }
+  g_static_base[dev] = (char*)base;
+  g_static_state[dev] = 1;
 }
 
 std::string class_key(const fstat_plan* p, const fstat_wu* w) {
@@ -887,6 +933,7 @@ int fstat_plan_create(fstat_plan** out, const fstat_desc* d) {
     return FSTAT_E_DEVICE;
   }
   p->cu_count = prop.multiProcessorCount;
+  static_setup(dev);
   if (d->max_cands < 0 || d->max_cands > ((int64_t)1 << 24)) {
     delete p;
     return FSTAT_E_ARG;
@@ -965,6 +1012,62 @@ int fstat_compute(fstat_plan* p, const fstat_wu* wu, const fstat_out* out, void*
   if (rc) return rc;
   rc = run_demod(p, v, pick_tile(p, wu), st);
   if (rc == FSTAT_OK) queue_drop_check(p, p->status_d, p->status_h, 0, st);
+  return rc;
+}
+
+int fstat_compute_noalloc(fstat_plan* p, const fstat_wu* wu, const fstat_out* out, void* stream) {
+  if (!p) return FSTAT_E_ARG;
+  p->err[0] = 0;
+  p->timed = false;
+  p->ms_prev = 0.0;
+  int rc = check_prev_drops(p);
+  if (rc) return rc;
+  rc = validate_wu(p, wu, out, -1);
+  if (rc) return rc;
+  if (hipSetDevice(p->device) != hipSuccess) return set_err(p, FSTAT_E_DEVICE, "hipSetDevice failed");
+  char* base = p->device < kMaxDevices && g_static_state[p->device] == 1 ? g_static_base[p->device] : nullptr;
+  if (!base) return set_err(p, FSTAT_E_DEVICE, "the static scratch of device %d is not available", p->device);
+  // work region: geometry, A,B,C,D and, for the interp kernel, the
+  // coefficients (with their padding) and the FP16 form's exponents
+  const bool interp = resolved_kernel(p) == fstat::KERNEL_INTERP;
+  const size_t geo = align256((size_t)wu->n_sky * wu->n_sft * sizeof(double2));
+  const size_t abcd = align256((size_t)wu->n_sky * sizeof(double4));
+  const size_t coef = interp ? align256(coef_bytes(p, wu)) : 0;
+  const size_t cexp = interp && coef16(p) ? align256((size_t)wu->n_sft * sizeof(int32_t)) : 0;
+  const size_t need = geo + abcd + coef + cexp, have = fstat::kStaticScratchBytes - fstat::kStaticWorkOff;
+  if (need > have)
+    return set_err(p, FSTAT_E_SIZE, "fstat_compute_noalloc: the work unit needs %zu bytes of scratch, the static array "
+                   "has %zu", need, have);
+  const int64_t cap = p->cand_cap < fstat::kStaticCands ? p->cand_cap : fstat::kStaticCands;
+  if (out->top_k > cap)
+    return set_err(p, FSTAT_E_SIZE, "fstat_compute_noalloc: top_k %d exceeds the static toplist capacity %lld",
+                   out->top_k, (long long)cap);
+  hipStream_t st = (hipStream_t)stream;
+  fstat::GeoStatus* status = (fstat::GeoStatus*)(base + fstat::kStaticStatusOff);
+  rc = reset_drops(p, status, st);
+  if (rc) return rc;
+  WuDev v = make_dev(p, wu, out);
+  char* work = base + fstat::kStaticWorkOff;
+  v.geo = (double2*)work;
+  v.abcd = (double4*)(work + geo);
+  v.coef = interp ? (float4*)(work + geo + abcd) : nullptr;
+  v.cexp = cexp ? (int32_t*)(work + geo + abcd + coef) : nullptr;
+  v.acc = nullptr;
+  const int c = coef16(p) ? 1 : 0;
+  v.ctab = interp ? (const double*)(base + g_tab_off[c][wu->dterms]) : nullptr;
+  v.csum = g_tab_csum[c][wu->dterms];
+  v.dropped = &status->dropped;
+  v.cand_cap = cap;
+  if (out->top_k > 0) {
+    v.cand = (uint4*)(base + fstat::kStaticCandOff);
+    v.cand_count = (unsigned long long*)(base + fstat::kStaticCountOff);
+  }
+  rc = run_geometry_at(p, v, status, st, -1);
+  if (rc) return rc;
+  Tile t = pick_tile(p, wu);
+  t.sblock = 0;                      // one launch over all SFTs: no carried Fa, Fb
+  rc = run_demod(p, v, t, st);
+  if (rc == FSTAT_OK) queue_drop_check(p, status, p->status_h, 0, st);
   return rc;
 }
 
@@ -1077,6 +1180,8 @@ int fstat_bins(fstat_plan* p, const fstat_wu* wu, int64_t n, const int32_t* i_sk
 }
 
 // A tile the launchers implement (cache entries are checked against it).
+static_assert(FSTAT_NOALLOC_SCRATCH_BYTES == fstat::kStaticScratchBytes, "one size of the static scratch");
+
 static bool valid_tile(const fstat_plan* p, const Tile& t) {
   if (t.sblock < 0) return false;
   if (resolved_kernel(p) == fstat::KERNEL_INTERP) {

@@ -115,6 +115,20 @@ struct GeoStatus {
 // The geometry pass resets the first kGeoResetInts ints (not `dropped`).
 constexpr int kGeoResetInts = 6;
 
+// Static scratch of the no-allocation entry point: one array of this many
+// bytes per device, laid out as the polynomial tables of every Dterms in both
+// bases (kStaticTabBytes), the status record and toplist counter, the
+// toplist buffer (kStaticCands entries) and the work region.
+constexpr size_t kStaticScratchBytes = (size_t)128 << 20;
+constexpr size_t kStaticTabBytes = (size_t)1 << 20;
+constexpr size_t kStaticStatusOff = kStaticTabBytes;            // GeoStatus
+constexpr size_t kStaticCountOff = kStaticTabBytes + 256;       // toplist counter (2 x u64)
+constexpr int64_t kStaticCands = 65536;
+constexpr size_t kStaticCandOff = kStaticTabBytes + 4096;       // kStaticCands x 16 B
+constexpr size_t kStaticWorkOff = kStaticCandOff + (size_t)kStaticCands * 16;
+// Address of this device's static scratch (the current device must be the one asked for).
+hipError_t static_scratch_address(void** ptr);
+
 constexpr int kThreads = 256;          // work-group size of the demodulation kernels
 constexpr int kMaxDterms = 64;
 // The batched form runs the SFT loop in launches of this many SFTs, Fa and

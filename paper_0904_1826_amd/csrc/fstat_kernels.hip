@@ -1121,6 +1121,15 @@ __global__ void bins_kernel(WuDev w, int64_t n, const int32_t* i_sky, const int3
   }
 }
 
+// ---------------------------------------------- static scratch (no alloc)
+// Device memory of fstat_compute_noalloc, for callers that cannot allocate:
+// every device that loads the library holds one copy of this array until the
+// process ends.  Host code never passes the array's name to a kernel or a
+// copy: it asks for the device address once per device (below) and uses that.
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+hipError_t static_scratch_address(void** ptr) { return hipGetSymbolAddress(ptr, HIP_SYMBOL(scratch)); }
+
 // Small fill kernel used instead of hipMemsetAsync, so that the same code is
 // safe inside captured graphs.
 __global__ void fill_int_kernel(int* p, int v, int n) {

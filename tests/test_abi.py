@@ -139,3 +139,5 @@ def test_array_checks_refuse_storage_mismatch_and_bad_outputs():
             P.check_output(w, SimpleNamespace(**kw))
 
 
+def test_noalloc_entry_point_null_arguments(lib):
+    assert lib.fstat_compute_noalloc(None, None, None, None) == P.FSTAT_E_ARG
