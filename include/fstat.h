@@ -219,7 +219,10 @@ int fstat_compute_noalloc(fstat_plan* p, const fstat_wu* wu, const fstat_out* ou
 /* 2F of many work units with uneven SFT counts, bands and template grids in
  * persistent launches shared by all of them (the "several clients per
  * system" idea of the Cell port, Section 5, done on one device): one pair of
- * launches per block of 512 SFTs, each over the units with SFTs left.  All
+ * launches per block of SFTs (256 unless fstat_autotune chose another), each
+ * over the units with SFTs left; inside a launch the tiles are dealt to one
+ * queue per XCD in chunks of consecutive tiles, so that tiles sharing
+ * coefficients are served by one L2.  All
  * work units are validated and band-checked before anything is launched; on
  * failure the index of the first failing work unit is in fstat_last_error.
  * The launch sequence is captured once in a hipGraph per signature (table
@@ -273,12 +276,19 @@ int fstat_detector_inputs(fstat_plan* p, const fstat_earth* earth, int32_t n_sit
 
 /* Measure the candidate tile shapes on this work unit (timed on `stream`,
  * outputs overwritten) and keep the fastest for work units of its class
- * (storage, Dterms, kernel).  `cache_path` (may be NULL) names a text file
- * that stores results across processes; it is read first and updated.  One
- * line per class: "<class> <nf_reg> <chunk> <sblock> <threads>" (spindowns
- * or frequencies per thread, waves per SIMD (interp) or SFTs per LDS chunk
- * (direct), SFTs per launch with 0 = all, work-group size of the interp
- * kernel); lines naming a tile the library does not implement are ignored. */
+ * (storage, Dterms, kernel), and, for the interp kernel, the fastest launch
+ * shape of fstat_batch_compute for the plan's batch class (storage and
+ * coefficient form), timed on this unit as a batch of one.  `cache_path` (may
+ * be NULL) names a text file that stores results across processes; it is read
+ * first and updated, and only what it lacks is measured.  One line per class:
+ * "<class> <nf_reg> <chunk> <sblock> <threads>".  Single-unit classes
+ * ("s<storage>_d<Dterms>_k<kernel>_c<coef16>"): spindowns or frequencies per
+ * thread, waves per SIMD (interp) or SFTs per LDS chunk (direct), SFTs per
+ * launch with 0 = all, work-group size of the interp kernel.  Batch classes
+ * ("batch_s<storage>_c<coef16>"): spindowns per thread (8: blocks of 8 and a
+ * remainder of 1 to 4 in a block of 4; 4: blocks of 4), tiles per chunk of
+ * the per-XCD queues, SFTs per launch (0 = all), 256.  Lines naming a shape
+ * the library does not implement are ignored. */
 int fstat_autotune(fstat_plan* p, const fstat_wu* wu, const fstat_out* out, void* stream,
                    const char* cache_path);
 

@@ -130,11 +130,10 @@ constexpr size_t kStaticWorkOff = kStaticCandOff + (size_t)kStaticCands * 16;
 hipError_t static_scratch_address(void** ptr);
 
 constexpr int kThreads = 256;          // work-group size of the demodulation kernels
+// XCDs of the device: the persistent batch kernel keeps one tile queue per XCD
+// (kXcds counters of 8 bytes per launch).
+constexpr int kXcds = 8;
 constexpr int kMaxDterms = 64;
-// The batched form runs the SFT loop in launches of this many SFTs, Fa and
-// Fb carried over in each work unit's `acc`, so that the work-groups resident
-// at once stay on nearby SFTs and share coefficient slices in L2.
-constexpr int kBatchSftBlock = 512;
 
 // Width in bins of the LDS segment staged per SFT for a tile of `nf` frequency
 // templates: the window span 2D, the templates' spread (nf bins times the
@@ -152,9 +151,10 @@ int64_t coef_blocks(const WuDev& w);
 hipError_t launch_coef_batch(const BatchEntry* ents_dev, int n_ent, int64_t total_blocks, bool c16, hipStream_t s);
 // SFTs [al0, al1) of the first n_ent entries (each clipped to its unit's
 // SFT count; every one of them must have more than al0 SFTs).
+// Tiles are dealt to kXcds queues (counters[0, kXcds)) in chunks of `chunk`.
 hipError_t launch_interp_batch(const BatchEntry* ents_dev, int n_ent, int64_t total_tiles,
-                               unsigned long long* counter, int grid, bool c16, int nfd, bool fast, int64_t al0,
-                               int64_t al1, hipStream_t s);
+                               unsigned long long* counters, int64_t chunk, int grid, bool c16, int nfd, bool fast,
+                               int64_t al0, int64_t al1, hipStream_t s);
 int interp_batch_grid(bool c16, int nfd, bool fast);
 hipError_t launch_bins(const WuDev& w, int64_t n, const int32_t* i_sky, const int32_t* i_fd, const int32_t* i_f,
                        const int32_t* i_sft, int64_t* kstar, double* kappa, double* phi_frac, hipStream_t s);

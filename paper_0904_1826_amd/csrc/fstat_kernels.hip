@@ -969,13 +969,19 @@ __global__ __launch_bounds__(NT, MINW) void demod_interp_kernel(WuDev w, int W, 
 }
 
 // Many work units in one persistent launch: the grid holds as many
-// work-groups as fit on the device at once; each takes the next tile of the
-// concatenated tile list from a device counter until none is left (every
+// work-groups as fit on the device at once; each takes tiles of the
+// concatenated tile list from device counters until none is left (every
 // work-group reaches that exit).  Entries are ordered by cost (SFT count)
 // descending, so the long tiles start first and the tail is short.  Tiles of
-// one work unit are sky point fastest, as in the single-unit kernel, so the
-// work-groups running at once share coefficient slices in L2.  Dterms may
-// differ between work units: the window is folded into the coefficients.
+// one work unit are sky point fastest, as in the single-unit kernel, so
+// consecutive tiles share coefficient slices.  The list is cut into chunks of
+// `chunk` consecutive tiles dealt in turn to kXcds queues, one per XCD (the
+// hardware places work-group b of a launch on XCD b mod kXcds): the
+// work-groups of one XCD take the tiles of its chunks in order, so a slice is
+// read by the work-groups of one L2 rather than of all eight.  A work-group
+// whose queue is drained takes tiles from the next queue, so every tile runs
+// once whatever the placement.  Dterms may differ between work units: the
+// window is folded into the coefficients.
 // One launch serves the work units of one spindown block size (8 or 4 per
 // thread), so that each specialisation keeps the registers, and hence the
 // occupancy, of the single-unit kernel, and SFTs [al0, al1) of each: the
@@ -984,20 +990,44 @@ __global__ __launch_bounds__(NT, MINW) void demod_interp_kernel(WuDev w, int W, 
 // drift apart and L2 no longer holds it for all of them.
 template <int NFD, bool C16, bool SAFE>
 __global__ __launch_bounds__(kThreads, NFD == 8 ? (C16 ? 5 : 4) : 3) void demod_interp_batch_kernel(
-    const BatchEntry* __restrict__ ents, int n_ent, int64_t total_tiles, unsigned long long* counter, int64_t al0,
-    int64_t al1) {
+    const BatchEntry* __restrict__ ents, int n_ent, int64_t total_tiles, unsigned long long* counters, int64_t chunk,
+    int64_t al0, int64_t al1) {
   using F = SliceForm<kThreads, C16>;
   constexpr int S = C16 ? 16 : 8;                  // per-SFT values per group: four work-groups' LDS fits a CU
   __shared__ GroupMeta<NFD, S> meta[2];
   __shared__ float4 cbuf0[F::rows * F::cap];
   __shared__ float4 cbuf1[F::rows * F::cap];
-  __shared__ unsigned long long next;
+  __shared__ long long next;
+  __shared__ int queue[2];                         // thread 0's queue and count of drained queues
+  if (threadIdx.x == 0) {
+    queue[0] = (int)(blockIdx.x % kXcds);          // this XCD's queue first
+    queue[1] = 0;
+  }
   for (;;) {
-    if (threadIdx.x == 0) next = atomicAdd(counter, 1ull);
+    if (threadIdx.x == 0) {
+      long long t = -1;
+      int q = queue[0], drained = queue[1];
+      while (drained < kXcds) {
+        // queue q hands out chunks q, q + kXcds, ... in order; past the end
+        // of the list it stays past it, so it is drained once seen so
+        const unsigned long long n = atomicAdd(counters + q, 1ull);
+        const long long c = (long long)q + (long long)kXcds * (long long)(n / (unsigned long long)chunk);
+        const long long u = c * chunk + (long long)(n % (unsigned long long)chunk);
+        if (u < total_tiles) {
+          t = u;
+          break;
+        }
+        q = q + 1 == kXcds ? 0 : q + 1;
+        ++drained;
+      }
+      queue[0] = q;
+      queue[1] = drained;
+      next = t;
+    }
     __syncthreads();
     const int64_t tile = (int64_t)next;
     __syncthreads();                                 // all have read `next` before it is replaced
-    if (tile >= total_tiles) break;
+    if (tile < 0) break;
     int lo = 0, hi = n_ent - 1;                      // last entry with tile_begin <= tile
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
@@ -1213,16 +1243,17 @@ int interp_batch_grid(bool c16, int nfd, bool fast) {
 }
 
 hipError_t launch_interp_batch(const BatchEntry* ents_dev, int n_ent, int64_t total_tiles,
-                               unsigned long long* counter, int grid, bool c16, int nfd, bool fast, int64_t al0,
-                               int64_t al1, hipStream_t st) {
+                               unsigned long long* counters, int64_t chunk, int grid, bool c16, int nfd, bool fast,
+                               int64_t al0, int64_t al1, hipStream_t st) {
   if (n_ent <= 0 || total_tiles <= 0) return hipSuccess;
-  if (al0 < 0 || al1 <= al0) return hipErrorInvalidValue;
-  hipError_t e = launch_fill_int((int*)counter, 0, 2, st);   // kernel, not memset: safe under capture
+  if (al0 < 0 || al1 <= al0 || chunk < 1) return hipErrorInvalidValue;
+  // kernel, not memset: safe under capture
+  hipError_t e = launch_fill_int((int*)counters, 0, 2 * kXcds, st);
   if (e != hipSuccess) return e;
   const dim3 g((unsigned)grid), b(kThreads);
 #define FSTAT_BATCH_LAUNCH(N, C, SF) \
-  hipLaunchKernelGGL((demod_interp_batch_kernel<N, C, SF>), g, b, 0, st, ents_dev, n_ent, total_tiles, counter, \
-                     al0, al1)
+  hipLaunchKernelGGL((demod_interp_batch_kernel<N, C, SF>), g, b, 0, st, ents_dev, n_ent, total_tiles, counters, \
+                     chunk, al0, al1)
   if (nfd == 8) {
     if (c16) { if (fast) FSTAT_BATCH_LAUNCH(8, true, false); else FSTAT_BATCH_LAUNCH(8, true, true); }
     else { if (fast) FSTAT_BATCH_LAUNCH(8, false, false); else FSTAT_BATCH_LAUNCH(8, false, true); }

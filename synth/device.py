@@ -49,20 +49,37 @@ def alloc_output(w, device: str = "cuda", fafb: bool = False, top_k: int = 0, th
     return Output(twoF=tw, fa=fa, fb=fb, top_k=top_k, threshold=threshold, top=top, n_above=n_above)
 
 
-def draw_noise_16bit(w, storage: str = "bf16", seed: int = 0, device: str = "cuda"):
+def draw_noise_c64(w, seed: int = 0, device: str = "cuda"):
     """Device-side inputs for a work unit whose SFTs were not drawn on the host
     (noise="device"): CN(0,1) noise from torch's seeded generator on `device`,
-    stored as 16-bit pairs with a per-SFT scale max|re,im| / 256 (the same
-    rule as synth.quantise_sfts).  Returns a paper_0904_1826_amd.WorkUnit."""
+    stored as complex64 ([n_sft, n_bins, 2] float32).  Returns a
+    paper_0904_1826_amd.WorkUnit."""
     import torch
     from paper_0904_1826_amd import WorkUnit
     g = torch.Generator(device=device)
     g.manual_seed(int(seed))
     x = torch.randn((w.n_sft, w.n_bins, 2), generator=g, device=device, dtype=torch.float32) * (0.5 ** 0.5)
+
+    def t(a, dt):
+        return torch.from_numpy(np.ascontiguousarray(a)).to(device=device, dtype=dt)
+
+    return WorkUnit(n_det=int(w.n_det), sft=x, sft_scale=None, k_first=int(w.k_first),
+                    t_sft=float(w.t_sft), t_start=t(w.t_start, torch.float64), pos=t(w.pos, torch.float64),
+                    vel=t(w.vel, torch.float64), sky=t(w.sky, torch.float64), a=t(w.a, torch.float32),
+                    b=t(w.b, torch.float32), f0=float(w.f0), df=float(w.df), n_f=int(w.n_f), fdot0=float(w.fdot0),
+                    dfdot=float(w.dfdot), n_fd=int(w.n_fd), t_ref=float(w.t_ref), dterms=int(w.dterms))
+
+
+def quantise_device(wu, storage: str = "bf16"):
+    """The 16-bit storage of a complex64 device work unit with a per-SFT scale
+    max|re,im| / 256 (the rule of synth.quantise_sfts): a new WorkUnit sharing
+    every other array with `wu`."""
+    import dataclasses
+    import torch
+    x = wu.sft
     m = x.abs().amax(dim=(1, 2))
     scale = torch.where(m > 0, m / 256.0, torch.ones_like(m))
     y = x / scale[:, None, None]
-    del x
     if storage == "bf16":
         stored = y.to(torch.bfloat16).view(torch.int16)
     elif storage == "fp16":
@@ -70,15 +87,16 @@ def draw_noise_16bit(w, storage: str = "bf16", seed: int = 0, device: str = "cud
     else:
         raise ValueError(storage)
     del y
+    return dataclasses.replace(wu, sft=stored, sft_scale=scale.contiguous())
 
-    def t(a, dt):
-        return torch.from_numpy(np.ascontiguousarray(a)).to(device=device, dtype=dt)
 
-    return WorkUnit(n_det=int(w.n_det), sft=stored, sft_scale=scale.contiguous(), k_first=int(w.k_first),
-                    t_sft=float(w.t_sft), t_start=t(w.t_start, torch.float64), pos=t(w.pos, torch.float64),
-                    vel=t(w.vel, torch.float64), sky=t(w.sky, torch.float64), a=t(w.a, torch.float32),
-                    b=t(w.b, torch.float32), f0=float(w.f0), df=float(w.df), n_f=int(w.n_f), fdot0=float(w.fdot0),
-                    dfdot=float(w.dfdot), n_fd=int(w.n_fd), t_ref=float(w.t_ref), dterms=int(w.dterms))
+def draw_noise_16bit(w, storage: str = "bf16", seed: int = 0, device: str = "cuda"):
+    """draw_noise_c64 stored as 16-bit pairs with a per-SFT scale
+    (quantise_device).  Returns a paper_0904_1826_amd.WorkUnit."""
+    wu = draw_noise_c64(w, seed, device)
+    q = quantise_device(wu, storage)
+    del wu
+    return q
 
 
 def host_values(wu, storage: str = "bf16"):

@@ -62,8 +62,9 @@ def slice_edge_workload(coef, side):
 
 
 def sft_block_workloads():
-    """Three units of 1100, 600 and 300 SFTs (3, 2 and 1 blocks of 512 SFTs
-    in the batched form) with 9 spindowns (a block of 8 and a remainder)."""
+    """Three units of 1100, 600 and 300 SFTs (5, 3 and 2 launches of the
+    batched form's default 256 SFTs; 3, 2 and 1 of 512) with 9 spindowns (a
+    block of 8 and a remainder)."""
     return [small_workload(700 + k, n_det=2, slots=s, keep=1.0, n_sky=2, n_fd=9, n_f=300, dterms=8,
                            injections=((1, 4, 150, 12.0),)) for k, s in enumerate([550, 300, 150])]
 

@@ -42,3 +42,15 @@ def test_traffic_only_for_the_measured_kernel_source():
     else:
         assert (b, n) == (None, None)
     assert bench.measured_traffic("demod_interp", "no-such-workload") == (None, None)
+
+
+def test_error_statistics_and_form_names():
+    import numpy as np
+    e = bench.err_stats([4.0004, 10.0, 2.0], [4.0, 10.0, 2.0002])
+    assert abs(e["max_e"] - 1e-4) < 1e-12 and e["n_templates"] == 3 and e["at_metric_tolerance"]
+    assert not bench.err_stats([4.01], [4.0])["at_metric_tolerance"]
+    assert bench.err_stats([np.nan], [4.0])["finite"] is False
+    assert bench.parse_form("bf16+coef16") == ("bf16", False, True)
+    assert bench.parse_form("c64+split") == ("c64", True, False)
+    assert bench.method_slots(8) == 108 and bench.method_slots(16) == 188
+    assert 1 <= bench.host_threads() <= 16

@@ -203,7 +203,7 @@ def test_batch_slice_capacity_edge(torch_cuda, oracle_lib, coef, mix):
 @pytest.mark.parametrize("coef", ["f32", "f16"])
 def test_batch_sft_blocks(torch_cuda, oracle_lib, coef):
     """Units of about 1100, 600 and 300 SFTs: the batched SFT loop runs in
-    launches of 512 SFTs, Fa and Fb carried between them, and each launch
+    launches of 256 SFTs, Fa and Fb carried between them, and each launch
     serves only the units with SFTs left.  Every template against the oracle,
     and bit for bit against single-unit calls (the carried sums are exact
     FP32 values, so the split changes no rounding)."""
@@ -247,3 +247,64 @@ def test_batch_sft_blocks_toplists(torch_cuda):
         assert a[4] == b[4] > 30
         for x, y in zip(a[:4], b[:4]):
             assert np.array_equal(x, y)
+
+
+BATCH_TILES = [("c0", "4 64 256 256"), ("c0", "8 1 100 256"), ("c1", "4 1024 1024 256"), ("c1", "8 7 384 256")]
+
+
+@pytest.mark.parametrize("cls,shape", BATCH_TILES, ids=[f"{c}-{s.replace(' ', '_')}" for c, s in BATCH_TILES])
+def test_batch_tile_from_the_autotune_cache(torch_cuda, oracle_lib, tmp_path, cls, shape):
+    """Batched launch shapes forced through the autotune cache (spindowns in
+    blocks of 4 or of 8 plus a 4-block remainder, tiles per chunk of the
+    per-XCD queues, SFTs per launch): every unit bit for bit equal to its
+    single-unit call with the default tile, and every template within the
+    oracle's tolerance."""
+    torch = torch_cuda
+    coef = "f16" if cls == "c1" else "f32"
+    ws = sft_block_workloads() + [small_workload(720 + k, n_sky=3, n_fd=nfd, n_f=290, slots=40, fdot_lo=-1e-9,
+                                                 injections=()) for k, nfd in enumerate([3, 12, 13])]
+    cache = tmp_path / "tiles.txt"
+    # the single-unit class of the first unit keeps its default tile; the
+    # batch class gets the forced shape
+    c16 = 1 if coef == "f16" else 0
+    cache.write_text(f"s0_d8_k0_c{c16} 8 {5 if c16 else 4} 512 256\nbatch_s0_{cls} {shape}\n")
+    devs = [to_device(w) for w in ws]
+    outs = [alloc_output(w) for w in ws]
+    with _plan_for(ws, coef=coef) as p:
+        p.autotune(devs[0][0], outs[0], cache_path=str(cache))
+        p.batch_compute([d[0] for d in devs], outs)
+        torch.cuda.synchronize()
+    tol = 1e-4 if coef == "f32" else 5e-3
+    for k, w in enumerate(ws):
+        single = alloc_output(w)
+        with _plan_for([w], coef=coef) as p:
+            p.compute(devs[k][0], single)
+            torch.cuda.synchronize()
+        a = outs[k].twoF.cpu().numpy()
+        assert np.array_equal(a, single.twoF.cpu().numpy()), k
+        r = oracle_lib.fstat(w)
+        s, i, j = r["templates"]
+        e = twoF_error(a[s, i, j], r["twoF"])
+        _say(f"  {shape} wu {k}: n_sft={w.n_sft} n_fd={w.n_fd} max_e={e.max():.2e}")
+        assert e.max() <= tol
+
+
+def test_batch_autotune_writes_both_classes(torch_cuda, oracle_lib, tmp_path):
+    """fstat_autotune on one unit tunes the single-unit tile and the batched
+    launch shape and appends both to the cache; a batch then runs with the
+    tuned shape and matches the oracle."""
+    torch = torch_cuda
+    ws = sft_block_workloads()[1:]
+    devs = [to_device(w)[0] for w in ws]
+    outs = [alloc_output(w) for w in ws]
+    cache = tmp_path / "tiles.txt"
+    with _plan_for(ws) as p:
+        p.autotune(devs[0], outs[0], cache_path=str(cache))
+        p.batch_compute(devs, outs)
+        torch.cuda.synchronize()
+    lines = [l.split() for l in cache.read_text().splitlines()]
+    assert [l[0] for l in lines] == ["s0_d8_k0_c0", "batch_s0_c0"] and all(len(l) == 5 for l in lines)
+    _say("tuned:", lines)
+    for w, o in zip(ws, outs):
+        e = twoF_error(o.twoF.cpu().numpy().ravel(), oracle_lib.fstat(w)["twoF"])
+        assert e.max() <= 1e-4

@@ -28,9 +28,10 @@ def test_slice_edge_workloads_sit_at_the_capacity(coef, side):
         assert width == cap + 1
 
 
-def test_sft_block_workloads_span_three_blocks():
+def test_sft_block_workloads_span_several_blocks():
     ws = sft_block_workloads()
     assert [(w.n_sft + 511) // 512 for w in ws] == [3, 2, 1]
+    assert [(w.n_sft + 255) // 256 for w in ws] == [5, 3, 2]
     assert all(w.n_fd % 8 == 1 for w in ws)          # a 4-spindown remainder table as well
 
 
