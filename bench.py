@@ -24,8 +24,12 @@ with whether the form is within the metric's 1e-4.  16-bit storage forms are
 compared with the oracle run on their exactly dequantised values (arithmetic)
 and with the oracle on the complex64 values (storage error).
 
+With --workload large the 256-unit batch is the main case (a step is one
+fstat_batch_compute call over all its units) and nothing else is timed.
+
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--forms c64,c64+split,bf16,fp16,bf16+coef16]
-                  [--workload workunit|semicoherent] [--batch 4|3|0] [--batch-replays R]
+                  [--workload workunit|semicoherent|large] [--batch 4|3|0] [--batch-replays R]
+                  [--large-forms c64,bf16]
 """
 import argparse
 import hashlib
@@ -200,9 +204,12 @@ def main():
                     help="also time the batched form on the 256-unit case (4: complex64 and BF16 storage of the "
                          "same values) or the 64-unit case (3), 0: skip")
     ap.add_argument("--batch-replays", type=int, default=3, help="timed calls per batched form after one warm-up")
-    ap.add_argument("--workload", default="workunit", choices=["workunit", "semicoherent"],
-                    help="the case the forms are timed on: the work-unit-shaped case, or the same case as "
-                         "--semicoherent segments combined by fstat_semicoherent")
+    ap.add_argument("--large-forms", default="c64,bf16",
+                    help="forms of the 256-unit batch, in order: c64 and/or bf16 (the BF16 storage of the same "
+                         "values), optionally +coef16")
+    ap.add_argument("--workload", default="workunit", choices=["workunit", "semicoherent", "large"],
+                    help="the case the forms are timed on: the work-unit-shaped case, the same case as "
+                         "--semicoherent segments combined by fstat_semicoherent, or the 256-unit batch alone")
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle leg (no errors either)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (HBM counter calibration)")
@@ -228,6 +235,8 @@ def main():
         torch.cuda.synchronize()
         say(f"calibration copy: {n} bytes read, {n} bytes written")
         del src, dst
+    if args.workload == "large":
+        return main_large(args, torch, P, synth, say)
     t0 = time.time()
     semi_main = args.workload == "semicoherent"
     if semi_main:
@@ -410,6 +419,32 @@ def main():
     print(json.dumps(line), flush=True)
 
 
+def main_large(args, torch, P, synth, say):
+    """--workload large: the 256-unit batch is the main case; one JSON line
+    whose value is the first form's rate (a step = one fstat_batch_compute
+    call over the 256 units, after one warm-up call)."""
+    args.batch = 4
+    batch, ref = run_batch(args, torch, P, synth, say)
+    if not args.no_cpu_baseline:
+        batch_errors(batch, ref, say)
+    first = [f for f in args.large_forms.split(",") if f][0]
+    key = first
+    r = batch[key]
+    line = {
+        "metric": METRIC, "value": r["value"], "unit": "templates*SFTs/s", "n_gpus": 1,
+        "steps": args.batch_replays, "warmup": 1, "ms_per_step": 1e3 * r["s_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": batch["workload"], "n_wu": batch["n_wu"], "form": key, "kernel": "interp",
+                   "pairs_per_step": batch["pairs_per_step"]},
+        "err": r.get("err"), "large": batch,
+        "roofline": {"bound": "alu", "achieved": r["slots_per_pair"] * batch["pairs_per_step"] / r["kernel_s"] / 1e12,
+                     "peak": PEAK_SLOTS / 1e12, "unit": "TOP/s", "frac": r["roofline_frac"], "traffic": None,
+                     "kernel": "demod_interp_batch", "slots_per_pair": r["slots_per_pair"],
+                     "kernel_ms": 1e3 * r["kernel_s"], "method_rate_vs_peak": r["method_rate_vs_peak"]},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def oracle_free_templates(w, sky_indices):
     """(sky, fdot, f) index arrays of every template of the listed sky points
     in output order (plain index arithmetic)."""
@@ -530,12 +565,15 @@ def run_batch(args, torch, P, synth, say):
                      "roofline_frac": slots_b * bpairs / (kmean * 1e-3) / PEAK_SLOTS,
                      "method_rate_vs_peak": method_slots(dmax) * bpairs / (kmean * 1e-3) / PEAK_SLOTS}
 
-    key, res = timed("c64")
-    batch[key] = res
-    say(f"batch {key}: {res}")
+    forms = [f for f in getattr(args, "large_forms", "c64,bf16").split(",") if f] if large else ["c64"]
     if large:
         for k in units:
             ref["sft"][k] = bdevs[k].sft.cpu().numpy().astype(np.float64).view(np.complex128)[..., 0]
+    for form in [f for f in forms if f.startswith("c64")]:
+        key, res = timed("c64", form.endswith("+coef16"))
+        batch[key] = res
+        say(f"batch {key}: {res}")
+    if large and any(f.startswith("bf16") for f in forms):
         # the BF16 storage of the same values, unit by unit (the complex64
         # copy of each unit is released as its BF16 copy is made)
         for k in range(len(bdevs)):
@@ -543,9 +581,11 @@ def run_batch(args, torch, P, synth, say):
         torch.cuda.empty_cache()
         for k in units:
             ref["sft"][("bf16", k)] = host_values(bdevs[k], "bf16")
-        key, res = timed("bf16")
-        batch[key] = res
-        say(f"batch {key}: {res}")
+        for form in [f for f in forms if f.startswith("bf16")]:
+            key, res = timed("bf16", form.endswith("+coef16"))
+            batch[key] = res
+            say(f"batch {key}: {res}")
+    if "bf16" in batch and "c64" in batch:
         batch["bf16_vs_c64"] = batch["bf16"]["value"] / batch["c64"]["value"]
     del bdevs, bouts
     torch.cuda.empty_cache()
@@ -565,6 +605,8 @@ def batch_errors(batch, ref, say):
     for k in ref["units"]:
         w = ref["ws"][k]
         tm = ref["templates"][k]
+        if w.sft is None and k not in ref["sft"]:
+            return                          # no host copy of these inputs (complex64 form not run)
         r64.append(oracle.fstat(w, tm, sft=ref["sft"].get(k), nthreads=threads)["twoF"])
         if ("bf16", k) in ref["sft"]:
             r16.append(oracle.fstat(w, tm, sft=ref["sft"][("bf16", k)], nthreads=threads)["twoF"])
@@ -575,7 +617,7 @@ def batch_errors(batch, ref, say):
               f"every frequency")
     for key in g:
         gk = np.concatenate(g[key])
-        if key == "c64":
+        if key.startswith("c64"):
             batch[key]["err"] = err_stats(gk, r64)
             batch[key]["err"]["reference"] = "oracle on the complex64 values"
         else:
@@ -583,7 +625,7 @@ def batch_errors(batch, ref, say):
             batch[key]["err"]["reference"] = "oracle on the exactly dequantised BF16 values"
             batch[key]["storage_err_vs_c64"] = err_stats(gk, r64, tol=5e-3)
         batch[key]["err"]["sample"] = sample
-    if "bf16" in batch and "c64" in batch:
+    if "bf16" in batch and "c64" in batch and "err" in batch["bf16"] and "err" in batch["c64"]:
         ok = batch["bf16"]["err"]["at_metric_tolerance"] and batch["c64"]["err"]["at_metric_tolerance"]
         batch["mixed_exceeds_plain_at_tolerance"] = bool(ok and batch["bf16_vs_c64"] > 1.0)
     say(f"batch errors: { {k: batch[k].get('err') for k in g} }")
