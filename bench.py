@@ -438,8 +438,8 @@ def main_large(args, torch, P, synth, say):
                    "pairs_per_step": batch["pairs_per_step"]},
         "err": r.get("err"), "large": batch,
         "roofline": {"bound": "alu", "achieved": r["slots_per_pair"] * batch["pairs_per_step"] / r["kernel_s"] / 1e12,
-                     "peak": PEAK_SLOTS / 1e12, "unit": "TOP/s", "frac": r["roofline_frac"], "traffic": None,
-                     "kernel": "demod_interp_batch", "slots_per_pair": r["slots_per_pair"],
+                     "peak": PEAK_SLOTS / 1e12, "unit": "TOP/s", "frac": r["roofline_frac"],
+                     "traffic": r.get("traffic"), "kernel": "demod_interp_batch", "slots_per_pair": r["slots_per_pair"],
                      "kernel_ms": 1e3 * r["kernel_s"], "method_rate_vs_peak": r["method_rate_vs_peak"]},
     }
     print(json.dumps(line), flush=True)
@@ -560,8 +560,10 @@ def run_batch(args, torch, P, synth, say):
         key = storage + ("+coef16" if c16 else "")
         ref["gpu"][key] = {k: take(bouts[k].twoF, tm[k]) for k in units}
         kmean = float(np.mean(kms))
+        # HBM bytes per call from the committed counter summary (BF16 FP32-coefficient call of the 256-unit case)
+        traffic = measured_traffic("demod_interp_batch", "large")[0] if (large and key == "bf16") else None
         return key, {"value": bpairs / el, "s_per_step": el, "warmup_s": warm_s, "kernel_s": kmean / 1e3,
-                     "slots_per_pair": slots_b,
+                     "traffic": traffic, "slots_per_pair": slots_b,
                      "roofline_frac": slots_b * bpairs / (kmean * 1e-3) / PEAK_SLOTS,
                      "method_rate_vs_peak": method_slots(dmax) * bpairs / (kmean * 1e-3) / PEAK_SLOTS}
 

@@ -72,7 +72,20 @@ def test_batch_64_work_units_full_size(torch_cuda, oracle_lib):
         assert e.max() <= 1e-4, (k, e.max())
         assert outs[k].twoF[x.sky_index, x.fdot_index, x.f_index].item() > 0.4 * x.snr ** 2
     _say(f"  sampled max 2F error over 64 units: {worst:.2e}")
-    # the mixed-precision form (FP16 polynomial coefficients) on the same inputs
+    # the units the persistent queues serve last (fewest SFTs) and units with a
+    # 4-spindown remainder table: every template of their last sky point
+    # (every spindown, every frequency including the ragged last tile)
+    by_sft = sorted(range(len(ws)), key=lambda k: ws[k].n_sft)
+    rem4 = [k for k in range(len(ws)) if 1 <= ws[k].n_fd % 8 <= 4 and ws[k].n_fd > 8][:3]
+    for k in sorted(set(by_sft[:3] + rem4)):
+        w = ws[k]
+        s_, i_, j_ = oracle_lib.all_templates(w, [w.n_sky - 1])
+        ref = oracle_lib.fstat(w, (s_, i_, j_))["twoF"]
+        got = outs[k].twoF[w.n_sky - 1].cpu().numpy().ravel().astype(np.float64)
+        e = twoF_error(got, ref)
+        _say(f"  unit {k}: {w.n_sft} SFTs, {w.n_fd} spindowns, last sky point: max 2F error {e.max():.2e}")
+        assert e.max() <= 1e-4, (k, e.max())
+    # the FP16-coefficient form (outside the metric's 1e-4; its own bound) on the same inputs
     with _plan_for(ws, coef="f16") as p:
         p.batch_compute(devs, outs)
         torch.cuda.synchronize()
@@ -124,7 +137,21 @@ def test_batch_256_work_units_bf16_full_size(torch_cuda, oracle_lib):
         _say(f"  unit {k}: {w.n_sft} SFTs x {w.n_bins} bins, sampled max 2F error {e.max():.2e}")
         assert e.max() <= 1e-4, (k, e.max())
         del vals
-    # the mixed-precision form: BF16 storage and FP16 polynomial coefficients
+    # the units served last (fewest SFTs): their last sky point, first and
+    # last spindown, every frequency
+    by_sft = sorted(range(len(ws)), key=lambda k: ws[k].n_sft)
+    for k in by_sft[:2]:
+        w = ws[k]
+        vals = host_values(devs[k], "bf16")
+        s_, i_, j_ = np.meshgrid([w.n_sky - 1], [0, w.n_fd - 1], np.arange(w.n_f), indexing="ij")
+        s_, i_, j_ = (a.ravel().astype(np.int32) for a in (s_, i_, j_))
+        ref = oracle_lib.fstat(w, (s_, i_, j_), sft=vals)["twoF"]
+        got = outs[k].twoF[w.n_sky - 1].cpu().numpy()[i_, j_].astype(np.float64)
+        e = twoF_error(got, ref)
+        _say(f"  unit {k} (served last): {w.n_sft} SFTs, last sky point: max 2F error {e.max():.2e}")
+        assert e.max() <= 1e-4, (k, e.max())
+        del vals
+    # BF16 storage with FP16 polynomial coefficients (outside the metric's 1e-4; its own bound)
     with _plan_for(ws, storage="bf16", coef="f16") as p:
         t0 = time.perf_counter()
         p.batch_compute(devs, outs)

@@ -80,7 +80,8 @@ def test_split_phase_bins_and_phase_error(torch_cuda, oracle_lib, cfg1):
     d = np.abs(ph.cpu().numpy() - ph_ref[r, idx[3]])
     d = np.minimum(d, 1.0 - d)
     _say(f"split-FP32 phase vs FP64: max |dphi| = {d.max():.2e} cycles, rms {math.sqrt(np.mean(d * d)):.2e}")
-    assert d.max() < 2e-4
+    # 1e-5 cycles (6e-5 rad) per SFT keeps the 2F error well inside the 1e-4 bound
+    assert d.max() < 1e-5
 
 
 def test_precision_forms_per_block(torch_cuda, oracle_lib, cfg1):
