@@ -112,15 +112,17 @@ def test_autotune_and_cache(torch_cuda, oracle_lib, wl, tmp_path):
         p.autotune(wu, out, cache_path=cache)
         p.compute(wu, out)
         torch.cuda.synchronize()
-    lines = open(cache).read().split()
-    assert len(lines) == 5 and lines[0].startswith("s0_d8_k")
+    lines = [l.split() for l in open(cache).read().splitlines()]
+    # one line for the single-unit class, one for the plan's batch class
+    assert len(lines) == 2 and all(len(l) == 5 for l in lines)
+    assert lines[0][0].startswith("s0_d8_k") and lines[1][0] == "batch_s0_c0"
     ref = oracle_lib.fstat(wl)["twoF"]
     assert twoF_error(out.twoF.cpu().numpy().ravel(), ref).max() <= 1e-4
     # a cache entry chosen by hand is taken as is: one spindown per thread and
     # the SFT loop split into launches of 5 SFTs (running sums in between)
-    key = lines[0]
+    key = lines[0][0]
     with open(cache, "w") as f:
-        f.write(f"{key} 1 3 5 256\n")
+        f.write(f"{key} 1 3 5 256\n{' '.join(lines[1])}\n")
     out2 = alloc_output(wl)
     with _plan(wl) as p:
         p.autotune(wu, out2, cache_path=cache)

@@ -147,6 +147,59 @@ def test_time_domain_matched_filter_agreement(oracle_lib):
     assert errs[0] < 0.08 and errs[2] < 0.03, errs
 
 
+def test_time_domain_discrete_kernel_identity_and_convergence(oracle_lib):
+    """The survey's time-domain pin, at 4096 samples per SFT: (1) the
+    time-domain matched filter of each SFT's samples with the SFT-linear phase
+    equals the sum over all N bins of the SFT's DFT weighted by the discrete
+    Dirichlet kernel (1/N) sum_j exp(-2 pi i kappa j / N), to rounding (an
+    identity of the DFT, which checks this test's own conventions); (2) the
+    oracle's Fa, which keeps the 2D bins nearest the instantaneous frequency
+    and uses the continuous kernel sinc, approaches the time-domain Fa as D
+    grows, to 2.5e-4 at D = 256 (the rest is the continuous kernel standing
+    in for the discrete one, of order (D / N)^2)."""
+    N = 4096
+    w = synth.make_workload("tdmf4096", seed=9, n_det=1, slots_per_det=6, keep_frac=1.0, jitter=20.0, t_sft=60.0,
+                            f0=20.0, n_f=8, n_sky=2, n_fd=1, fdot_lo=0.0, fdot_hi=0.0, dterms=8,
+                            injections=(), noise=False)
+    k_first = w.k_first + w.n_bins // 2 - N // 2       # a band of N bins around the templates
+    w = replace(w, k_first=k_first, sft=np.zeros((w.n_sft, N), dtype=np.complex64))
+    rng = np.random.default_rng(3)
+    j = np.arange(N)
+    s_i, j_i = 1, 4
+    f = w.f0 + j_i * w.df
+    # noise plus a tone 0.3 bins from the template's frequency (heterodyned samples)
+    td = (rng.standard_normal((w.n_sft, N)) + 1j * rng.standard_normal((w.n_sft, N))) / math.sqrt(2)
+    td += 3.0 * np.exp(2j * np.pi * (f * w.t_sft - k_first + 0.3) * j / N)
+    X = np.fft.fft(td, axis=1) / N                    # column q is bin k_first + q
+    # the discrete kernel by its geometric-series closed form, checked against the plain sum
+    def kdisc(kap):
+        e1 = np.exp(-2j * np.pi * kap)
+        eN = np.exp(-2j * np.pi * kap / N)
+        return (1.0 - e1) / (N * (1.0 - eN))
+    for kap in rng.uniform(-50.0, 50.0, 8):
+        assert abs(kdisc(kap) - np.mean(np.exp(-2j * np.pi * kap * j / N))) < 1e-12
+    n = w.sky[s_i]
+    tau = (w.t_start + 0.5 * w.t_sft - w.t_ref) + w.pos @ n
+    finst = f * (1.0 + w.vel @ n)                     # fdot = 0
+    phi = tau * f
+    fa_td = 0.0
+    for al in range(w.n_sft):
+        t_rel = j * (w.t_sft / N) - 0.5 * w.t_sft
+        cyc = phi[al] + finst[al] * t_rel - (w.k_first * j) / N
+        z_td = np.mean(td[al] * np.exp(-2j * np.pi * cyc))
+        dphi = finst[al] * w.t_sft
+        kap = dphi - (k_first + np.arange(N))
+        z_disc = np.exp(-2j * np.pi * (phi[al] - dphi / 2.0)) * np.sum(X[al] * kdisc(kap))
+        assert abs(z_disc - z_td) <= 1e-10 * abs(z_td), (al, abs(z_disc - z_td) / abs(z_td))
+        fa_td += w.a[s_i, al] * z_td
+    errs = {}
+    for dterms in (8, 64, 256):
+        r = oracle_lib.fstat(replace(w, dterms=dterms), ([s_i], [0], [j_i]), sft=X)
+        errs[dterms] = abs(r["Fa"][0] - fa_td) / abs(fa_td)
+    assert errs[8] > errs[64] > errs[256], errs
+    assert errs[256] < 5e-4 and errs[8] < 0.05, errs
+
+
 # ------------------------------------------------- P2: noise statistics ---
 def test_noise_only_chi2_4(oracle_lib):
     from scipy import stats, integrate
