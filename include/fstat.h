@@ -108,7 +108,11 @@ typedef struct fstat_desc {
 
 /* One work unit (all pointers are device pointers, caller-owned). */
 typedef struct fstat_wu {
-  int32_t n_det;              /* detectors, >= 1 (informational: the sum is coherent) */
+  int32_t n_det;              /* detectors, >= 1 */
+  const int64_t* det_offset;  /* HOST array [n_det + 1] or NULL: the SFTs of detector d are rows
+                                 [det_offset[d], det_offset[d+1]) (the flat data + offset arrays of
+                                 Section 7); checked (0, non-decreasing, n_sft at the end), otherwise
+                                 informational: the sum over detectors is coherent */
   int64_t n_sft;              /* SFTs of all detectors together */
   int64_t n_bins;             /* bins per SFT */
   int64_t k_first;            /* absolute bin index of column 0 (bin k <-> k / T Hz) */

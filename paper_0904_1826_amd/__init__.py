@@ -62,7 +62,8 @@ class fstat_desc(ctypes.Structure):
 
 
 class fstat_wu(ctypes.Structure):
-    _fields_ = [("n_det", ctypes.c_int32), ("n_sft", ctypes.c_int64), ("n_bins", ctypes.c_int64),
+    _fields_ = [("n_det", ctypes.c_int32), ("det_offset", ctypes.c_void_p), ("n_sft", ctypes.c_int64),
+                ("n_bins", ctypes.c_int64),
                 ("k_first", ctypes.c_int64), ("t_sft", ctypes.c_double), ("sft", ctypes.c_void_p),
                 ("sft_scale", ctypes.c_void_p), ("t_start", ctypes.c_void_p), ("pos", ctypes.c_void_p),
                 ("vel", ctypes.c_void_p), ("n_sky", ctypes.c_int64), ("sky", ctypes.c_void_p),
@@ -252,6 +253,7 @@ class WorkUnit:
     n_fd: int
     t_ref: float
     dterms: int
+    det_offset: object = None  # host [n_det + 1] SFT offsets of the detectors, or None
 
     @property
     def n_sft(self):
@@ -281,10 +283,20 @@ class Output:
 
 
 def _wu_struct(w) -> fstat_wu:
-    return fstat_wu(int(w.n_det), int(w.n_sft), int(w.n_bins), int(w.k_first), float(w.t_sft), _ptr(w.sft),
-                    _ptr(w.sft_scale), _ptr(w.t_start), _ptr(w.pos), _ptr(w.vel), int(w.n_sky), _ptr(w.sky),
-                    _ptr(w.a), _ptr(w.b), float(w.f0), float(w.df), int(w.n_f), float(w.fdot0), float(w.dfdot),
-                    int(w.n_fd), float(w.t_ref), int(w.dterms))
+    off = getattr(w, "det_offset", None)
+    keep = None
+    if off is not None:                                  # a host array the call reads synchronously
+        vals = [int(x) for x in (off.tolist() if hasattr(off, "tolist") else off)]
+        if len(vals) != int(w.n_det) + 1:
+            raise ValueError(f"det_offset: {len(vals)} entries, expected n_det + 1 = {int(w.n_det) + 1}")
+        keep = (ctypes.c_int64 * len(vals))(*vals)
+    s = fstat_wu(int(w.n_det), ctypes.cast(keep, ctypes.c_void_p) if keep is not None else None, int(w.n_sft),
+                 int(w.n_bins), int(w.k_first), float(w.t_sft), _ptr(w.sft), _ptr(w.sft_scale), _ptr(w.t_start),
+                 _ptr(w.pos), _ptr(w.vel), int(w.n_sky), _ptr(w.sky), _ptr(w.a), _ptr(w.b), float(w.f0),
+                 float(w.df), int(w.n_f), float(w.fdot0), float(w.dfdot), int(w.n_fd), float(w.t_ref),
+                 int(w.dterms))
+    s._keep = keep                                       # alive as long as the struct
+    return s
 
 
 def _out_struct(o) -> fstat_out:
@@ -397,7 +409,8 @@ def fstat_batch_compute(plan, wus: Sequence, outs: Sequence, stream=None) -> Non
 
 def fstat_semicoherent(plan, segs: Sequence, out, stream=None) -> None:
     n = len(segs)
-    ws = (fstat_wu * max(n, 1))(*[_checked(plan, w)[0] for w in segs])
+    structs = [_checked(plan, w)[0] for w in segs]       # hold each struct's det_offset copy during the call
+    ws = (fstat_wu * max(n, 1))(*structs)
     if n:
         check_output(segs[0], out)
     o = _out_struct(out)

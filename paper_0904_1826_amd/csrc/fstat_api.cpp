@@ -212,6 +212,13 @@ int validate_wu(fstat_plan* p, const fstat_wu* w, const fstat_out* o, int idx) {
   if (o->top_k > 0 && !std::isfinite(o->threshold))
     return set_err(p, FSTAT_E_ARG, "%snon-finite toplist threshold", tag);
   if (w->n_det < 1) return set_err(p, FSTAT_E_ARG, "%sn_det < 1", tag);
+  if (w->det_offset) {               // detector blocks of the flat SFT array
+    if (w->det_offset[0] != 0 || w->det_offset[w->n_det] != w->n_sft)
+      return set_err(p, FSTAT_E_ARG, "%sdet_offset must run from 0 to n_sft", tag);
+    for (int d = 0; d < w->n_det; ++d)
+      if (w->det_offset[d + 1] < w->det_offset[d])
+        return set_err(p, FSTAT_E_ARG, "%sdet_offset decreases at detector %d", tag, d);
+  }
   if (w->dterms < 1 || w->dterms > d.max_dterms) return set_err(p, FSTAT_E_ARG, "%sdterms %d outside [1, %d]", tag, w->dterms, d.max_dterms);
   if (w->n_sft < 1 || w->n_bins < 1 || w->n_sky < 1 || w->n_f < 1 || w->n_fd < 1)
     return set_err(p, FSTAT_E_ARG, "%ssizes must be >= 1", tag);

@@ -30,7 +30,7 @@ def to_device(w, storage: str = "c64", device: str = "cuda"):
                   t_start=t(w.t_start, torch.float64), pos=t(w.pos, torch.float64), vel=t(w.vel, torch.float64),
                   sky=t(w.sky, torch.float64), a=t(w.a, torch.float32), b=t(w.b, torch.float32), f0=float(w.f0),
                   df=float(w.df), n_f=int(w.n_f), fdot0=float(w.fdot0), dfdot=float(w.dfdot), n_fd=int(w.n_fd),
-                  t_ref=float(w.t_ref), dterms=int(w.dterms))
+                  t_ref=float(w.t_ref), dterms=int(w.dterms), det_offset=np.asarray(w.det_offset, dtype=np.int64))
     return wu, deq
 
 
@@ -67,7 +67,8 @@ def draw_noise_c64(w, seed: int = 0, device: str = "cuda"):
                     t_sft=float(w.t_sft), t_start=t(w.t_start, torch.float64), pos=t(w.pos, torch.float64),
                     vel=t(w.vel, torch.float64), sky=t(w.sky, torch.float64), a=t(w.a, torch.float32),
                     b=t(w.b, torch.float32), f0=float(w.f0), df=float(w.df), n_f=int(w.n_f), fdot0=float(w.fdot0),
-                    dfdot=float(w.dfdot), n_fd=int(w.n_fd), t_ref=float(w.t_ref), dterms=int(w.dterms))
+                    dfdot=float(w.dfdot), n_fd=int(w.n_fd), t_ref=float(w.t_ref), dterms=int(w.dterms),
+                    det_offset=np.asarray(w.det_offset, dtype=np.int64))
 
 
 def quantise_device(wu, storage: str = "bf16"):

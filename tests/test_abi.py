@@ -139,5 +139,17 @@ def test_array_checks_refuse_storage_mismatch_and_bad_outputs():
             P.check_output(w, SimpleNamespace(**kw))
 
 
+def test_det_offset_length_is_checked_by_the_binding():
+    w = _host_wu()
+    w.det_offset = [0, 5]
+    w.n_det = 2
+    with pytest.raises(ValueError, match="det_offset"):
+        P._wu_struct(w)
+    w.det_offset = [0, 2, 5]
+    w.n_sft, w.n_bins, w.n_sky = 5, 40, 2          # the WorkUnit properties
+    s = P._wu_struct(w)
+    assert s.det_offset and s.n_det == 2
+
+
 def test_noalloc_entry_point_null_arguments(lib):
     assert lib.fstat_compute_noalloc(None, None, None, None) == P.FSTAT_E_ARG

@@ -88,14 +88,20 @@ def test_host_side_argument_errors(torch_cuda, wl):
     out = alloc_output(wl)
     with _plan(wl) as p:
         import dataclasses
+        n = wl.n_sft
         bad = [dict(dterms=0), dict(dterms=17), dict(a=None), dict(t_start=None), dict(f0=-1.0), dict(df=0.0),
-               dict(t_sft=float("nan")), dict(n_f=wl.n_f + 1)]
+               dict(t_sft=float("nan")), dict(n_f=wl.n_f + 1), dict(det_offset=np.array([1, 5, n])),
+               dict(det_offset=np.array([0, 5, n - 1])), dict(det_offset=np.array([0, n + 2, n]))]
         for kw in bad:
             w2 = dataclasses.replace(wu, **kw)
             o2 = alloc_output(dataclasses.replace(wl, n_f=w2.n_f))      # outputs sized for the unit
             with pytest.raises(P.FstatError) as e:
                 p.compute(w2, o2)
             assert e.value.code in (P.FSTAT_E_ARG, P.FSTAT_E_SIZE), kw
+        for off in ([0, n // 2, n], [0, n, n], [0, 0, n]):      # consistent detector blocks are accepted
+            p.compute(dataclasses.replace(wu, det_offset=np.array(off)), out)
+        torch_sync = __import__("torch").cuda.synchronize
+        torch_sync()
         # arrays that do not match the unit's sizes are refused by the binding
         with pytest.raises(ValueError, match="elements"):
             p.compute(dataclasses.replace(wu, n_f=wl.n_f - 1), out)
