@@ -140,15 +140,18 @@ def test_array_checks_refuse_storage_mismatch_and_bad_outputs():
 
 
 def test_det_offset_length_is_checked_by_the_binding():
-    w = _host_wu()
-    w.det_offset = [0, 5]
-    w.n_det = 2
+    """det_offset is a host array of n_det + 1 entries copied into the call's
+    struct; a wrong length is refused before any call."""
+    from types import SimpleNamespace
+    fields = dict(n_det=2, n_sft=5, n_bins=40, k_first=1, t_sft=1.0, sft=None, sft_scale=None, t_start=None,
+                  pos=None, vel=None, n_sky=2, sky=None, a=None, b=None, f0=1.0, df=1.0, n_f=1, fdot0=0.0, dfdot=0.0,
+                  n_fd=1, t_ref=0.0, dterms=1)
     with pytest.raises(ValueError, match="det_offset"):
-        P._wu_struct(w)
-    w.det_offset = [0, 2, 5]
-    w.n_sft, w.n_bins, w.n_sky = 5, 40, 2          # the WorkUnit properties
-    s = P._wu_struct(w)
-    assert s.det_offset and s.n_det == 2
+        P._wu_struct(SimpleNamespace(det_offset=[0, 5], **fields))
+    s = P._wu_struct(SimpleNamespace(det_offset=[0, 2, 5], **fields))
+    arr = ctypes.cast(s.det_offset, ctypes.POINTER(ctypes.c_int64))
+    assert [arr[i] for i in range(3)] == [0, 2, 5] and s.n_det == 2
+    assert not P._wu_struct(SimpleNamespace(det_offset=None, **fields)).det_offset
 
 
 def test_noalloc_entry_point_null_arguments(lib):
