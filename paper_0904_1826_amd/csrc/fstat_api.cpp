@@ -1369,7 +1369,7 @@ int fstat_autotune(fstat_plan* p, const fstat_wu* wu, const fstat_out* out, void
     Tile best_t = default_batch_tile();
     for (int nfd : {8, 4})
       for (int chunk : {64, 256, 1024})
-        for (int sb : {256, 512, 1024}) {
+        for (int sb : {256, 512, 1024, 0}) {
           const Tile t{nfd, chunk, 0, sb, fstat::kThreads, 0, 0};
           p->tiles[bkey] = t;
           float ms = 0.f;
