@@ -222,11 +222,15 @@ int fstat_compute_noalloc(fstat_plan* p, const fstat_wu* wu, const fstat_out* ou
 
 /* 2F of many work units with uneven SFT counts, bands and template grids in
  * persistent launches shared by all of them (the "several clients per
- * system" idea of the Cell port, Section 5, done on one device): one pair of
- * launches per block of SFTs (256 unless fstat_autotune chose another), each
- * over the units with SFTs left; inside a launch the tiles are dealt to one
- * queue per XCD in chunks of consecutive tiles, so that tiles sharing
- * coefficients are served by one L2.  All
+ * system" idea of the Cell port, Section 5, done on one device).  Each
+ * unit's spindowns are split into ranges run 8, 7, 6, 5 or 4 per thread (8 or
+ * 4 with FP16 coefficients), chosen per unit to waste the fewest lanes
+ * weighted by the measured cost of each size (13 spindowns run as 8 + 5, not
+ * as 8 and a partial 8).  Per block of SFTs (256 unless fstat_autotune chose
+ * another) one persistent launch per spindown-block size runs over the units
+ * with SFTs left; inside a launch the tiles are dealt to one queue per XCD in
+ * chunks of consecutive tiles, so that tiles sharing coefficients are served
+ * by one L2.  All
  * work units are validated and band-checked before anything is launched; on
  * failure the index of the first failing work unit is in fstat_last_error.
  * The launch sequence is captured once in a hipGraph per signature (table
@@ -234,8 +238,8 @@ int fstat_compute_noalloc(fstat_plan* p, const fstat_wu* wu, const fstat_out* ou
  * replayed; the work-unit table lives in device memory, so a replay may
  * change every pointer and size of the units.  Plan scratch per unit:
  * geometry (16 B per sky point and SFT), coefficients (64 B per SFT and bin,
- * 32 B with FP16 coefficients) and, for units of more than 512 SFTs, the
- * carried Fa, Fb (16 B per template); units are processed in groups whose
+ * 32 B with FP16 coefficients) and, for units of more SFTs than one block,
+ * the carried Fa, Fb (16 B per template); units are processed in groups whose
  * scratch fits 64 GB (FSTAT_BATCH_SCRATCH_GB overrides).  outs[i] belongs to
  * wus[i]. */
 int fstat_batch_compute(fstat_plan* p, const fstat_wu* wus, int32_t n_wu, const fstat_out* outs,
@@ -289,10 +293,10 @@ int fstat_detector_inputs(fstat_plan* p, const fstat_earth* earth, int32_t n_sit
  * ("s<storage>_d<Dterms>_k<kernel>_c<coef16>"): spindowns or frequencies per
  * thread, waves per SIMD (interp) or SFTs per LDS chunk (direct), SFTs per
  * launch with 0 = all, work-group size of the interp kernel.  Batch classes
- * ("batch_s<storage>_c<coef16>"): spindowns per thread (8: blocks of 8 and a
- * remainder of 1 to 4 in a block of 4; 4: blocks of 4), tiles per chunk of
- * the per-XCD queues, SFTs per launch (0 = all), 256.  Lines naming a shape
- * the library does not implement are ignored. */
+ * ("batch_s<storage>_c<coef16>"): spindowns per thread (8: blocks of 4 to 8
+ * split per unit as fstat_batch_compute describes; 4: blocks of 4 only),
+ * tiles per chunk of the per-XCD queues, SFTs per launch (0 = all), 256.
+ * Lines naming a shape the library does not implement are ignored. */
 int fstat_autotune(fstat_plan* p, const fstat_wu* wu, const fstat_out* out, void* stream,
                    const char* cache_path);
 

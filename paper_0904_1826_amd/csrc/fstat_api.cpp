@@ -76,9 +76,9 @@ struct fstat_plan {
   size_t ents_cap = 0;
   unsigned long long* counter = nullptr;
   hipStream_t cap_stream = nullptr;
-  // persistent grids of the 8- and 4-spindown batch kernels, with [1] and
-  // without [0] the global-memory fallback
-  int batch_grid[2] = {0, 0}, batch_grid4[2] = {0, 0};
+  // persistent grids of the batch kernels with 8 - i spindowns per thread,
+  // with [i][1] and without [i][0] the global-memory fallback
+  int batch_grid[fstat::kBatchSizes][2] = {};
   std::map<std::vector<int64_t>, hipGraphExec_t> graphs;
   // fault injection (host-side forcing of error paths); force_seg > 0 runs the
   // interp kernels without the global-memory path at that slice width
@@ -663,9 +663,10 @@ double status_p(const fstat::GeoStatus& g) {
 }
 
 // Launch shape of the batched form (a Tile under the plan's batch class):
-// nf_reg 8 runs each unit's spindowns in blocks of 8 and a remainder of 1 to
-// 4 in a block of 4, nf_reg 4 runs all of them in blocks of 4; chunk = tiles
-// per chunk of the per-XCD queues; sblock = SFTs per launch (0: all).
+// nf_reg 8 runs each unit's spindowns in blocks of 4 to 8 per thread (8 or 4
+// with FP16 coefficients) chosen by split_spindowns, nf_reg 4 runs all of
+// them in blocks of 4; chunk = tiles per chunk of the per-XCD queues;
+// sblock = SFTs per launch (0: all).
 std::string batch_key(const fstat_plan* p) {
   char b[64];
   snprintf(b, sizeof b, "batch_s%d_c%d", p->d.storage, coef16(p) ? 1 : 0);
@@ -685,6 +686,61 @@ Tile default_batch_tile() { return Tile{8, 256, 0, 256, fstat::kThreads, 0, 0}; 
 Tile batch_tile(const fstat_plan* p) {
   auto it = p->tiles.find(batch_key(p));
   return it != p->tiles.end() ? it->second : default_batch_tile();
+}
+
+// The spindowns of one unit in the batched form as blocks of b per thread,
+// b from the allowed sizes (bit b of `sizes`, 4 <= b <= 8): n[8 - b]
+// spindowns run b per thread, as consecutive ranges (8 per thread first),
+// each range's last block possibly partial.  The split minimises the lanes
+// computed weighted by the time per lane of each block size, measured with
+// the batched kernel on the work-unit-shaped case with 840 spindowns (every
+// size divides it; identical outputs): 8: 1, 7: 1.072, 6: 1.136, 5: 1.259,
+// 4: 1.415 (fewer spindowns per thread use each staged slice for fewer
+// pairs).  So 13 spindowns run as 8 + 5 rather than as 8 and a partial 8,
+// 12 as 6 + 6 rather than 8 + 4, and 5 as one block of 5.  All but the last two to three blocks' worth run
+// in blocks of the largest allowed size (the cheapest per lane); the tail
+// is split exactly by dynamic programming.
+struct FdSplit {
+  int64_t n[fstat::kBatchSizes] = {};
+};
+
+FdSplit split_spindowns(int64_t nf, unsigned sizes) {
+  static const double kLaneCost[9] = {0.0, 0.0, 0.0, 0.0, 1.415, 1.259, 1.136, 1.072, 1.0};
+  FdSplit r;
+  int bmax = 0;
+  for (int b = 8; b >= 4 && !bmax; --b) bmax = (sizes >> b) & 1u ? b : 0;
+  if (nf <= 0 || !bmax) return r;
+  const int64_t head = nf > 3 * bmax ? ((nf - 2 * bmax) / bmax) * bmax : 0;
+  const int t = (int)(nf - head);                 // below 3 bmax <= 24
+  double best[25];
+  int pick[25];
+  best[0] = 0.0;
+  pick[0] = 0;
+  for (int x = 1; x <= t; ++x) {
+    best[x] = HUGE_VAL;
+    pick[x] = bmax;
+    for (int b = 8; b >= 4; --b) {                // larger blocks first: ties take fewer tiles
+      if (!((sizes >> b) & 1u)) continue;
+      const double c = best[x > b ? x - b : 0] + b * kLaneCost[b];
+      if (c < best[x]) {
+        best[x] = c;
+        pick[x] = b;
+      }
+    }
+  }
+  r.n[8 - bmax] = head;
+  for (int x = t; x > 0;) {
+    const int b = pick[x], take = x > b ? b : x;
+    r.n[8 - b] += take;
+    x -= take;
+  }
+  return r;
+}
+
+// Block sizes the batched form may use with this plan and launch shape.
+unsigned batch_sizes(const fstat_plan* p, const Tile& bt) {
+  if (bt.nf_reg == 4) return 1u << 4;
+  return coef16(p) ? (1u << 8) | (1u << 4) : 0x1F0u;      // {8, 4} or 4..8
 }
 
 // Batched interp path: work units are grouped so that one group's scratch
@@ -719,16 +775,19 @@ int batch_interp(fstat_plan* p, const fstat_wu* wus, int n, const fstat_out* out
   if (rc) return rc;
   rc = ensure_pinned_pair(p, &p->bstat_d, &p->bstat_h, &p->bstat_cap, (size_t)n, "batch status");
   if (rc) return rc;
-  // per group: one entry per unit and up to two demodulation entries per unit
-  rc = ensure_pinned_pair(p, &p->ents_d, &p->ents_h, &p->ents_cap, 3 * (size_t)n, "work-unit table");
+  // per group: one entry per unit and up to one demodulation entry per unit
+  // and block size
+  constexpr int kEnts = 1 + fstat::kBatchSizes;
+  rc = ensure_pinned_pair(p, &p->ents_d, &p->ents_h, &p->ents_cap, kEnts * (size_t)n, "work-unit table");
   if (rc) return rc;
   for (int k = 0; k < n; ++k) {
     rc = ensure_ctab(p, wus[k].dterms);
     if (rc) return rc;
   }
-  if (!p->counter) {               // the per-XCD tile queues of the 8- and the 4-spindown launch
+  if (!p->counter) {               // the per-XCD tile queues of the launch of each block size
     size_t have = 0;
-    rc = dev_alloc(p, (void**)&p->counter, &have, 2 * fstat::kXcds * sizeof(unsigned long long), "tile counters");
+    rc = dev_alloc(p, (void**)&p->counter, &have, fstat::kBatchSizes * fstat::kXcds * sizeof(unsigned long long),
+                   "tile counters");
     if (rc) return rc;
   }
   bool any_top = false;
@@ -747,11 +806,10 @@ int batch_interp(fstat_plan* p, const fstat_wu* wus, int n, const fstat_out* out
     rc = dev_alloc(p, &p->bcount, &p->bcount_bytes, count_need, "toplist counters");
     if (rc) return rc;
   }
-  if (!p->batch_grid[0]) {
-    for (int sf = 0; sf < 2; ++sf) {
-      p->batch_grid[sf] = fstat::interp_batch_grid(coef16(p), 8, sf == 0);
-      p->batch_grid4[sf] = fstat::interp_batch_grid(coef16(p), 4, sf == 0);
-    }
+  const unsigned sizes = batch_sizes(p, bt);
+  for (int i = 0; i < fstat::kBatchSizes; ++i) {
+    if (!((sizes >> (8 - i)) & 1u) || p->batch_grid[i][0]) continue;
+    for (int sf = 0; sf < 2; ++sf) p->batch_grid[i][sf] = fstat::interp_batch_grid(coef16(p), 8 - i, sf == 0);
   }
   // every work unit is checked before anything is demodulated
   if (groups.size() > 1) {
@@ -767,15 +825,15 @@ int batch_interp(fstat_plan* p, const fstat_wu* wus, int n, const fstat_out* out
     rc = batch_check(p, wus, outs, g.first, g.second, (char*)p->arena, offs, st);
     if (rc) return rc;
     // table of the group: one entry per work unit (coefficient passes and
-    // toplists), most SFTs first; then the demodulation tables: each unit's
-    // spindowns [0, split) in blocks of 8 and the remaining 1 to 4 in one
-    // block of 4 (a remainder of 5 to 7 takes a partial block of 8), one
+    // toplists), most SFTs first; then one demodulation table per block size
+    // (8 down to 4 spindowns per thread): each unit's spindowns split by
+    // split_spindowns into consecutive ranges, one per block size; one
     // persistent launch per table, most SFTs first within each
     std::vector<int> order;
     for (int k = g.first; k < g.second; ++k) order.push_back(k);
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return wus[x].n_sft > wus[y].n_sft; });
     const int m = (int)order.size();
-    fstat::BatchEntry* eh = p->ents_h + 3 * (size_t)g.first;
+    fstat::BatchEntry* eh = p->ents_h + kEnts * (size_t)g.first;
     int64_t blocks = 0, sfts = 0;
     int max_top_k = 0;
     uint4* gcand = any_top ? (uint4*)p->bcand + (size_t)g.first * p->cand_cap : nullptr;
@@ -807,17 +865,24 @@ int batch_interp(fstat_plan* p, const fstat_wu* wus, int n, const fstat_out* out
       blocks += fstat::coef_blocks(v);
       sfts += wus[k].n_sft;
     }
-    int m8 = 0, m4 = 0;
-    int64_t tiles8 = 0, tiles4 = 0;
-    bool fast8 = true, fast4 = true;      // every entry of the table holds its windows in the slice
-    for (int nfd : {8, 4}) {
+    constexpr int NS = fstat::kBatchSizes;
+    int mc[NS] = {}, off[NS] = {};
+    int64_t tiles[NS] = {};
+    bool fast[NS];                         // every entry of a table holds its windows in the slice
+    std::vector<FdSplit> splits(m);
+    for (int q = 0; q < m; ++q) splits[q] = split_spindowns(wus[order[q]].n_fd, sizes);
+    int ne = m;
+    for (int i = 0; i < NS; ++i) {
+      const int nfd = 8 - i;
+      off[i] = ne;
+      fast[i] = true;
       for (int q = 0; q < m; ++q) {
         const int k = order[q];
-        const int64_t nf = wus[k].n_fd, rem = nf % 8;
-        const int64_t split = bt.nf_reg == 4 ? 0 : (rem > 4 ? nf : nf - rem);
-        const int64_t lo = nfd == 8 ? 0 : split, hi = nfd == 8 ? split : nf;
+        int64_t lo = 0;
+        for (int j = 0; j < i; ++j) lo += splits[q].n[j];
+        const int64_t hi = lo + splits[q].n[i];
         if (hi <= lo) continue;
-        fstat::BatchEntry& e = eh[m + m8 + m4];
+        fstat::BatchEntry& e = eh[ne++];
         e = eh[q];
         e.nfd = nfd;
         e.fd_begin = (int32_t)lo;
@@ -830,17 +895,15 @@ int batch_interp(fstat_plan* p, const fstat_wu* wus, int n, const fstat_out* out
           fits = true;
         }
         e.fast = fits ? 1 : 0;
-        (nfd == 8 ? fast8 : fast4) &= fits;
+        fast[i] = fast[i] && fits;
         e.n_tiles = fstat::interp_tiles(e.w, nfd, lo, hi);
-        int64_t& tiles = nfd == 8 ? tiles8 : tiles4;
-        e.tile_begin = tiles;
-        tiles += e.n_tiles;
-        if (nfd == 8) ++m8; else ++m4;
+        e.tile_begin = tiles[i];
+        tiles[i] += e.n_tiles;
+        ++mc[i];
       }
     }
-    fstat::BatchEntry* ed = p->ents_d + 3 * (size_t)g.first;
-    hipError_t e = hipMemcpyAsync(ed, eh, (size_t)(m + m8 + m4) * sizeof(fstat::BatchEntry), hipMemcpyHostToDevice,
-                                  st);
+    fstat::BatchEntry* ed = p->ents_d + kEnts * (size_t)g.first;
+    hipError_t e = hipMemcpyAsync(ed, eh, (size_t)ne * sizeof(fstat::BatchEntry), hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return hip_err(p, e, "work-unit table upload");
     if (first) {
       (void)hipEventRecord(p->ev0, st);
@@ -851,25 +914,26 @@ int batch_interp(fstat_plan* p, const fstat_wu* wus, int n, const fstat_out* out
     // more than b blocks' SFTs, a prefix of each table (most SFTs first),
     // whose tiles are the first tile_begin of the first entry left out.
     const int64_t n_blocks = (wus[order[0]].n_sft + B - 1) / B;
-    std::vector<int64_t> bplan;             // per block: entries and tiles of the 8- and the 4-table
+    std::vector<int64_t> bplan;             // per block and table: entries and tiles
     for (int64_t b = 0; b < n_blocks; ++b) {
-      int n8 = 0, n4 = 0;
-      while (n8 < m8 && eh[m + n8].w.n_sft > b * B) ++n8;
-      while (n4 < m4 && eh[m + m8 + n4].w.n_sft > b * B) ++n4;
-      bplan.insert(bplan.end(), {n8, n8 < m8 ? eh[m + n8].tile_begin : tiles8, n4,
-                                 n4 < m4 ? eh[m + m8 + n4].tile_begin : tiles4});
+      for (int i = 0; i < NS; ++i) {
+        int c = 0;
+        while (c < mc[i] && eh[off[i] + c].w.n_sft > b * B) ++c;
+        bplan.insert(bplan.end(), {c, c < mc[i] ? eh[off[i] + c].tile_begin : tiles[i]});
+      }
     }
     auto launch_demod_blocks = [&](hipStream_t s, bool counted) -> int {
       for (int64_t b = 0; b < n_blocks; ++b) {
-        const int64_t* q = &bplan[4 * b];
-        hipError_t e8 = fstat::launch_interp_batch(ed + m, (int)q[0], q[1], p->counter, bt.chunk,
-                                                   p->batch_grid[fast8 ? 0 : 1], c16, 8, fast8, b * B, (b + 1) * B, s);
-        int r = counted ? check_launch(p, e8, "batch kernel") : (e8 == hipSuccess ? FSTAT_OK : hip_err(p, e8, "graph capture"));
-        if (r) return r;
-        hipError_t e4 = fstat::launch_interp_batch(ed + m + m8, (int)q[2], q[3], p->counter + fstat::kXcds, bt.chunk,
-                                                   p->batch_grid4[fast4 ? 0 : 1], c16, 4, fast4, b * B, (b + 1) * B, s);
-        r = counted ? check_launch(p, e4, "batch kernel") : (e4 == hipSuccess ? FSTAT_OK : hip_err(p, e4, "graph capture"));
-        if (r) return r;
+        for (int i = 0; i < NS; ++i) {
+          const int64_t* q = &bplan[2 * (NS * b + i)];
+          if (q[0] == 0) continue;
+          hipError_t ek = fstat::launch_interp_batch(ed + off[i], (int)q[0], q[1], p->counter + i * fstat::kXcds,
+                                                     bt.chunk, p->batch_grid[i][fast[i] ? 0 : 1], c16, 8 - i, fast[i],
+                                                     b * B, (b + 1) * B, s);
+          const int r = counted ? check_launch(p, ek, "batch kernel")
+                                : (ek == hipSuccess ? FSTAT_OK : hip_err(p, ek, "graph capture"));
+          if (r) return r;
+        }
       }
       return FSTAT_OK;
     };
@@ -893,8 +957,8 @@ int batch_interp(fstat_plan* p, const fstat_wu* wus, int n, const fstat_out* out
     }
     // everything a captured graph holds by value: addresses, counts, kernel variants
     std::vector<int64_t> sig = {(int64_t)(intptr_t)ed, (int64_t)(intptr_t)gcand, (int64_t)(intptr_t)gcount,
-                                m, m8, m4, blocks, tiles8, tiles4, fast8, fast4, sfts, max_top_k, n_blocks,
-                                B, bt.chunk};
+                                m, blocks, sfts, max_top_k, n_blocks, B, bt.chunk};
+    for (int i = 0; i < NS; ++i) sig.insert(sig.end(), {mc[i], off[i], tiles[i], fast[i] ? 1 : 0});
     sig.insert(sig.end(), bplan.begin(), bplan.end());
     auto it = p->graphs.find(sig);
     if (it == p->graphs.end()) {

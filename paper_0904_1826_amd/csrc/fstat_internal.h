@@ -152,6 +152,10 @@ hipError_t launch_coef_batch(const BatchEntry* ents_dev, int n_ent, int64_t tota
 // SFTs [al0, al1) of the first n_ent entries (each clipped to its unit's
 // SFT count; every one of them must have more than al0 SFTs).
 // Tiles are dealt to kXcds queues (counters[0, kXcds)) in chunks of `chunk`.
+// The batched kernel exists for 8 - i spindowns per thread, i < kBatchSizes
+// (with FP16 coefficients for 8 and 4 only); other sizes are refused with
+// hipErrorInvalidValue.
+constexpr int kBatchSizes = 5;
 hipError_t launch_interp_batch(const BatchEntry* ents_dev, int n_ent, int64_t total_tiles,
                                unsigned long long* counters, int64_t chunk, int grid, bool c16, int nfd, bool fast,
                                int64_t al0, int64_t al1, hipStream_t s);

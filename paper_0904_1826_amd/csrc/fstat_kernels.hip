@@ -982,14 +982,15 @@ __global__ __launch_bounds__(NT, MINW) void demod_interp_kernel(WuDev w, int W, 
 // whose queue is drained takes tiles from the next queue, so every tile runs
 // once whatever the placement.  Dterms may differ between work units: the
 // window is folded into the coefficients.
-// One launch serves the work units of one spindown block size (8 or 4 per
-// thread), so that each specialisation keeps the registers, and hence the
-// occupancy, of the single-unit kernel, and SFTs [al0, al1) of each: the
+// One launch serves the work units of one spindown block size (4 to 8 per
+// thread; 8 or 4 with FP16 coefficients), so that each specialisation keeps
+// four waves per SIMD (five for 8 with FP16 coefficients), and SFTs
+// [al0, al1) of each: the
 // host runs the SFT loop as a sequence of such launches (Fa, Fb carried in
 // `acc`), because over thousands of SFTs the work-groups sharing a slice
 // drift apart and L2 no longer holds it for all of them.
 template <int NFD, bool C16, bool SAFE>
-__global__ __launch_bounds__(kThreads, NFD == 8 ? (C16 ? 5 : 4) : 3) void demod_interp_batch_kernel(
+__global__ __launch_bounds__(kThreads, NFD == 8 ? (C16 ? 5 : 4) : (NFD >= 5 ? 4 : 3)) void demod_interp_batch_kernel(
     const BatchEntry* __restrict__ ents, int n_ent, int64_t total_tiles, unsigned long long* counters, int64_t chunk,
     int64_t al0, int64_t al1) {
   using F = SliceForm<kThreads, C16>;
@@ -1234,12 +1235,17 @@ int interp_batch_grid(bool c16, int nfd, bool fast) {
   int dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     cus = 256;
-  if (fast) {
-    if (nfd == 8) return c16 ? batch_grid_t<8, true, false>(cus) : batch_grid_t<8, false, false>(cus);
-    return c16 ? batch_grid_t<4, true, false>(cus) : batch_grid_t<4, false, false>(cus);
+  if (c16) {
+    if (nfd == 8) return fast ? batch_grid_t<8, true, false>(cus) : batch_grid_t<8, true, true>(cus);
+    return fast ? batch_grid_t<4, true, false>(cus) : batch_grid_t<4, true, true>(cus);
   }
-  if (nfd == 8) return c16 ? batch_grid_t<8, true, true>(cus) : batch_grid_t<8, false, true>(cus);
-  return c16 ? batch_grid_t<4, true, true>(cus) : batch_grid_t<4, false, true>(cus);
+  switch (nfd) {
+    case 8: return fast ? batch_grid_t<8, false, false>(cus) : batch_grid_t<8, false, true>(cus);
+    case 7: return fast ? batch_grid_t<7, false, false>(cus) : batch_grid_t<7, false, true>(cus);
+    case 6: return fast ? batch_grid_t<6, false, false>(cus) : batch_grid_t<6, false, true>(cus);
+    case 5: return fast ? batch_grid_t<5, false, false>(cus) : batch_grid_t<5, false, true>(cus);
+    default: return fast ? batch_grid_t<4, false, false>(cus) : batch_grid_t<4, false, true>(cus);
+  }
 }
 
 hipError_t launch_interp_batch(const BatchEntry* ents_dev, int n_ent, int64_t total_tiles,
@@ -1247,6 +1253,7 @@ hipError_t launch_interp_batch(const BatchEntry* ents_dev, int n_ent, int64_t to
                                int64_t al0, int64_t al1, hipStream_t st) {
   if (n_ent <= 0 || total_tiles <= 0) return hipSuccess;
   if (al0 < 0 || al1 <= al0 || chunk < 1) return hipErrorInvalidValue;
+  if (c16 ? (nfd != 8 && nfd != 4) : (nfd < 4 || nfd > 8)) return hipErrorInvalidValue;
   // kernel, not memset: safe under capture
   hipError_t e = launch_fill_int((int*)counters, 0, 2 * kXcds, st);
   if (e != hipSuccess) return e;
@@ -1254,13 +1261,21 @@ hipError_t launch_interp_batch(const BatchEntry* ents_dev, int n_ent, int64_t to
 #define FSTAT_BATCH_LAUNCH(N, C, SF) \
   hipLaunchKernelGGL((demod_interp_batch_kernel<N, C, SF>), g, b, 0, st, ents_dev, n_ent, total_tiles, counters, \
                      chunk, al0, al1)
-  if (nfd == 8) {
-    if (c16) { if (fast) FSTAT_BATCH_LAUNCH(8, true, false); else FSTAT_BATCH_LAUNCH(8, true, true); }
-    else { if (fast) FSTAT_BATCH_LAUNCH(8, false, false); else FSTAT_BATCH_LAUNCH(8, false, true); }
+#define FSTAT_BATCH_LAUNCH2(N, C) \
+  do { if (fast) FSTAT_BATCH_LAUNCH(N, C, false); else FSTAT_BATCH_LAUNCH(N, C, true); } while (0)
+  if (c16) {
+    if (nfd == 8) FSTAT_BATCH_LAUNCH2(8, true);
+    else FSTAT_BATCH_LAUNCH2(4, true);
   } else {
-    if (c16) { if (fast) FSTAT_BATCH_LAUNCH(4, true, false); else FSTAT_BATCH_LAUNCH(4, true, true); }
-    else { if (fast) FSTAT_BATCH_LAUNCH(4, false, false); else FSTAT_BATCH_LAUNCH(4, false, true); }
+    switch (nfd) {
+      case 8: FSTAT_BATCH_LAUNCH2(8, false); break;
+      case 7: FSTAT_BATCH_LAUNCH2(7, false); break;
+      case 6: FSTAT_BATCH_LAUNCH2(6, false); break;
+      case 5: FSTAT_BATCH_LAUNCH2(5, false); break;
+      default: FSTAT_BATCH_LAUNCH2(4, false); break;
+    }
   }
+#undef FSTAT_BATCH_LAUNCH2
 #undef FSTAT_BATCH_LAUNCH
   return hipGetLastError();
 }
