@@ -291,7 +291,10 @@ int fstat_detector_inputs(fstat_plan* p, const fstat_earth* earth, int32_t n_sit
  * first and updated, and only what it lacks is measured.  One line per class:
  * "<class> <nf_reg> <chunk> <sblock> <threads>".  Single-unit classes
  * ("s<storage>_d<Dterms>_k<kernel>_c<coef16>"): spindowns or frequencies per
- * thread, waves per SIMD (interp) or SFTs per LDS chunk (direct), SFTs per
+ * thread (interp 8: the unit's spindowns split into blocks of 8 and fewer as
+ * in fstat_batch_compute, 4 to 8 per thread for the 256-thread tile with four
+ * waves per SIMD and FP32 coefficients, else 8 and 4),
+ * waves per SIMD (interp) or SFTs per LDS chunk (direct), SFTs per
  * launch with 0 = all, work-group size of the interp kernel.  Batch classes
  * ("batch_s<storage>_c<coef16>"): spindowns per thread (8: blocks of 4 to 8
  * split per unit as fstat_batch_compute describes; 4: blocks of 4 only),

@@ -78,7 +78,7 @@ struct fstat_plan {
   hipStream_t cap_stream = nullptr;
   // persistent grids of the batch kernels with 8 - i spindowns per thread,
   // with [i][1] and without [i][0] the global-memory fallback
-  int batch_grid[fstat::kBatchSizes][2] = {};
+  int batch_grid[fstat::kSplitSizes][2] = {};
   std::map<std::vector<int64_t>, hipGraphExec_t> graphs;
   // fault injection (host-side forcing of error paths); force_seg > 0 runs the
   // interp kernels without the global-memory path at that slice width
@@ -463,7 +463,8 @@ int interp_seg(const fstat_plan* p, const fstat_wu* w, int nfd, int threads, boo
 
 Tile default_tile(const fstat_plan* p, const fstat_wu* w) {
   if (resolved_kernel(p) == fstat::KERNEL_INTERP) {
-    // 5 to 7 spindowns: one partial block of 8 costs no more lanes than two of 4
+    // 5 or more spindowns: tiles of 8 per thread, which complete_tile splits
+    // into blocks of 4 to 8 (split_spindowns)
     const int nfd = w->n_fd >= 5 ? 8 : (w->n_fd >= 3 ? 4 : (w->n_fd >= 2 ? 2 : 1));
     // measured on the work-unit-shaped case: 8 spindowns per thread with room
     // for 4 waves per SIMD (5 with FP16 coefficients, whose slices and packed
@@ -479,20 +480,89 @@ Tile default_tile(const fstat_plan* p, const fstat_wu* w) {
   return Tile{4, 4, 0, 0, 0};   // fastest direct tile on the work-unit-shaped case
 }
 
-// Slice widths of a tile for this work unit (the 8-spindown blocks and, for
-// 1 to 4 spindowns left over, the 4-spindown launch) and whether the variant
-// without the global-memory path may run.
+// The spindowns of one unit (single or batched) as blocks of b per thread,
+// b from the allowed sizes (bit b of `sizes`, 4 <= b <= 8): n[8 - b]
+// spindowns run b per thread, as consecutive ranges (8 per thread first),
+// each range's last block possibly partial.  The split minimises the lanes
+// computed weighted by the time per lane of each block size, measured with
+// the batched kernel on the work-unit-shaped case with 840 spindowns (every
+// size divides it; identical outputs): 8: 1, 7: 1.072, 6: 1.136, 5: 1.259,
+// 4: 1.415 (fewer spindowns per thread use each staged slice for fewer
+// pairs).  So 13 spindowns run as 8 + 5 rather than as 8 and a partial 8,
+// 12 as 6 + 6 rather than 8 + 4, and 5 as one block of 5.  All but the last
+// two to three blocks' worth run in blocks of the largest allowed size (the
+// cheapest per lane); the tail is split exactly by dynamic programming.
+struct FdSplit {
+  int64_t n[fstat::kSplitSizes] = {};
+};
+
+FdSplit split_spindowns(int64_t nf, unsigned sizes) {
+  static const double kLaneCost[9] = {0.0, 0.0, 0.0, 0.0, 1.415, 1.259, 1.136, 1.072, 1.0};
+  FdSplit r;
+  int bmax = 0;
+  for (int b = 8; b >= 4 && !bmax; --b) bmax = (sizes >> b) & 1u ? b : 0;
+  if (nf <= 0 || !bmax) return r;
+  const int64_t head = nf > 3 * bmax ? ((nf - 2 * bmax) / bmax) * bmax : 0;
+  const int t = (int)(nf - head);                 // below 3 bmax <= 24
+  double best[25];
+  int pick[25];
+  best[0] = 0.0;
+  pick[0] = 0;
+  for (int x = 1; x <= t; ++x) {
+    best[x] = HUGE_VAL;
+    pick[x] = bmax;
+    for (int b = 8; b >= 4; --b) {                // larger blocks first: ties take fewer tiles
+      if (!((sizes >> b) & 1u)) continue;
+      const double c = best[x > b ? x - b : 0] + b * kLaneCost[b];
+      if (c < best[x]) {
+        best[x] = c;
+        pick[x] = b;
+      }
+    }
+  }
+  r.n[8 - bmax] = head;
+  for (int x = t; x > 0;) {
+    const int b = pick[x], take = x > b ? b : x;
+    r.n[8 - b] += take;
+    x -= take;
+  }
+  return r;
+}
+
+// Block sizes a single-unit tile of 8 spindowns per thread may split a unit's
+// spindowns into: 4 to 8 for the 256-thread FP32-coefficient tile with four
+// waves per SIMD (the sizes with kernels of that shape), else 8 and 4; 0 for
+// other tiles (one range).
+unsigned single_sizes(const fstat_plan* p, const Tile& t) {
+  if (t.nf_reg != 8) return 0u;
+  if (!coef16(p) && t.threads == fstat::kThreads && t.chunk >= 4) return 0x1F0u;
+  return (1u << 8) | (1u << 4);
+}
+
+// Slice widths of a tile for this work unit, its spindown split
+// (split_spindowns, when it is anything but one range of nf_reg per thread)
+// and whether the variant without the global-memory path may run.
 Tile complete_tile(const fstat_plan* p, const fstat_wu* w, Tile t) {
   if (resolved_kernel(p) == fstat::KERNEL_INTERP) {
-    bool fits = false, fits4 = true;
+    bool fits = false;
     t.seg = interp_seg(p, w, t.nf_reg, t.threads, &fits);
-    // 8 spindowns per thread and 1 to 4 left over: those run 4 per thread
-    const int64_t rem = w->n_fd % 8;
-    t.seg4 = (t.nf_reg == 8 && w->n_fd > 8 && rem >= 1 && rem <= 4) ? interp_seg(p, w, 4, t.threads, &fits4) : 0;
-    t.fast = fits && fits4;
+    t.fast = fits;
+    for (int i = 0; i < fstat::kSplitSizes; ++i) t.fd_split[i] = t.seg_split[i] = 0;
+    const unsigned sizes = single_sizes(p, t);
+    const FdSplit sp = split_spindowns(w->n_fd, sizes);
+    if (sizes && sp.n[0] != w->n_fd) {
+      t.fast = 1;
+      for (int i = 0; i < fstat::kSplitSizes; ++i) {
+        if (sp.n[i] <= 0) continue;
+        bool f = false;
+        t.fd_split[i] = (int32_t)sp.n[i];
+        t.seg_split[i] = interp_seg(p, w, 8 - i, t.threads, &f);
+        t.fast = t.fast && f;
+      }
+    }
     if (p->force_seg > 0) {          // fault injection: a slice narrower than the windows need
       t.seg = p->force_seg;
-      t.seg4 = t.seg4 > 0 ? p->force_seg : 0;
+      for (int i = 0; i < fstat::kSplitSizes; ++i) t.seg_split[i] = t.fd_split[i] > 0 ? p->force_seg : 0;
       t.fast = 1;
     }
   }
@@ -688,55 +758,6 @@ Tile batch_tile(const fstat_plan* p) {
   return it != p->tiles.end() ? it->second : default_batch_tile();
 }
 
-// The spindowns of one unit in the batched form as blocks of b per thread,
-// b from the allowed sizes (bit b of `sizes`, 4 <= b <= 8): n[8 - b]
-// spindowns run b per thread, as consecutive ranges (8 per thread first),
-// each range's last block possibly partial.  The split minimises the lanes
-// computed weighted by the time per lane of each block size, measured with
-// the batched kernel on the work-unit-shaped case with 840 spindowns (every
-// size divides it; identical outputs): 8: 1, 7: 1.072, 6: 1.136, 5: 1.259,
-// 4: 1.415 (fewer spindowns per thread use each staged slice for fewer
-// pairs).  So 13 spindowns run as 8 + 5 rather than as 8 and a partial 8,
-// 12 as 6 + 6 rather than 8 + 4, and 5 as one block of 5.  All but the last two to three blocks' worth run
-// in blocks of the largest allowed size (the cheapest per lane); the tail
-// is split exactly by dynamic programming.
-struct FdSplit {
-  int64_t n[fstat::kBatchSizes] = {};
-};
-
-FdSplit split_spindowns(int64_t nf, unsigned sizes) {
-  static const double kLaneCost[9] = {0.0, 0.0, 0.0, 0.0, 1.415, 1.259, 1.136, 1.072, 1.0};
-  FdSplit r;
-  int bmax = 0;
-  for (int b = 8; b >= 4 && !bmax; --b) bmax = (sizes >> b) & 1u ? b : 0;
-  if (nf <= 0 || !bmax) return r;
-  const int64_t head = nf > 3 * bmax ? ((nf - 2 * bmax) / bmax) * bmax : 0;
-  const int t = (int)(nf - head);                 // below 3 bmax <= 24
-  double best[25];
-  int pick[25];
-  best[0] = 0.0;
-  pick[0] = 0;
-  for (int x = 1; x <= t; ++x) {
-    best[x] = HUGE_VAL;
-    pick[x] = bmax;
-    for (int b = 8; b >= 4; --b) {                // larger blocks first: ties take fewer tiles
-      if (!((sizes >> b) & 1u)) continue;
-      const double c = best[x > b ? x - b : 0] + b * kLaneCost[b];
-      if (c < best[x]) {
-        best[x] = c;
-        pick[x] = b;
-      }
-    }
-  }
-  r.n[8 - bmax] = head;
-  for (int x = t; x > 0;) {
-    const int b = pick[x], take = x > b ? b : x;
-    r.n[8 - b] += take;
-    x -= take;
-  }
-  return r;
-}
-
 // Block sizes the batched form may use with this plan and launch shape.
 unsigned batch_sizes(const fstat_plan* p, const Tile& bt) {
   if (bt.nf_reg == 4) return 1u << 4;
@@ -777,7 +798,7 @@ int batch_interp(fstat_plan* p, const fstat_wu* wus, int n, const fstat_out* out
   if (rc) return rc;
   // per group: one entry per unit and up to one demodulation entry per unit
   // and block size
-  constexpr int kEnts = 1 + fstat::kBatchSizes;
+  constexpr int kEnts = 1 + fstat::kSplitSizes;
   rc = ensure_pinned_pair(p, &p->ents_d, &p->ents_h, &p->ents_cap, kEnts * (size_t)n, "work-unit table");
   if (rc) return rc;
   for (int k = 0; k < n; ++k) {
@@ -786,7 +807,7 @@ int batch_interp(fstat_plan* p, const fstat_wu* wus, int n, const fstat_out* out
   }
   if (!p->counter) {               // the per-XCD tile queues of the launch of each block size
     size_t have = 0;
-    rc = dev_alloc(p, (void**)&p->counter, &have, fstat::kBatchSizes * fstat::kXcds * sizeof(unsigned long long),
+    rc = dev_alloc(p, (void**)&p->counter, &have, fstat::kSplitSizes * fstat::kXcds * sizeof(unsigned long long),
                    "tile counters");
     if (rc) return rc;
   }
@@ -807,7 +828,7 @@ int batch_interp(fstat_plan* p, const fstat_wu* wus, int n, const fstat_out* out
     if (rc) return rc;
   }
   const unsigned sizes = batch_sizes(p, bt);
-  for (int i = 0; i < fstat::kBatchSizes; ++i) {
+  for (int i = 0; i < fstat::kSplitSizes; ++i) {
     if (!((sizes >> (8 - i)) & 1u) || p->batch_grid[i][0]) continue;
     for (int sf = 0; sf < 2; ++sf) p->batch_grid[i][sf] = fstat::interp_batch_grid(coef16(p), 8 - i, sf == 0);
   }
@@ -865,7 +886,7 @@ int batch_interp(fstat_plan* p, const fstat_wu* wus, int n, const fstat_out* out
       blocks += fstat::coef_blocks(v);
       sfts += wus[k].n_sft;
     }
-    constexpr int NS = fstat::kBatchSizes;
+    constexpr int NS = fstat::kSplitSizes;
     int mc[NS] = {}, off[NS] = {};
     int64_t tiles[NS] = {};
     bool fast[NS];                         // every entry of a table holds its windows in the slice

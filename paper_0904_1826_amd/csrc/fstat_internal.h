@@ -49,6 +49,10 @@ struct WuDev {
   int32_t phase_mode;      // 0: frac(phi) in FP64; 1: in double-FP32 (split) products
 };
 
+// Spindown-block sizes of split interp launches: 8 - i spindowns per thread
+// for i < kSplitSizes.
+constexpr int kSplitSizes = 5;
+
 // Tile shape of the demodulation kernels.
 struct Tile {
   int32_t nf_reg;   // direct: frequency templates per thread (1, 2 or 4); interp: spindowns per thread
@@ -56,10 +60,14 @@ struct Tile {
   int32_t seg;      // interp: LDS segment width in bins (0: derived)
   int32_t sblock;   // interp: SFTs per launch (the SFT loop is split into launches of this many SFTs)
   int32_t threads;  // interp: work-group size, 64 or 256
-  int32_t seg4;     // interp with nf_reg 8: if > 0, spindowns past the last multiple of 8 (1 to 4 of them) run
-                    // in a second launch with 4 per thread and this slice width
-  int32_t fast;     // interp: 1 if the slice holds every window of every SFT (seg and seg4 were not capped), so
+  int32_t fast;     // interp: 1 if the slice holds every window of every SFT (no slice width was capped), so
                     // the kernel without the global-memory fallback may run
+  // interp with nf_reg 8, filled by the host for the work unit: the
+  // spindowns run as consecutive ranges of fd_split[i] spindowns, 8 - i per
+  // thread, slice width seg_split[i], 8 per thread first; all zero: one
+  // range of nf_reg per thread with slice width seg
+  int32_t fd_split[kSplitSizes];
+  int32_t seg_split[kSplitSizes];
 };
 
 enum Kernel : int32_t { KERNEL_DIRECT = 1, KERNEL_INTERP = 2 };
@@ -85,10 +93,11 @@ __host__ __device__ constexpr int seg_cap16(int nt) { return 3 * nt / 2; }
 constexpr int kSegMax16 = seg_cap16(256);
 
 // One entry of a batched launch: a work unit's device view and, for the
-// demodulation tables, its slice width, its spindowns per thread (4 or 8),
+// demodulation tables, its slice width, its spindowns per thread (4 to 8),
 // the spindown range its tiles cover and the index of its first tile in the
-// concatenated tile list.  A work unit may have an entry in both the 8- and
-// the 4-spindown table (e.g. 12 spindowns: [0, 8) and [8, 12)).
+// concatenated tile list.  A work unit has an entry in the table of each
+// block size its spindowns are split into (e.g. 13 spindowns: [0, 8) at 8
+// per thread and [8, 13) at 5).
 struct BatchEntry {
   WuDev w;
   int32_t seg;
@@ -152,10 +161,9 @@ hipError_t launch_coef_batch(const BatchEntry* ents_dev, int n_ent, int64_t tota
 // SFTs [al0, al1) of the first n_ent entries (each clipped to its unit's
 // SFT count; every one of them must have more than al0 SFTs).
 // Tiles are dealt to kXcds queues (counters[0, kXcds)) in chunks of `chunk`.
-// The batched kernel exists for 8 - i spindowns per thread, i < kBatchSizes
+// The batched kernel exists for 8 - i spindowns per thread, i < kSplitSizes
 // (with FP16 coefficients for 8 and 4 only); other sizes are refused with
 // hipErrorInvalidValue.
-constexpr int kBatchSizes = 5;
 hipError_t launch_interp_batch(const BatchEntry* ents_dev, int n_ent, int64_t total_tiles,
                                unsigned long long* counters, int64_t chunk, int grid, bool c16, int nfd, bool fast,
                                int64_t al0, int64_t al1, hipStream_t s);

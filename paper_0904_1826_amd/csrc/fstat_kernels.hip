@@ -1350,6 +1350,13 @@ static hipError_t launch_interp_range(const WuDev& w, const Tile& t, hipStream_t
                                           : launch_interp_t<8, 8, 4, 4, kThreads, false>(w, t, st, fd0, fd1))
                    : w3         ? launch_interp_t<8, 16, 3, 4, kThreads, false>(w, t, st, fd0, fd1)
                                 : launch_interp_t<8, 16, 2, 4, kThreads, false>(w, t, st, fd0, fd1);
+    // 7 to 5: ranges of a split 8-spindown tile (four waves per SIMD)
+    case 7: return t.fast ? launch_interp_t<7, 8, 4, 4, kThreads, false, false>(w, t, st, fd0, fd1)
+                          : launch_interp_t<7, 8, 4, 4, kThreads, false>(w, t, st, fd0, fd1);
+    case 6: return t.fast ? launch_interp_t<6, 8, 4, 4, kThreads, false, false>(w, t, st, fd0, fd1)
+                          : launch_interp_t<6, 8, 4, 4, kThreads, false>(w, t, st, fd0, fd1);
+    case 5: return t.fast ? launch_interp_t<5, 8, 4, 4, kThreads, false, false>(w, t, st, fd0, fd1)
+                          : launch_interp_t<5, 8, 4, 4, kThreads, false>(w, t, st, fd0, fd1);
     case 4: return w3 ? (t.fast ? launch_interp_t<4, 16, 3, 4, kThreads, false, false>(w, t, st, fd0, fd1)
                                 : launch_interp_t<4, 16, 3, 4, kThreads, false>(w, t, st, fd0, fd1))
                       : launch_interp_t<4, 16, 2, 4, kThreads, false>(w, t, st, fd0, fd1);
@@ -1359,20 +1366,27 @@ static hipError_t launch_interp_range(const WuDev& w, const Tile& t, hipStream_t
   }
 }
 
-// The spindowns in blocks of nf_reg; with seg4 > 0 (nf_reg 8) the 1 to 4
-// spindowns past the last multiple of 8 run in a second launch with 4 per
-// thread instead of a partial block of 8.
+// The spindowns in blocks of nf_reg, or, with a split (Tile::fd_split), as
+// consecutive ranges with 8, 7, ..., 4 per thread, one launch sequence per
+// range (t.fast covers every range's slice).
 static hipError_t launch_interp(const WuDev& w, const Tile& t, hipStream_t st) {
-  const int64_t rem = w.n_fd % 8;
-  if (t.nf_reg != 8 || t.seg4 <= 0 || rem == 0 || rem > 4 || w.n_fd < 8) return launch_interp_range(w, t, st, 0, w.n_fd);
-  const int64_t split = w.n_fd - rem;
-  hipError_t e = launch_interp_range(w, t, st, 0, split);
-  if (e != hipSuccess) return e;
-  Tile t4 = t;
-  t4.nf_reg = 4;
-  t4.seg = t.seg4;          // t.fast covers both slices
-  t4.chunk = t.chunk > 3 ? 3 : t.chunk;
-  return launch_interp_range(w, t4, st, split, w.n_fd);
+  int64_t total = 0;
+  for (int i = 0; i < kSplitSizes; ++i) total += t.fd_split[i] > 0 ? t.fd_split[i] : 0;
+  if (total == 0) return launch_interp_range(w, t, st, 0, w.n_fd);
+  if (total != w.n_fd) return hipErrorInvalidValue;
+  int64_t lo = 0;
+  for (int i = 0; i < kSplitSizes; ++i) {
+    if (t.fd_split[i] <= 0) continue;
+    Tile ti = t;
+    ti.nf_reg = 8 - i;
+    ti.seg = t.seg_split[i];
+    if (ti.nf_reg == 4) ti.chunk = t.chunk > 3 ? 3 : t.chunk;
+    else if (ti.nf_reg < 8) ti.chunk = 4;
+    const hipError_t e = launch_interp_range(w, ti, st, lo, lo + t.fd_split[i]);
+    if (e != hipSuccess) return e;
+    lo += t.fd_split[i];
+  }
+  return hipSuccess;
 }
 
 template <class Seg>
