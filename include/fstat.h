@@ -223,10 +223,11 @@ int fstat_compute_noalloc(fstat_plan* p, const fstat_wu* wu, const fstat_out* ou
 /* 2F of many work units with uneven SFT counts, bands and template grids in
  * persistent launches shared by all of them (the "several clients per
  * system" idea of the Cell port, Section 5, done on one device).  Each
- * unit's spindowns are split into ranges run 8, 7, 6, 5 or 4 per thread (8 or
- * 4 with FP16 coefficients), chosen per unit to waste the fewest lanes
- * weighted by the measured cost of each size (13 spindowns run as 8 + 5, not
- * as 8 and a partial 8).  Per block of SFTs (256 unless fstat_autotune chose
+ * unit's spindowns are split into ranges run 16 (where its slice holds every
+ * window), 8, 7, 6, 5 or 4 per thread (8 or 4 with FP16 coefficients), chosen
+ * per unit to waste the fewest lanes weighted by the measured cost of each
+ * size (5 spindowns run as one block of 5, 12 as 6 + 6, 32 as 16 + 16).  Per
+ * block of SFTs (256 unless fstat_autotune chose
  * another) one persistent launch per spindown-block size runs over the units
  * with SFTs left; inside a launch the tiles are dealt to one queue per XCD in
  * chunks of consecutive tiles, so that tiles sharing coefficients are served
@@ -291,13 +292,13 @@ int fstat_detector_inputs(fstat_plan* p, const fstat_earth* earth, int32_t n_sit
  * first and updated, and only what it lacks is measured.  One line per class:
  * "<class> <nf_reg> <chunk> <sblock> <threads>".  Single-unit classes
  * ("s<storage>_d<Dterms>_k<kernel>_c<coef16>"): spindowns or frequencies per
- * thread (interp 8: the unit's spindowns split into blocks of 8 and fewer as
- * in fstat_batch_compute, 4 to 8 per thread for the 256-thread tile with four
- * waves per SIMD and FP32 coefficients, else 8 and 4),
+ * thread (interp 8: the unit's spindowns split into blocks as in
+ * fstat_batch_compute, 16 and 4 to 8 per thread for the 256-thread tile with
+ * four waves per SIMD and FP32 coefficients, else 8 and 4),
  * waves per SIMD (interp) or SFTs per LDS chunk (direct), SFTs per
  * launch with 0 = all, work-group size of the interp kernel.  Batch classes
- * ("batch_s<storage>_c<coef16>"): spindowns per thread (8: blocks of 4 to 8
- * split per unit as fstat_batch_compute describes; 4: blocks of 4 only),
+ * ("batch_s<storage>_c<coef16>"): spindowns per thread (8: blocks of 16 and
+ * 4 to 8 split per unit as fstat_batch_compute describes; 4: blocks of 4 only),
  * tiles per chunk of the per-XCD queues, SFTs per launch (0 = all), 256.
  * Lines naming a shape the library does not implement are ignored. */
 int fstat_autotune(fstat_plan* p, const fstat_wu* wu, const fstat_out* out, void* stream,

@@ -76,7 +76,7 @@ struct fstat_plan {
   size_t ents_cap = 0;
   unsigned long long* counter = nullptr;
   hipStream_t cap_stream = nullptr;
-  // persistent grids of the batch kernels with 8 - i spindowns per thread,
+  // persistent grids of the batch kernels with split_nfd(i) spindowns per thread,
   // with [i][1] and without [i][0] the global-memory fallback
   int batch_grid[fstat::kSplitSizes][2] = {};
   std::map<std::vector<int64_t>, hipGraphExec_t> graphs;
@@ -481,37 +481,50 @@ Tile default_tile(const fstat_plan* p, const fstat_wu* w) {
 }
 
 // The spindowns of one unit (single or batched) as blocks of b per thread,
-// b from the allowed sizes (bit b of `sizes`, 4 <= b <= 8): n[8 - b]
-// spindowns run b per thread, as consecutive ranges (8 per thread first),
-// each range's last block possibly partial.  The split minimises the lanes
-// computed weighted by the time per lane of each block size, measured with
-// the batched kernel on the work-unit-shaped case with 840 spindowns (every
-// size divides it; identical outputs): 8: 1, 7: 1.072, 6: 1.136, 5: 1.259,
-// 4: 1.415 (fewer spindowns per thread use each staged slice for fewer
-// pairs).  So 13 spindowns run as 8 + 5 rather than as 8 and a partial 8,
-// 12 as 6 + 6 rather than 8 + 4, and 5 as one block of 5.  All but the last
-// two to three blocks' worth run in blocks of the largest allowed size (the
-// cheapest per lane); the tail is split exactly by dynamic programming.
+// b from the allowed sizes (bit b of `sizes`, b = 16 or 4 <= b <= 8): n[i]
+// spindowns run split_nfd(i) per thread, as consecutive ranges (largest
+// blocks first), each range's last block possibly partial.  The split
+// minimises the lanes computed weighted by the time per lane of each block
+// size, measured with the batched kernel on the work-unit-shaped case with
+// 840 (832 for 16) spindowns, every size dividing it, identical outputs: 16:
+// 0.890, 8: 1, 7: 1.072, 6: 1.136, 5: 1.259, 4: 1.415 (more spindowns per
+// thread use each staged slice and each thread's per-SFT work for more
+// pairs).  So 5 spindowns run as one block of 5 rather than a partial 8,
+// 12 as 6 + 6 rather than 8 + 4, 32 as 16 + 16 and 13 as one partial block
+// of 16 (8 + 5 without 16).
+// All but the last two to three blocks' worth run in blocks of the largest
+// allowed size (the cheapest per lane); the tail is split exactly by
+// dynamic programming.
 struct FdSplit {
   int64_t n[fstat::kSplitSizes] = {};
 };
 
+int split_index(int b) { return b == 16 ? 0 : 9 - b; }
+
 FdSplit split_spindowns(int64_t nf, unsigned sizes) {
-  static const double kLaneCost[9] = {0.0, 0.0, 0.0, 0.0, 1.415, 1.259, 1.136, 1.072, 1.0};
+  static const double kLaneCost[17] = {0.0, 0.0, 0.0, 0.0, 1.415, 1.259, 1.136, 1.072, 1.0,
+                                       0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.890};
+  static const int kSizes[] = {16, 8, 7, 6, 5, 4};   // larger blocks first: ties take fewer tiles
+  constexpr int kTail = 48;
   FdSplit r;
   int bmax = 0;
-  for (int b = 8; b >= 4 && !bmax; --b) bmax = (sizes >> b) & 1u ? b : 0;
+  for (int b : kSizes) {
+    if ((sizes >> b) & 1u) {
+      bmax = b;
+      break;
+    }
+  }
   if (nf <= 0 || !bmax) return r;
   const int64_t head = nf > 3 * bmax ? ((nf - 2 * bmax) / bmax) * bmax : 0;
-  const int t = (int)(nf - head);                 // below 3 bmax <= 24
-  double best[25];
-  int pick[25];
+  const int t = (int)(nf - head);                 // at most 3 bmax <= kTail
+  double best[kTail + 1];
+  int pick[kTail + 1];
   best[0] = 0.0;
   pick[0] = 0;
   for (int x = 1; x <= t; ++x) {
     best[x] = HUGE_VAL;
     pick[x] = bmax;
-    for (int b = 8; b >= 4; --b) {                // larger blocks first: ties take fewer tiles
+    for (int b : kSizes) {
       if (!((sizes >> b) & 1u)) continue;
       const double c = best[x > b ? x - b : 0] + b * kLaneCost[b];
       if (c < best[x]) {
@@ -520,22 +533,26 @@ FdSplit split_spindowns(int64_t nf, unsigned sizes) {
       }
     }
   }
-  r.n[8 - bmax] = head;
+  r.n[split_index(bmax)] = head;
   for (int x = t; x > 0;) {
     const int b = pick[x], take = x > b ? b : x;
-    r.n[8 - b] += take;
+    r.n[split_index(b)] += take;
     x -= take;
   }
   return r;
 }
 
+// Block sizes (bit b: b spindowns per thread) with kernels for every
+// block size of the split: 16 and 4 to 8.
+constexpr unsigned kAllSplitSizes = (1u << 16) | 0x1F0u;
+
 // Block sizes a single-unit tile of 8 spindowns per thread may split a unit's
-// spindowns into: 4 to 8 for the 256-thread FP32-coefficient tile with four
-// waves per SIMD (the sizes with kernels of that shape), else 8 and 4; 0 for
-// other tiles (one range).
+// spindowns into: 16 and 4 to 8 for the 256-thread FP32-coefficient tile
+// with four waves per SIMD (the sizes with kernels of that shape), else 8
+// and 4; 0 for other tiles (one range).
 unsigned single_sizes(const fstat_plan* p, const Tile& t) {
   if (t.nf_reg != 8) return 0u;
-  if (!coef16(p) && t.threads == fstat::kThreads && t.chunk >= 4) return 0x1F0u;
+  if (!coef16(p) && t.threads == fstat::kThreads && t.chunk >= 4) return kAllSplitSizes;
   return (1u << 8) | (1u << 4);
 }
 
@@ -548,15 +565,20 @@ Tile complete_tile(const fstat_plan* p, const fstat_wu* w, Tile t) {
     t.seg = interp_seg(p, w, t.nf_reg, t.threads, &fits);
     t.fast = fits;
     for (int i = 0; i < fstat::kSplitSizes; ++i) t.fd_split[i] = t.seg_split[i] = 0;
-    const unsigned sizes = single_sizes(p, t);
+    unsigned sizes = single_sizes(p, t);
+    if ((sizes >> 16) & 1u) {         // 16 per thread only where its wider slice holds every window
+      bool f16 = false;
+      (void)interp_seg(p, w, 16, t.threads, &f16);
+      if (!f16) sizes &= ~(1u << 16);
+    }
     const FdSplit sp = split_spindowns(w->n_fd, sizes);
-    if (sizes && sp.n[0] != w->n_fd) {
+    if (sizes && sp.n[split_index(8)] != w->n_fd) {
       t.fast = 1;
       for (int i = 0; i < fstat::kSplitSizes; ++i) {
         if (sp.n[i] <= 0) continue;
         bool f = false;
         t.fd_split[i] = (int32_t)sp.n[i];
-        t.seg_split[i] = interp_seg(p, w, 8 - i, t.threads, &f);
+        t.seg_split[i] = interp_seg(p, w, fstat::split_nfd(i), t.threads, &f);
         t.fast = t.fast && f;
       }
     }
@@ -761,7 +783,7 @@ Tile batch_tile(const fstat_plan* p) {
 // Block sizes the batched form may use with this plan and launch shape.
 unsigned batch_sizes(const fstat_plan* p, const Tile& bt) {
   if (bt.nf_reg == 4) return 1u << 4;
-  return coef16(p) ? (1u << 8) | (1u << 4) : 0x1F0u;      // {8, 4} or 4..8
+  return coef16(p) ? (1u << 8) | (1u << 4) : kAllSplitSizes;      // {8, 4} or 16, 4..8
 }
 
 // Batched interp path: work units are grouped so that one group's scratch
@@ -829,8 +851,9 @@ int batch_interp(fstat_plan* p, const fstat_wu* wus, int n, const fstat_out* out
   }
   const unsigned sizes = batch_sizes(p, bt);
   for (int i = 0; i < fstat::kSplitSizes; ++i) {
-    if (!((sizes >> (8 - i)) & 1u) || p->batch_grid[i][0]) continue;
-    for (int sf = 0; sf < 2; ++sf) p->batch_grid[i][sf] = fstat::interp_batch_grid(coef16(p), 8 - i, sf == 0);
+    const int nfd = fstat::split_nfd(i);
+    if (!((sizes >> nfd) & 1u) || p->batch_grid[i][0]) continue;
+    for (int sf = 0; sf < 2; ++sf) p->batch_grid[i][sf] = fstat::interp_batch_grid(coef16(p), nfd, sf == 0);
   }
   // every work unit is checked before anything is demodulated
   if (groups.size() > 1) {
@@ -891,10 +914,20 @@ int batch_interp(fstat_plan* p, const fstat_wu* wus, int n, const fstat_out* out
     int64_t tiles[NS] = {};
     bool fast[NS];                         // every entry of a table holds its windows in the slice
     std::vector<FdSplit> splits(m);
-    for (int q = 0; q < m; ++q) splits[q] = split_spindowns(wus[order[q]].n_fd, sizes);
+    for (int q = 0; q < m; ++q) {
+      const int k = order[q];
+      unsigned sz = sizes;
+      if ((sz >> 16) & 1u) {          // 16 per thread only where its wider slice holds every window
+        bool f16 = false;
+        (void)interp_seg_tau(&wus[k], 16, fstat::kThreads, coef16(p), status_tau(p->bstat_h[k]),
+                             status_p(p->bstat_h[k]), &f16);
+        if (!f16) sz &= ~(1u << 16);
+      }
+      splits[q] = split_spindowns(wus[k].n_fd, sz);
+    }
     int ne = m;
     for (int i = 0; i < NS; ++i) {
-      const int nfd = 8 - i;
+      const int nfd = fstat::split_nfd(i);
       off[i] = ne;
       fast[i] = true;
       for (int q = 0; q < m; ++q) {
@@ -949,7 +982,8 @@ int batch_interp(fstat_plan* p, const fstat_wu* wus, int n, const fstat_out* out
           const int64_t* q = &bplan[2 * (NS * b + i)];
           if (q[0] == 0) continue;
           hipError_t ek = fstat::launch_interp_batch(ed + off[i], (int)q[0], q[1], p->counter + i * fstat::kXcds,
-                                                     bt.chunk, p->batch_grid[i][fast[i] ? 0 : 1], c16, 8 - i, fast[i],
+                                                     bt.chunk, p->batch_grid[i][fast[i] ? 0 : 1], c16,
+                                                     fstat::split_nfd(i), fast[i],
                                                      b * B, (b + 1) * B, s);
           const int r = counted ? check_launch(p, ek, "batch kernel")
                                 : (ek == hipSuccess ? FSTAT_OK : hip_err(p, ek, "graph capture"));

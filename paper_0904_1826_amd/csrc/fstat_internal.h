@@ -49,9 +49,10 @@ struct WuDev {
   int32_t phase_mode;      // 0: frac(phi) in FP64; 1: in double-FP32 (split) products
 };
 
-// Spindown-block sizes of split interp launches: 8 - i spindowns per thread
-// for i < kSplitSizes.
-constexpr int kSplitSizes = 5;
+// Spindown-block sizes of split interp launches, largest first: index i runs
+// split_nfd(i) = 16, 8, 7, 6, 5, 4 spindowns per thread.
+constexpr int kSplitSizes = 6;
+__host__ __device__ constexpr int split_nfd(int i) { return i == 0 ? 16 : 9 - i; }
 
 // Tile shape of the demodulation kernels.
 struct Tile {
@@ -63,9 +64,9 @@ struct Tile {
   int32_t fast;     // interp: 1 if the slice holds every window of every SFT (no slice width was capped), so
                     // the kernel without the global-memory fallback may run
   // interp with nf_reg 8, filled by the host for the work unit: the
-  // spindowns run as consecutive ranges of fd_split[i] spindowns, 8 - i per
-  // thread, slice width seg_split[i], 8 per thread first; all zero: one
-  // range of nf_reg per thread with slice width seg
+  // spindowns run as consecutive ranges of fd_split[i] spindowns,
+  // split_nfd(i) per thread, slice width seg_split[i], largest blocks first;
+  // all zero: one range of nf_reg per thread with slice width seg
   int32_t fd_split[kSplitSizes];
   int32_t seg_split[kSplitSizes];
 };
@@ -93,7 +94,7 @@ __host__ __device__ constexpr int seg_cap16(int nt) { return 3 * nt / 2; }
 constexpr int kSegMax16 = seg_cap16(256);
 
 // One entry of a batched launch: a work unit's device view and, for the
-// demodulation tables, its slice width, its spindowns per thread (4 to 8),
+// demodulation tables, its slice width, its spindowns per thread (4 to 8 or 16),
 // the spindown range its tiles cover and the index of its first tile in the
 // concatenated tile list.  A work unit has an entry in the table of each
 // block size its spindowns are split into (e.g. 13 spindowns: [0, 8) at 8
@@ -161,9 +162,9 @@ hipError_t launch_coef_batch(const BatchEntry* ents_dev, int n_ent, int64_t tota
 // SFTs [al0, al1) of the first n_ent entries (each clipped to its unit's
 // SFT count; every one of them must have more than al0 SFTs).
 // Tiles are dealt to kXcds queues (counters[0, kXcds)) in chunks of `chunk`.
-// The batched kernel exists for 8 - i spindowns per thread, i < kSplitSizes
-// (with FP16 coefficients for 8 and 4 only); other sizes are refused with
-// hipErrorInvalidValue.
+// The batched kernel exists for split_nfd(i) spindowns per thread, i <
+// kSplitSizes (with FP16 coefficients for 8 and 4 only); other sizes are
+// refused with hipErrorInvalidValue.
 hipError_t launch_interp_batch(const BatchEntry* ents_dev, int n_ent, int64_t total_tiles,
                                unsigned long long* counters, int64_t chunk, int grid, bool c16, int nfd, bool fast,
                                int64_t al0, int64_t al1, hipStream_t s);

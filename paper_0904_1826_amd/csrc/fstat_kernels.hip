@@ -982,15 +982,16 @@ __global__ __launch_bounds__(NT, MINW) void demod_interp_kernel(WuDev w, int W, 
 // whose queue is drained takes tiles from the next queue, so every tile runs
 // once whatever the placement.  Dterms may differ between work units: the
 // window is folded into the coefficients.
-// One launch serves the work units of one spindown block size (4 to 8 per
-// thread; 8 or 4 with FP16 coefficients), so that each specialisation keeps
-// four waves per SIMD (five for 8 with FP16 coefficients), and SFTs
-// [al0, al1) of each: the
+// One launch serves the work units of one spindown block size (16 or 4 to 8
+// per thread; 8 or 4 with FP16 coefficients; four waves per SIMD, five for 8
+// with FP16 coefficients, three for 16, whose 64 accumulators per thread
+// take the registers of a fourth but which uses each staged slice for twice
+// the pairs), and SFTs [al0, al1) of each: the
 // host runs the SFT loop as a sequence of such launches (Fa, Fb carried in
 // `acc`), because over thousands of SFTs the work-groups sharing a slice
 // drift apart and L2 no longer holds it for all of them.
 template <int NFD, bool C16, bool SAFE>
-__global__ __launch_bounds__(kThreads, NFD == 8 ? (C16 ? 5 : 4) : (NFD >= 5 ? 4 : 3)) void demod_interp_batch_kernel(
+__global__ __launch_bounds__(kThreads, NFD == 16 ? 3 : NFD == 8 ? (C16 ? 5 : 4) : (NFD >= 5 ? 4 : 3)) void demod_interp_batch_kernel(
     const BatchEntry* __restrict__ ents, int n_ent, int64_t total_tiles, unsigned long long* counters, int64_t chunk,
     int64_t al0, int64_t al1) {
   using F = SliceForm<kThreads, C16>;
@@ -1240,6 +1241,7 @@ int interp_batch_grid(bool c16, int nfd, bool fast) {
     return fast ? batch_grid_t<4, true, false>(cus) : batch_grid_t<4, true, true>(cus);
   }
   switch (nfd) {
+    case 16: return fast ? batch_grid_t<16, false, false>(cus) : batch_grid_t<16, false, true>(cus);
     case 8: return fast ? batch_grid_t<8, false, false>(cus) : batch_grid_t<8, false, true>(cus);
     case 7: return fast ? batch_grid_t<7, false, false>(cus) : batch_grid_t<7, false, true>(cus);
     case 6: return fast ? batch_grid_t<6, false, false>(cus) : batch_grid_t<6, false, true>(cus);
@@ -1253,7 +1255,7 @@ hipError_t launch_interp_batch(const BatchEntry* ents_dev, int n_ent, int64_t to
                                int64_t al0, int64_t al1, hipStream_t st) {
   if (n_ent <= 0 || total_tiles <= 0) return hipSuccess;
   if (al0 < 0 || al1 <= al0 || chunk < 1) return hipErrorInvalidValue;
-  if (c16 ? (nfd != 8 && nfd != 4) : (nfd < 4 || nfd > 8)) return hipErrorInvalidValue;
+  if (c16 ? (nfd != 8 && nfd != 4) : ((nfd < 4 || nfd > 8) && nfd != 16)) return hipErrorInvalidValue;
   // kernel, not memset: safe under capture
   hipError_t e = launch_fill_int((int*)counters, 0, 2 * kXcds, st);
   if (e != hipSuccess) return e;
@@ -1268,6 +1270,7 @@ hipError_t launch_interp_batch(const BatchEntry* ents_dev, int n_ent, int64_t to
     else FSTAT_BATCH_LAUNCH2(4, true);
   } else {
     switch (nfd) {
+      case 16: FSTAT_BATCH_LAUNCH2(16, false); break;
       case 8: FSTAT_BATCH_LAUNCH2(8, false); break;
       case 7: FSTAT_BATCH_LAUNCH2(7, false); break;
       case 6: FSTAT_BATCH_LAUNCH2(6, false); break;
@@ -1350,7 +1353,10 @@ static hipError_t launch_interp_range(const WuDev& w, const Tile& t, hipStream_t
                                           : launch_interp_t<8, 8, 4, 4, kThreads, false>(w, t, st, fd0, fd1))
                    : w3         ? launch_interp_t<8, 16, 3, 4, kThreads, false>(w, t, st, fd0, fd1)
                                 : launch_interp_t<8, 16, 2, 4, kThreads, false>(w, t, st, fd0, fd1);
-    // 7 to 5: ranges of a split 8-spindown tile (four waves per SIMD)
+    // 16 and 7 to 5: ranges of a split 8-spindown tile (three waves per SIMD
+    // for 16, four for the others)
+    case 16: return t.fast ? launch_interp_t<16, 8, 3, 4, kThreads, false, false>(w, t, st, fd0, fd1)
+                           : launch_interp_t<16, 8, 3, 4, kThreads, false>(w, t, st, fd0, fd1);
     case 7: return t.fast ? launch_interp_t<7, 8, 4, 4, kThreads, false, false>(w, t, st, fd0, fd1)
                           : launch_interp_t<7, 8, 4, 4, kThreads, false>(w, t, st, fd0, fd1);
     case 6: return t.fast ? launch_interp_t<6, 8, 4, 4, kThreads, false, false>(w, t, st, fd0, fd1)
@@ -1367,8 +1373,8 @@ static hipError_t launch_interp_range(const WuDev& w, const Tile& t, hipStream_t
 }
 
 // The spindowns in blocks of nf_reg, or, with a split (Tile::fd_split), as
-// consecutive ranges with 8, 7, ..., 4 per thread, one launch sequence per
-// range (t.fast covers every range's slice).
+// consecutive ranges with 16, 8, 7, ..., 4 per thread, one launch sequence
+// per range (t.fast covers every range's slice).
 static hipError_t launch_interp(const WuDev& w, const Tile& t, hipStream_t st) {
   int64_t total = 0;
   for (int i = 0; i < kSplitSizes; ++i) total += t.fd_split[i] > 0 ? t.fd_split[i] : 0;
@@ -1378,9 +1384,9 @@ static hipError_t launch_interp(const WuDev& w, const Tile& t, hipStream_t st) {
   for (int i = 0; i < kSplitSizes; ++i) {
     if (t.fd_split[i] <= 0) continue;
     Tile ti = t;
-    ti.nf_reg = 8 - i;
+    ti.nf_reg = split_nfd(i);
     ti.seg = t.seg_split[i];
-    if (ti.nf_reg == 4) ti.chunk = t.chunk > 3 ? 3 : t.chunk;
+    if (ti.nf_reg == 4 || ti.nf_reg == 16) ti.chunk = t.chunk > 3 ? 3 : t.chunk;
     else if (ti.nf_reg < 8) ti.chunk = 4;
     const hipError_t e = launch_interp_range(w, ti, st, lo, lo + t.fd_split[i]);
     if (e != hipSuccess) return e;

@@ -67,11 +67,12 @@ def test_batch_matches_single_and_oracle(torch_cuda, oracle_lib):
 def test_batch_spindown_ranges(torch_cuda, oracle_lib, coef):
     """Spindown counts with every remainder modulo 8 and the splits they take
     in the batched tables (blocks of 4 to 8 per thread with FP32
-    coefficients, e.g. 13 = 8 + 5, 11 = 6 + 5, 12 = 6 + 6; blocks of 8
+    coefficients, and 16 where its slice fits, e.g. 9 = 5 + 4, 12 = 6 + 6,
+    20 = 16 + 4, 33 = 16 + 16 + 1 in a block of 4; blocks of 8
     and 4 with FP16 ones, partial blocks included); every template against
     the oracle and against the single-unit call."""
     torch = torch_cuda
-    n_fds = [1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 20, 21, 23, 30]
+    n_fds = [1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 20, 21, 23, 30, 32, 33, 49, 50]
     ws = [small_workload(300 + k, n_sky=3, n_fd=nfd, n_f=300, slots=12, fdot_lo=-1e-9, injections=())
           for k, nfd in enumerate(n_fds)]
     outs, devs = _batch(torch, ws, coef=coef)
