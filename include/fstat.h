@@ -326,6 +326,19 @@ int32_t fstat_interp_slice(double df, double dfdot, int32_t nfd, int32_t threads
  * the stream it ran on (waits for it).  Returns a negative value if none. */
 double fstat_last_kernel_ms(fstat_plan* p);
 
+/* The demodulation launch shape of the last fstat_compute call (after
+ * fstat_semicoherent: of its last segment; not set by the other calls), for
+ * tuning and tests: out[0..4] = spindowns per thread (interp) or frequencies
+ * per thread (direct), waves per SIMD or SFTs per LDS chunk, slice width,
+ * SFTs per launch (0: all), work-group size; out[5] = slice width of the
+ * tiles of two sky points (0: one sky point per tile); out[6] = number of
+ * sky tiles (sky points, or pairs); out[7..12] = the spindowns run 16, 8, 7,
+ * 6, 5 and 4 per thread (all 0: one range at out[0] per thread).  `out`
+ * holds FSTAT_LAST_TILE_LEN entries.  Returns FSTAT_OK, or FSTAT_E_ARG for
+ * NULL arguments or before any such call. */
+#define FSTAT_LAST_TILE_LEN 13
+int fstat_last_tile(const fstat_plan* p, int32_t* out);
+
 /* Release the plan and everything it allocated (waits for its device work).
  * Safe on NULL and after any error. */
 void fstat_plan_destroy(fstat_plan* p);

@@ -44,7 +44,9 @@ PHASES = {"fp64": FSTAT_PHASE_FP64, "split": FSTAT_PHASE_SPLIT_FP32}
 # Every entry point include/fstat.h declares.
 EXPORTS = ("fstat_plan_create", "fstat_compute", "fstat_batch_compute", "fstat_bins", "fstat_autotune",
            "fstat_last_kernel_ms", "fstat_plan_destroy", "fstat_strerror", "fstat_last_error",
-           "fstat_detector_inputs", "fstat_semicoherent", "fstat_compute_noalloc", "fstat_interp_slice")
+           "fstat_detector_inputs", "fstat_semicoherent", "fstat_compute_noalloc", "fstat_interp_slice",
+           "fstat_last_tile")
+LAST_TILE_LEN = 13                    # FSTAT_LAST_TILE_LEN
 NOALLOC_SCRATCH_BYTES = 128 << 20     # FSTAT_NOALLOC_SCRATCH_BYTES
 
 
@@ -124,6 +126,8 @@ def load_library(path: str = LIB_PATH):
     lib.fstat_autotune.restype = ctypes.c_int
     lib.fstat_last_kernel_ms.argtypes = [P]
     lib.fstat_last_kernel_ms.restype = ctypes.c_double
+    lib.fstat_last_tile.argtypes = [P, ctypes.POINTER(I32)]
+    lib.fstat_last_tile.restype = ctypes.c_int
     lib.fstat_plan_destroy.argtypes = [P]
     lib.fstat_plan_destroy.restype = None
     lib.fstat_strerror.argtypes = [ctypes.c_int]
@@ -447,6 +451,18 @@ def fstat_last_kernel_ms(plan) -> float:
     return float(load_library().fstat_last_kernel_ms(plan))
 
 
+def fstat_last_tile(plan) -> dict:
+    """Launch shape of the plan's last single-unit demodulation (see
+    include/fstat.h): keys nf_reg, chunk, seg, sblock, threads, pair_seg,
+    sky_tiles, and split = {spindowns per thread: spindowns run so}."""
+    buf = (ctypes.c_int32 * LAST_TILE_LEN)()
+    _check(plan, load_library().fstat_last_tile(plan, buf))
+    v = list(buf)
+    split = {b: n for b, n in zip((16, 8, 7, 6, 5, 4), v[7:]) if n}
+    return dict(nf_reg=v[0], chunk=v[1], seg=v[2], sblock=v[3], threads=v[4], pair_seg=v[5], sky_tiles=v[6],
+                split=split)
+
+
 class Plan:
     """Owning wrapper around an fstat_plan handle."""
 
@@ -476,6 +492,9 @@ class Plan:
 
     def last_kernel_ms(self) -> float:
         return fstat_last_kernel_ms(self.handle)
+
+    def last_tile(self) -> dict:
+        return fstat_last_tile(self.handle)
 
     def last_error(self) -> str:
         return fstat_last_error(self.handle)

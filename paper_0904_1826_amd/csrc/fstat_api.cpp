@@ -75,6 +75,17 @@ struct fstat_plan {
   fstat::BatchEntry* ents_h = nullptr;
   size_t ents_cap = 0;
   unsigned long long* counter = nullptr;
+  // launch shape of the last single-unit demodulation (fstat_last_tile)
+  bool have_last = false;
+  Tile last_tile{};
+  int64_t last_sky_tiles = 0;
+  // tiles of two sky points (single-unit interp): the sky vectors on the
+  // host and the pair table
+  double* sky_h = nullptr;              // pinned
+  size_t sky_h_cap = 0;
+  int2* pairs_d = nullptr;
+  int2* pairs_h = nullptr;              // pinned
+  size_t pairs_cap = 0;
   hipStream_t cap_stream = nullptr;
   // persistent grids of the batch kernels with split_nfd(i) spindowns per thread,
   // with [i][1] and without [i][0] the global-memory fallback
@@ -652,6 +663,9 @@ int run_geometry(fstat_plan* p, const WuDev& v, hipStream_t st, int idx) {
 
 int run_demod(fstat_plan* p, const WuDev& v, const Tile& t, hipStream_t st) {
   const int kernel = resolved_kernel(p);
+  p->have_last = true;
+  p->last_tile = t;
+  p->last_sky_tiles = v.n_pairs > 0 && t.pair_seg > 0 ? v.n_pairs : v.n_sky;
   if (kernel == fstat::KERNEL_INTERP) {
     if (v.coef16) {
       int rc = check_launch(p, fstat::launch_cexp(v, st), "coefficient exponent kernel");
@@ -752,6 +766,112 @@ double status_p(const fstat::GeoStatus& g) {
   double t;
   memcpy(&t, &g.max_p_bits, sizeof t);
   return t;
+}
+
+double status_bits(unsigned long long b) {
+  double t;
+  memcpy(&t, &b, sizeof t);
+  return t;
+}
+
+// Tiles of two sky points for the single-unit interp kernel's range of 8
+// spindowns per thread: a tile evaluates 16 (sky point, spindown) slots per
+// thread and SFT from one staged slice, which halves the slice loads per
+// pair (and with them the L2 traffic that holds the clock down) and shares
+// each thread's per-SFT work.  The slice must then hold the windows of both
+// sky points: their bins differ by at most
+//   |n0 - n1| (f_max T |v|max + |fdot|max (|tau|max T |v|max + P_max |r|max))
+// (P = Tdot T = (1 + v.n) T and tau = t - t_ref + r.n, so P0 - P1 = T v.(n0 -
+// n1) and tau0 - tau1 = r.(n0 - n1)), which is added to the single sky
+// point's spread.  Sky points are ordered in bands of z of the grid's
+// spacing, alternately by increasing and decreasing longitude, and
+// consecutive points are paired when the pair's slice still fits the LDS
+// capacity; a point without a partner forms a tile of its own sky point
+// twice (computed twice, written once).  Pairing is skipped when fewer than
+// half the points find a partner.  Needs the plan status of this unit's
+// geometry pass; waits for the stream (idle after the band check).
+int prepare_pairs(fstat_plan* p, const fstat_wu* wu, WuDev& v, Tile& t, hipStream_t st) {
+  v.sky_pairs = nullptr;
+  v.n_pairs = 0;
+  t.pair_seg = 0;
+  const bool has8 = t.nf_reg == 8 && (t.fd_split[split_index(8)] > 0 ||
+                                      std::all_of(t.fd_split, t.fd_split + fstat::kSplitSizes,
+                                                  [](int32_t x) { return x == 0; }));
+  if (resolved_kernel(p) != fstat::KERNEL_INTERP || coef16(p) || t.threads != fstat::kThreads || t.chunk < 4 ||
+      !has8 || wu->n_sky < 4 || p->force_seg > 0)
+    return FSTAT_OK;
+  const int64_t n = wu->n_sky;
+  const int nt = fstat::kThreads, cap = fstat::interp_max_seg(nt, false);
+  const double vmax = status_bits(p->status_h->max_v_bits), rmax = status_bits(p->status_h->max_r_bits);
+  const double f_max = std::max(fabs(wu->f0), fabs(wu->f0 + (double)(wu->n_f - 1) * wu->df));
+  const double fd_max = std::max(fabs(wu->fdot0), fabs(wu->fdot0 + (double)(wu->n_fd - 1) * wu->dfdot));
+  const double T = wu->t_sft;
+  // bins per unit of |n0 - n1|
+  const double C = f_max * T * vmax + fd_max * (p->max_abs_tau * T * vmax + p->max_p * rmax);
+  const double spread1 = ((nt - 1.0) * wu->df + fabs(wu->dfdot) * 7.0 * p->max_abs_tau) * p->max_p;
+  const double over1 = spread1 - (nt - 1.0) > 0 ? spread1 - (nt - 1.0) : 0.0;
+  // extra bins the pair may add with the width nt + 6 + ceil(over1 + extra) <= cap
+  const double budget = (double)(cap - nt - 6) - over1 - 1.0;
+  if (!std::isfinite(C) || !std::isfinite(budget) || budget < 1.0) return FSTAT_OK;
+  const double d_max = C > 0.0 ? budget / C : 4.0;
+  int rc = FSTAT_OK;
+  if (p->sky_h_cap < (size_t)(3 * n)) {
+    if (p->sky_h) (void)hipHostFree(p->sky_h);
+    p->sky_h = nullptr;
+    p->sky_h_cap = 0;
+    if (hipHostMalloc((void**)&p->sky_h, (size_t)(3 * n) * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      return set_err(p, FSTAT_E_NOMEM, "sky vectors: allocation of %lld entries failed", (long long)n);
+    }
+    p->sky_h_cap = (size_t)(3 * n);
+  }
+  rc = ensure_pinned_pair(p, &p->pairs_d, &p->pairs_h, &p->pairs_cap, (size_t)n, "sky pairs");
+  if (rc) return rc;
+  hipError_t e = hipMemcpyAsync(p->sky_h, wu->sky, (size_t)(3 * n) * sizeof(double), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_err(p, e, "sky vector copy");
+  const double* sk = p->sky_h;
+  const double h = sqrt(4.0 * M_PI / (double)n);           // grid spacing
+  const int64_t n_band = std::max<int64_t>(1, (int64_t)ceil(2.0 / h));
+  std::vector<std::pair<std::pair<int64_t, double>, int64_t>> key((size_t)n);
+  for (int64_t i = 0; i < n; ++i) {
+    const double z = sk[3 * i + 2], ph = atan2(sk[3 * i + 1], sk[3 * i]);
+    int64_t b = (int64_t)floor((z + 1.0) / 2.0 * (double)n_band);
+    b = b < 0 ? 0 : (b >= n_band ? n_band - 1 : b);
+    key[(size_t)i] = {{b, (b & 1) ? -ph : ph}, i};
+  }
+  std::sort(key.begin(), key.end());
+  auto dist = [&](int64_t a, int64_t b) {
+    const double dx = sk[3 * a] - sk[3 * b], dy = sk[3 * a + 1] - sk[3 * b + 1], dz = sk[3 * a + 2] - sk[3 * b + 2];
+    return sqrt((dx * dx + dy * dy) + dz * dz);
+  };
+  int64_t np = 0, paired = 0;
+  double worst = 0.0;
+  for (int64_t q = 0; q < n;) {
+    const int64_t a = key[(size_t)q].second;
+    if (q + 1 < n) {
+      const int64_t b = key[(size_t)q + 1].second;
+      const double d = dist(a, b);
+      if (d <= d_max) {
+        p->pairs_h[np++] = make_int2((int)a, (int)b);
+        worst = std::max(worst, d);
+        paired += 2;
+        q += 2;
+        continue;
+      }
+    }
+    p->pairs_h[np++] = make_int2((int)a, (int)a);
+    ++q;
+  }
+  if (2 * paired < n) return FSTAT_OK;
+  const double width = nt + 6.0 + ceil(over1 + worst * C);
+  if (!(width <= cap)) return FSTAT_OK;
+  e = hipMemcpyAsync(p->pairs_d, p->pairs_h, (size_t)np * sizeof(int2), hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return hip_err(p, e, "sky pair upload");
+  v.sky_pairs = p->pairs_d;
+  v.n_pairs = np;
+  t.pair_seg = (int)width & ~3;
+  return FSTAT_OK;
 }
 
 // Launch shape of the batched form (a Tile under the plan's batch class):
@@ -1128,6 +1248,9 @@ void fstat_plan_destroy(fstat_plan* p) {
   if (p->ents_d) (void)hipFree(p->ents_d);
   if (p->ents_h) (void)hipHostFree(p->ents_h);
   if (p->counter) (void)hipFree(p->counter);
+  if (p->sky_h) (void)hipHostFree(p->sky_h);
+  if (p->pairs_d) (void)hipFree(p->pairs_d);
+  if (p->pairs_h) (void)hipHostFree(p->pairs_h);
   if (p->coef) (void)hipFree(p->coef);
   if (p->acc) (void)hipFree(p->acc);
   if (p->cexp) (void)hipFree(p->cexp);
@@ -1166,7 +1289,10 @@ int fstat_compute(fstat_plan* p, const fstat_wu* wu, const fstat_out* out, void*
   WuDev v = make_dev(p, wu, out);
   rc = run_geometry(p, v, st, -1);
   if (rc) return rc;
-  rc = run_demod(p, v, pick_tile(p, wu), st);
+  Tile t = pick_tile(p, wu);
+  rc = prepare_pairs(p, wu, v, t, st);
+  if (rc) return rc;
+  rc = run_demod(p, v, t, st);
   if (rc == FSTAT_OK) queue_drop_check(p, p->status_d, p->status_h, 0, st);
   return rc;
 }
@@ -1302,7 +1428,10 @@ int fstat_semicoherent(fstat_plan* p, const fstat_wu* segs, int32_t n_seg, const
       float ms = 0.f;
       if (hipEventElapsedTime(&ms, p->ev0, p->ev1) == hipSuccess) ms_done += ms;
     }
-    rc = run_demod(p, v, pick_tile(p, &segs[k]), st);
+    Tile t = pick_tile(p, &segs[k]);
+    rc = prepare_pairs(p, &segs[k], v, t, st);
+    if (rc) return rc;
+    rc = run_demod(p, v, t, st);
     if (rc) return rc;
   }
   p->ms_prev = ms_done;
@@ -1458,10 +1587,13 @@ int fstat_autotune(fstat_plan* p, const fstat_wu* wu, const fstat_out* out, void
     float best = 1e30f;
     Tile best_t = default_tile(p, wu);
     for (Tile t0 : cands) {
-      const Tile t = complete_tile(p, wu, t0);      // as pick_tile runs it
+      Tile t = complete_tile(p, wu, t0);            // as pick_tile and fstat_compute run it
+      WuDev vt = v;
+      rc = prepare_pairs(p, wu, vt, t, st);
+      if (rc) return rc;
       float ms = 0.f;
       for (int rep = 0; rep < 2; ++rep) {
-        rc = run_demod(p, v, t, st);
+        rc = run_demod(p, vt, t, st);
         if (rc) return rc;
         hipError_t e = hipEventSynchronize(p->ev1);
         if (e != hipSuccess) return hip_err(p, e, "autotune");
@@ -1524,6 +1656,15 @@ int32_t fstat_interp_slice(double df, double dfdot, int32_t nfd, int32_t threads
   const int W = interp_seg_tau(&w, nfd, threads == 64 ? 64 : fstat::kThreads, coef16 != 0, max_abs_tau, max_p, &f);
   if (fits) *fits = f ? 1 : 0;
   return W;
+}
+
+int fstat_last_tile(const fstat_plan* p, int32_t* out) {
+  if (!p || !out || !p->have_last) return FSTAT_E_ARG;
+  const Tile& t = p->last_tile;
+  const int32_t head[7] = {t.nf_reg, t.chunk, t.seg, t.sblock, t.threads, t.pair_seg, (int32_t)p->last_sky_tiles};
+  for (int i = 0; i < 7; ++i) out[i] = head[i];
+  for (int i = 0; i < fstat::kSplitSizes; ++i) out[7 + i] = t.fd_split[i];
+  return FSTAT_OK;
 }
 
 double fstat_last_kernel_ms(fstat_plan* p) {

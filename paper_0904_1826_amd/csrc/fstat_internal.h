@@ -38,6 +38,11 @@ struct WuDev {
   int4* top;               // [top_k] (2F bits, sky, fdot, f)
   unsigned long long* n_above;
   int32_t accumulate;      // 1: the epilogue adds 2F to twoF (semi-coherent sum) instead of storing it
+  // interp tiles of two sky points: tile sky index p covers sky points
+  // sky_pairs[p].x and .y (equal for a point without a partner: computed
+  // twice, written once); NULL / 0: one sky point per tile
+  const int2* sky_pairs;
+  int64_t n_pairs;
   // interp kernels compiled without the global-memory path: tiles (per launch)
   // with an SFT whose windows were not all inside the LDS slice are counted
   // here, and their outputs set to NaN; NULL: not counted
@@ -63,6 +68,8 @@ struct Tile {
   int32_t threads;  // interp: work-group size, 64 or 256
   int32_t fast;     // interp: 1 if the slice holds every window of every SFT (no slice width was capped), so
                     // the kernel without the global-memory fallback may run
+  int32_t pair_seg; // interp: > 0: the range of 8 spindowns per thread runs tiles of two sky points
+                    // (WuDev::sky_pairs) with this slice width
   // interp with nf_reg 8, filled by the host for the work unit: the
   // spindowns run as consecutive ranges of fd_split[i] spindowns,
   // split_nfd(i) per thread, slice width seg_split[i], largest blocks first;
@@ -120,10 +127,12 @@ struct GeoStatus {
   int pad;
   unsigned long long max_abs_tau_bits;   // max |tau| over (sky, SFT), as FP64 bits
   unsigned long long max_p_bits;         // max Tdot T over (sky, SFT), as FP64 bits
+  unsigned long long max_v_bits;         // max |v| over SFTs (units of c), as FP64 bits
+  unsigned long long max_r_bits;         // max |r| over SFTs (light-seconds), as FP64 bits
   unsigned long long dropped;            // demodulation: tiles with an SFT outside the slice
 };
 // The geometry pass resets the first kGeoResetInts ints (not `dropped`).
-constexpr int kGeoResetInts = 6;
+constexpr int kGeoResetInts = 10;
 
 // Static scratch of the no-allocation entry point: one array of this many
 // bytes per device, laid out as the polynomial tables of every Dterms in both

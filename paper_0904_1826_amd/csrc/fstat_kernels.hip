@@ -119,20 +119,28 @@ __device__ __forceinline__ double warp_sum(double v) {
 // One block per sky point (grid-stride).  Writes (tau, Tdot) of every SFT and
 // (A, B, C, AB - C^2), and sets status bit 1 if some window of the template
 // grid leaves the band, bit 2 if AB - C^2 <= 0.  k* is monotone in f and in
-// fdot (every rounding step is monotone), so the grid corners bound it.
+// fdot (every rounding step is monotone), so the grid corners bound it.  The
+// status also receives max |tau|, max Tdot T and (from sky point 0's block)
+// max |v| and max |r| over the SFTs, which bound slice widths on the host.
 __global__ __launch_bounds__(256) void geometry_kernel(WuDev w, GeoStatus* status) {
-  __shared__ double red[5][4];
+  __shared__ double red[7][4];
   const double T = w.t_sft;
   const double f_lo = template_f(w, 0), f_hi = template_f(w, w.n_f - 1);
   const double fd_a = template_fd(w, 0), fd_b = template_fd(w, w.n_fd - 1);
   const double band_lo = (double)w.k_first, band_hi = (double)(w.k_first + w.n_bins - 1);
   const int D = w.dterms;
   for (int64_t s = blockIdx.x; s < w.n_sky; s += gridDim.x) {
-    double A = 0.0, B = 0.0, C = 0.0, tmax = 0.0, pmax = 0.0;
+    double A = 0.0, B = 0.0, C = 0.0, tmax = 0.0, pmax = 0.0, vmax = 0.0, rmax = 0.0;
     int bad = 0;
     for (int64_t al = threadIdx.x; al < w.n_sft; al += blockDim.x) {
       double tau, tdot;
       sft_geometry(w, s, al, tau, tdot);
+      if (s == 0) {
+        const double* r = w.pos + 3 * al;
+        const double* v = w.vel + 3 * al;
+        vmax = fmax(vmax, sqrt((v[0] * v[0] + v[1] * v[1]) + v[2] * v[2]));
+        rmax = fmax(rmax, sqrt((r[0] * r[0] + r[1] * r[1]) + r[2] * r[2]));
+      }
       tmax = fmax(tmax, fabs(tau));
       const double P = bin_scale(tdot, T);
       pmax = fmax(pmax, P);
@@ -156,8 +164,13 @@ __global__ __launch_bounds__(256) void geometry_kernel(WuDev w, GeoStatus* statu
     C = warp_sum(C);
     for (int o = 32; o > 0; o >>= 1) tmax = fmax(tmax, __shfl_xor(tmax, o, 64));
     for (int o = 32; o > 0; o >>= 1) pmax = fmax(pmax, __shfl_xor(pmax, o, 64));
+    for (int o = 32; o > 0; o >>= 1) vmax = fmax(vmax, __shfl_xor(vmax, o, 64));
+    for (int o = 32; o > 0; o >>= 1) rmax = fmax(rmax, __shfl_xor(rmax, o, 64));
     const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
-    if (ln == 0) { red[0][wv] = A; red[1][wv] = B; red[2][wv] = C; red[3][wv] = tmax; red[4][wv] = pmax; }
+    if (ln == 0) {
+      red[0][wv] = A; red[1][wv] = B; red[2][wv] = C; red[3][wv] = tmax; red[4][wv] = pmax;
+      red[5][wv] = vmax; red[6][wv] = rmax;
+    }
     const int any_bad = __syncthreads_or(bad);
     if (threadIdx.x == 0) {
       A = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
@@ -172,6 +185,12 @@ __global__ __launch_bounds__(256) void geometry_kernel(WuDev w, GeoStatus* statu
       atomicMax(&status->max_abs_tau_bits, (unsigned long long)__double_as_longlong(tm));
       const double pm = fmax(fmax(red[4][0], red[4][1]), fmax(red[4][2], red[4][3]));
       atomicMax(&status->max_p_bits, (unsigned long long)__double_as_longlong(pm));   // P > 0: bits order as values
+      if (s == 0) {                  // non-negative: bits order as values
+        const double vm = fmax(fmax(red[5][0], red[5][1]), fmax(red[5][2], red[5][3]));
+        const double rm = fmax(fmax(red[6][0], red[6][1]), fmax(red[6][2], red[6][3]));
+        atomicMax(&status->max_v_bits, (unsigned long long)__double_as_longlong(vm));
+        atomicMax(&status->max_r_bits, (unsigned long long)__double_as_longlong(rm));
+      }
     }
     __syncthreads();
   }
@@ -576,53 +595,63 @@ __device__ __forceinline__ CoefSet16 load_coef16_global(const WuDev& w, int64_t 
 // SFT the first column of its coefficient slice and whether every window of
 // the tile falls inside the slice, and per (SFT, spindown) the FP64 product
 // fdot * tau and the phase factor exp(-2 pi i frac(tau (fdot/2) tau)).
-template <int NFD, int S>
+template <int NFD, int S, int NSKY = 1>
 struct GroupMeta {
-  double2 geo[S];     // (tau, Tdot T) of the sky point
-  float2 tsplit[S];   // tau as hi + lo FP32 (split phase mode)
-  float a[S], b[S];
+  double2 geo[S][NSKY];     // (tau, Tdot T) of the tile's sky points
+  float2 tsplit[S][NSKY];   // tau as hi + lo FP32 (split phase mode)
+  float a[S][NSKY], b[S][NSKY];
   int lo[S];
   int fast[S];
-  double g[S][NFD];
-  float2 e[S][NFD];
+  double g[S][NSKY][NFD];
+  float2 e[S][NSKY][NFD];
 };
 
 // Fills the meta of SFTs [al0, al0 + n) with all threads of the work-group.
 // k* is monotone in f and in fdot, so the tile's corners bound the bins of
-// every (template, SFT) pair of the tile: [kmin, kmax] in slice columns.
-template <int NFD, int S, int NT>
-__device__ __forceinline__ void group_meta(const WuDev& w, const double2* geo, const float* arow, const float* brow,
-                                           int64_t al0, int n, int64_t i0, int64_t i_last, double f_first,
-                                           double f_last, int W, GroupMeta<NFD, S>& m) {
+// every (template, SFT) pair of the tile: [kmin, kmax] in slice columns, over
+// the tile's NSKY sky points (rows geo[u], arow[u], brow[u]).
+template <int NFD, int S, int NT, int NSKY>
+__device__ __forceinline__ void group_meta(const WuDev& w, const double2* const* geo, const float* const* arow,
+                                           const float* const* brow, int64_t al0, int n, int64_t i0, int64_t i_last,
+                                           double f_first, double f_last, int W, GroupMeta<NFD, S, NSKY>& m) {
   const int tid = threadIdx.x;
-  const int t3 = tid - (NT - 2 * S);             // S threads before the last S copy tau, Tdot T, a, b
-  if (t3 >= 0 && t3 < n) {
-    m.geo[t3] = geo[al0 + t3];
-    m.tsplit[t3] = split64(geo[al0 + t3].x);
+  // NSKY S threads before the last S copy tau, Tdot T, a, b
+  const int t3 = tid - (NT - (NSKY + 1) * S);
+  if (t3 >= 0 && t3 < NSKY * S && t3 % S < n) {
+    const int u = t3 / S, c = t3 % S;
+    m.geo[c][u] = geo[u][al0 + c];
+    m.tsplit[c][u] = split64(geo[u][al0 + c].x);
     // the FP16 coefficient form stores c 2^-e: the weights carry 2^e
-    const float sa = w.coef16 ? ldexpf(1.f, w.cexp[al0 + t3]) : 1.f;
-    m.a[t3] = arow[al0 + t3] * sa;
-    m.b[t3] = brow[al0 + t3] * sa;
+    const float sa = w.coef16 ? ldexpf(1.f, w.cexp[al0 + c]) : 1.f;
+    m.a[c][u] = arow[u][al0 + c] * sa;
+    m.b[c][u] = brow[u][al0 + c] * sa;
   }
-  for (int e = tid; e < n * NFD; e += NT) {
-    const int c = e / NFD, r = e % NFD;
-    const double2 g = geo[al0 + c];
+  for (int e = tid; e < n * NSKY * NFD; e += NT) {
+    const int c = e / (NSKY * NFD), u = (e / NFD) % NSKY, r = e % NFD;
+    const double2 g = geo[u][al0 + c];
     const int64_t i = (i0 + r < w.n_fd) ? i0 + r : w.n_fd - 1;
     const double fd = template_fd(w, i);
-    m.g[c][r] = bin_offset(fd, g.x, g.y);
+    m.g[c][u][r] = bin_offset(fd, g.x, g.y);
     const double h = (0.5 * fd) * g.x;                 // (fdot / 2) tau
     const float q = w.phase_mode ? frac_split_product(split64(g.x), split64(h)) : (float)fract64(g.x * h);
-    m.e[c][r] = make_float2(cos_rev(q), -sin_rev(q));
+    m.e[c][u][r] = make_float2(cos_rev(q), -sin_rev(q));
   }
   const int t2 = tid - (NT - S);                 // the last S threads do the slice bounds
   if (t2 >= 0 && t2 < n) {
-    const double2 g = geo[al0 + t2];
-    const double ga = bin_offset(template_fd(w, i0), g.x, g.y), gb = bin_offset(template_fd(w, i_last), g.x, g.y);
-    const double d1 = bin_position(f_first, ga, g.y), d2 = bin_position(f_first, gb, g.y);
-    const double d3 = bin_position(f_last, ga, g.y), d4 = bin_position(f_last, gb, g.y);
+    double lo_d = 0.0, hi_d = 0.0;
+#pragma unroll
+    for (int u = 0; u < NSKY; ++u) {
+      const double2 g = geo[u][al0 + t2];
+      const double ga = bin_offset(template_fd(w, i0), g.x, g.y), gb = bin_offset(template_fd(w, i_last), g.x, g.y);
+      const double d1 = bin_position(f_first, ga, g.y), d2 = bin_position(f_first, gb, g.y);
+      const double d3 = bin_position(f_last, ga, g.y), d4 = bin_position(f_last, gb, g.y);
+      const double mn = d1 < d2 ? d1 : d2, mx = d3 > d4 ? d3 : d4;
+      lo_d = (u == 0 || mn < lo_d) ? mn : lo_d;
+      hi_d = (u == 0 || mx > hi_d) ? mx : hi_d;
+    }
     // column offsets of the extreme bins; the band is below 2^31 bins
-    const int kmin = (int)(floor(d1 < d2 ? d1 : d2) - (double)w.k_first);
-    const int kmax = (int)(floor(d3 > d4 ? d3 : d4) - (double)w.k_first);
+    const int kmin = (int)(floor(lo_d) - (double)w.k_first);
+    const int kmax = (int)(floor(hi_d) - (double)w.k_first);
     const int nb = (int)w.n_bins;
     const int max_lo = nb > W ? nb - W : 0;
     int lo = (kmin > 1 ? kmin : 1) - 1;           // one bin of slack
@@ -789,17 +818,26 @@ __device__ __forceinline__ v4f lds_load_v(LdsPtr p, int i) { return p[i]; }
 // The tile covers spindowns [fd0, fd1) of the work unit in blocks of NFD
 // (the last block of a range may be partial: its missing spindowns repeat
 // the range's last one and are not written).
-template <int NFD, int S, int G, int NT, bool C16, bool SAFE>
+template <int NFD, int S, int G, int NT, bool C16, bool SAFE, int NSKY = 1>
 __device__ __forceinline__ void interp_tile(const WuDev& w, int W, int64_t tile, int64_t al_begin, int64_t al_end,
-                                            float4* cbuf0, float4* cbuf1, GroupMeta<NFD, S>* meta, int64_t fd0,
+                                            float4* cbuf0, float4* cbuf1, GroupMeta<NFD, S, NSKY>* meta, int64_t fd0,
                                             int64_t fd1) {
   const int tid = threadIdx.x;
   const int64_t n_fdb = (fd1 - fd0 + NFD - 1) / NFD;
   using F = SliceForm<NT, C16>;
   constexpr int Wp = F::cap;                       // LDS row stride
   int64_t t = tile;
-  const int64_t s = t % w.n_sky;
-  t /= w.n_sky;
+  const int64_t n_st = NSKY == 2 ? w.n_pairs : w.n_sky;    // sky tiles
+  const int64_t st_idx = t % n_st;
+  t /= n_st;
+  int64_t su[NSKY];                                // the tile's sky points
+  if constexpr (NSKY == 2) {
+    const int2 pr = w.sky_pairs[st_idx];
+    su[0] = pr.x;
+    su[1] = pr.y;
+  } else {
+    su[0] = st_idx;
+  }
   const int64_t ib = t % n_fdb;
   const int64_t ft = t / n_fdb;
   const int64_t j0 = ft * NT;
@@ -813,21 +851,30 @@ __device__ __forceinline__ void interp_tile(const WuDev& w, int W, int64_t tile,
   const float2 fsplit = split64(f);
   const bool split_phase = w.phase_mode != 0;
   const double f_first = template_f(w, j0), f_last = template_f(w, j_last);
-  const double2* geo = w.geo + s * w.n_sft;
-  const float* arow = w.a + s * w.n_sft;
-  const float* brow = w.b + s * w.n_sft;
+  const double2* geo[NSKY];
+  const float* arow[NSKY];
+  const float* brow[NSKY];
+#pragma unroll
+  for (int u = 0; u < NSKY; ++u) {
+    geo[u] = w.geo + su[u] * w.n_sft;
+    arow[u] = w.a + su[u] * w.n_sft;
+    brow[u] = w.b + su[u] * w.n_sft;
+  }
   const int n = (int)(al_end - al_begin);
   const int k_first = (int)w.k_first;
 
-  float far[NFD], fai[NFD], fbr[NFD], fbi[NFD];
+  // accumulators of (sky point u, spindown r) at slot u NFD + r
+  constexpr int NSL = NSKY * NFD;
+  float far[NSL], fai[NSL], fbr[NSL], fbi[NSL];
 #pragma unroll
-  for (int r = 0; r < NFD; ++r) {
+  for (int x = 0; x < NSL; ++x) {
+    const int u = x / NFD, r = x % NFD;
     const int64_t i = (i0 + r < fd1) ? i0 + r : fd1 - 1;
     if (al_begin > 0) {
-      const float4 v = w.acc[(s * w.n_fd + i) * w.n_f + j];
-      far[r] = v.x; fai[r] = v.y; fbr[r] = v.z; fbi[r] = v.w;
+      const float4 v = w.acc[(su[u] * w.n_fd + i) * w.n_f + j];
+      far[x] = v.x; fai[x] = v.y; fbr[x] = v.z; fbi[x] = v.w;
     } else {
-      far[r] = fai[r] = fbr[r] = fbi[r] = 0.f;
+      far[x] = fai[x] = fbr[x] = fbi[x] = 0.f;
     }
   }
 
@@ -835,7 +882,7 @@ __device__ __forceinline__ void interp_tile(const WuDev& w, int W, int64_t tile,
   // help stage slices
   const bool wave_live = __builtin_amdgcn_readfirstlane((int)(j0 + (tid & ~63) < w.n_f));
   bool dropped_any = false;                        // (not SAFE) an SFT left its slice: outputs become NaN
-  group_meta<NFD, S, NT>(w, geo, arow, brow, al_begin, n < S ? n : S, i0, i_last, f_first, f_last, W, meta[0]);
+  group_meta<NFD, S, NT, NSKY>(w, geo, arow, brow, al_begin, n < S ? n : S, i0, i_last, f_first, f_last, W, meta[0]);
   __syncthreads();
   const uint32_t lane16 = lane_bytes16();
   slice_load_lds<NT, C16>(w, al_begin, meta[0].lo[0], cbuf0, lane16);
@@ -851,7 +898,8 @@ __device__ __forceinline__ void interp_tile(const WuDev& w, int W, int64_t tile,
     const int kk = k % S, gq = (k / S) & 1;
     if (kk == 0 && k + S < n) {                    // values of the next group, read after >= 1 barrier
       const int n1 = n - (k + S) < S ? n - (k + S) : S;
-      group_meta<NFD, S, NT>(w, geo, arow, brow, al_begin + k + S, n1, i0, i_last, f_first, f_last, W, meta[gq ^ 1]);
+      group_meta<NFD, S, NT, NSKY>(w, geo, arow, brow, al_begin + k + S, n1, i0, i_last, f_first, f_last, W,
+                                   meta[gq ^ 1]);
     }
     const bool more = k + 1 < n;
     // unconditional (the last step reloads its own SFT and discards it), so
@@ -860,14 +908,23 @@ __device__ __forceinline__ void interp_tile(const WuDev& w, int W, int64_t tile,
     // the other buffer was consumed before the last barrier
     const int k1 = more ? k + 1 : k;
     slice_load_lds<NT, C16>(w, al_begin + k1, meta[(k1 / S) & 1].lo[k1 % S], next, lane16);
-    const GroupMeta<NFD, S>& m = meta[gq];
+    const GroupMeta<NFD, S, NSKY>& m = meta[gq];
     const int64_t al = al_begin + k;
     if constexpr (decltype(live)::value) {
-    const double2 g = m.geo[kk];
-    const float a = m.a[kk], b = m.b[kk];
-    const float pf = split_phase ? frac_split_product(m.tsplit[kk], fsplit)   // frac(tau f)
-                                 : (float)fract64(g.x * f);
-    const float cf = cos_rev(pf), sf = sin_rev(pf);
+    // per sky point: Tdot T, the weights and exp(-2 pi i frac(tau f))
+    double pu[NSKY];
+    float au[NSKY], bu[NSKY], cf[NSKY], sf[NSKY];
+#pragma unroll
+    for (int u = 0; u < NSKY; ++u) {
+      const double2 g = m.geo[kk][u];
+      pu[u] = g.y;
+      au[u] = m.a[kk][u];
+      bu[u] = m.b[kk][u];
+      const float pf = split_phase ? frac_split_product(m.tsplit[kk][u], fsplit)   // frac(tau f)
+                                   : (float)fract64(g.x * f);
+      cf[u] = cos_rev(pf);
+      sf[u] = sin_rev(pf);
+    }
     // LDS byte address of bin k in row 0 of the slice: 16 k + (seg - 16 (k_first + lo)),
     // in 32-bit modular arithmetic
     // (uniform; kept opaque in a scalar register so that the compiler forms one
@@ -883,30 +940,33 @@ __device__ __forceinline__ void interp_tile(const WuDev& w, int W, int64_t tile,
     // schedules across SFTs and spills.
     if (__builtin_amdgcn_readfirstlane(m.fast[kk])) {
 #pragma unroll
-      for (int r = 0; r < NFD; ++r) {
-        const double dphi = bin_position(f, m.g[kk][r], g.y);
+      for (int x = 0; x < NSL; ++x) {
+        const int u = x / NFD, r = x % NFD;
+        const double dphi = bin_position(f, m.g[kk][u][r], pu[u]);
         const LdsPtr c = lds_pointer(((uint32_t)(int)dphi << 4) + boff);
-        const float u = (float)fract64(dphi);   // kappa
+        const float kap = (float)fract64(dphi);
         if constexpr (C16)
-          interp_accumulate16(lds_load_v(c, 0), lds_load_v(c, Wp), u, cf, sf, m.e[kk][r], a, b, far[r], fai[r],
-                              fbr[r], fbi[r]);
+          interp_accumulate16(lds_load_v(c, 0), lds_load_v(c, Wp), kap, cf[u], sf[u], m.e[kk][u][r], au[u], bu[u],
+                              far[x], fai[x], fbr[x], fbi[x]);
         else
-          interp_accumulate(lds_load(c, 0), lds_load(c, Wp), lds_load(c, 2 * Wp), lds_load(c, 3 * Wp), u, cf, sf,
-                            m.e[kk][r], a, b, far[r], fai[r], fbr[r], fbi[r]);
-        if (r % G == G - 1) __builtin_amdgcn_sched_barrier(0);   // bounds the coefficient registers in flight
+          interp_accumulate(lds_load(c, 0), lds_load(c, Wp), lds_load(c, 2 * Wp), lds_load(c, 3 * Wp), kap, cf[u],
+                            sf[u], m.e[kk][u][r], au[u], bu[u], far[x], fai[x], fbr[x], fbi[x]);
+        if (x % G == G - 1) __builtin_amdgcn_sched_barrier(0);   // bounds the coefficient registers in flight
       }
     } else if constexpr (SAFE) {
 #pragma unroll
-      for (int r = 0; r < NFD; ++r) {
-        const double dphi = bin_position(f, m.g[kk][r], g.y);
-        const float u = (float)fract64(dphi);   // kappa
+      for (int x = 0; x < NSL; ++x) {
+        const int u = x / NFD, r = x % NFD;
+        const double dphi = bin_position(f, m.g[kk][u][r], pu[u]);
+        const float kap = (float)fract64(dphi);
         if constexpr (C16) {
           const CoefSet16 cs = load_coef16_global(w, al, (int64_t)(int)dphi - w.k_first);
-          interp_accumulate16(cs.c[0], cs.c[1], u, cf, sf, m.e[kk][r], a, b, far[r], fai[r], fbr[r], fbi[r]);
+          interp_accumulate16(cs.c[0], cs.c[1], kap, cf[u], sf[u], m.e[kk][u][r], au[u], bu[u], far[x], fai[x],
+                              fbr[x], fbi[x]);
         } else {
           const CoefSet cs = load_coef_global(w, al, (int64_t)(int)dphi - w.k_first);
-          interp_accumulate(cs.c[0], cs.c[1], cs.c[2], cs.c[3], u, cf, sf, m.e[kk][r], a, b, far[r], fai[r], fbr[r],
-                            fbi[r]);
+          interp_accumulate(cs.c[0], cs.c[1], cs.c[2], cs.c[3], kap, cf[u], sf[u], m.e[kk][u][r], au[u], bu[u],
+                            far[x], fai[x], fbr[x], fbi[x]);
         }
       }
     } else {
@@ -934,38 +994,41 @@ __device__ __forceinline__ void interp_tile(const WuDev& w, int W, int64_t tile,
     if (tid == 0 && w.dropped) atomicAdd(w.dropped, 1ull);
     const float nan = __builtin_nanf("");
 #pragma unroll
-    for (int r = 0; r < NFD; ++r) far[r] = fai[r] = fbr[r] = fbi[r] = nan;
+    for (int x = 0; x < NSL; ++x) far[x] = fai[x] = fbr[x] = fbi[x] = nan;
   }
   const bool last = al_end == w.n_sft;
-  const double4 abcd = w.abcd[s];
 #pragma unroll
-  for (int r = 0; r < NFD; ++r) {
+  for (int x = 0; x < NSL; ++x) {
+    const int u = x / NFD, r = x % NFD;
+    if (u > 0 && su[u] == su[0]) continue;         // a sky point without a partner is written once
+    const int64_t s = su[u];
     const int64_t i = i0 + r;
     if (i >= fd1) continue;
     const int64_t o = (s * w.n_fd + i) * w.n_f + j;
     if (!last) {
-      w.acc[o] = make_float4(far[r], fai[r], fbr[r], fbi[r]);
+      w.acc[o] = make_float4(far[x], fai[x], fbr[x], fbi[x]);
       continue;
     }
-    const double ar = far[r], ai = fai[r], br = fbr[r], bi = fbi[r];
+    const double4 abcd = w.abcd[s];
+    const double ar = far[x], ai = fai[x], br = fbr[x], bi = fbi[x];
     const double fa2 = ar * ar + ai * ai, fb2 = br * br + bi * bi, re = ar * br + ai * bi;
     const double two_f = 2.0 * (abcd.y * fa2 + abcd.x * fb2 - 2.0 * abcd.z * re) / abcd.w;
     if (w.twoF) w.twoF[o] = w.accumulate ? w.twoF[o] + (float)two_f : (float)two_f;
     if (w.cand) cand_push(w, (float)two_f, o);
-    if (w.fa) w.fa[o] = make_float2(far[r], fai[r]);
-    if (w.fb) w.fb[o] = make_float2(fbr[r], fbi[r]);
+    if (w.fa) w.fa[o] = make_float2(far[x], fai[x]);
+    if (w.fb) w.fb[o] = make_float2(fbr[x], fbi[x]);
   }
 }
 
 // One tile per work-group (see interp_tile) over spindowns [fd0, fd1).
-template <int NFD, int S, int MINW, int G, int NT, bool C16, bool SAFE>
+template <int NFD, int S, int MINW, int G, int NT, bool C16, bool SAFE, int NSKY = 1>
 __global__ __launch_bounds__(NT, MINW) void demod_interp_kernel(WuDev w, int W, int64_t al_begin, int64_t al_end,
                                                                  int64_t fd0, int64_t fd1) {
   using F = SliceForm<NT, C16>;
-  __shared__ GroupMeta<NFD, S> meta[2];
+  __shared__ GroupMeta<NFD, S, NSKY> meta[2];
   __shared__ float4 cbuf0[F::rows * F::cap];
   __shared__ float4 cbuf1[F::rows * F::cap];
-  interp_tile<NFD, S, G, NT, C16, SAFE>(w, W, blockIdx.x, al_begin, al_end, cbuf0, cbuf1, meta, fd0, fd1);
+  interp_tile<NFD, S, G, NT, C16, SAFE, NSKY>(w, W, blockIdx.x, al_begin, al_end, cbuf0, cbuf1, meta, fd0, fd1);
 }
 
 // Many work units in one persistent launch: the grid holds as many
@@ -1288,19 +1351,20 @@ int interp_launches(const WuDev& w, const Tile& t) {
   return (int)((w.n_sft + sb - 1) / sb);
 }
 
-template <int NFD, int S, int MINW, int G, int NT, bool C16, bool SAFE = true>
+template <int NFD, int S, int MINW, int G, int NT, bool C16, bool SAFE = true, int NSKY = 1>
 static hipError_t launch_interp_t(const WuDev& w, const Tile& t, hipStream_t st, int64_t fd0, int64_t fd1) {
   const int W = t.seg;
   const int64_t n_ft = (w.n_f + NT - 1) / NT;
-  const int64_t n_tiles = n_ft * ((fd1 - fd0 + NFD - 1) / NFD) * w.n_sky;
+  if (NSKY == 2 && (!w.sky_pairs || w.n_pairs <= 0)) return hipErrorInvalidValue;
+  const int64_t n_tiles = n_ft * ((fd1 - fd0 + NFD - 1) / NFD) * (NSKY == 2 ? w.n_pairs : w.n_sky);
   if (n_tiles <= 0 || n_tiles > 0x7fffffffLL || W < 8 || W > SliceForm<NT, C16>::cap)
     return hipErrorInvalidConfiguration;
   const int64_t sb = t.sblock > 0 ? t.sblock : w.n_sft;
   if (sb < w.n_sft && !w.acc) return hipErrorInvalidValue;
   for (int64_t al = 0; al < w.n_sft; al += sb) {
     const int64_t end = al + sb < w.n_sft ? al + sb : w.n_sft;
-    hipLaunchKernelGGL((demod_interp_kernel<NFD, S, MINW, G, NT, C16, SAFE>), dim3((unsigned)n_tiles), dim3(NT), 0, st,
-                       w, W, al, end, fd0, fd1);
+    hipLaunchKernelGGL((demod_interp_kernel<NFD, S, MINW, G, NT, C16, SAFE, NSKY>), dim3((unsigned)n_tiles), dim3(NT),
+                       0, st, w, W, al, end, fd0, fd1);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -1349,7 +1413,12 @@ static hipError_t launch_interp_range(const WuDev& w, const Tile& t, hipStream_t
   switch (t.nf_reg) {
     // 4 waves per SIMD: per-SFT values for 8 SFTs at a time, so that four
     // work-groups' LDS fits a CU
-    case 8: return t.chunk >= 4 ? (t.fast ? launch_interp_t<8, 8, 4, 4, kThreads, false, false>(w, t, st, fd0, fd1)
+    // tiles of two sky points (t.pair_seg > 0): 16 accumulator slots per
+    // thread, three waves per SIMD
+    case 8: if (t.pair_seg > 0)
+              return t.fast ? launch_interp_t<8, 8, 3, 4, kThreads, false, false, 2>(w, t, st, fd0, fd1)
+                            : launch_interp_t<8, 8, 3, 4, kThreads, false, true, 2>(w, t, st, fd0, fd1);
+            return t.chunk >= 4 ? (t.fast ? launch_interp_t<8, 8, 4, 4, kThreads, false, false>(w, t, st, fd0, fd1)
                                           : launch_interp_t<8, 8, 4, 4, kThreads, false>(w, t, st, fd0, fd1))
                    : w3         ? launch_interp_t<8, 16, 3, 4, kThreads, false>(w, t, st, fd0, fd1)
                                 : launch_interp_t<8, 16, 2, 4, kThreads, false>(w, t, st, fd0, fd1);
@@ -1376,16 +1445,26 @@ static hipError_t launch_interp_range(const WuDev& w, const Tile& t, hipStream_t
 // consecutive ranges with 16, 8, 7, ..., 4 per thread, one launch sequence
 // per range (t.fast covers every range's slice).
 static hipError_t launch_interp(const WuDev& w, const Tile& t, hipStream_t st) {
+  // the 8-spindown range may run tiles of two sky points (t.pair_seg)
+  const bool pairs = t.pair_seg > 0 && w.sky_pairs && w.n_pairs > 0 && !w.coef16 && t.threads == kThreads;
   int64_t total = 0;
   for (int i = 0; i < kSplitSizes; ++i) total += t.fd_split[i] > 0 ? t.fd_split[i] : 0;
-  if (total == 0) return launch_interp_range(w, t, st, 0, w.n_fd);
+  if (total == 0) {
+    Tile t1 = t;
+    const bool pr = pairs && t.nf_reg == 8;
+    t1.seg = pr ? t.pair_seg : t.seg;
+    t1.pair_seg = pr ? t.pair_seg : 0;
+    return launch_interp_range(w, t1, st, 0, w.n_fd);
+  }
   if (total != w.n_fd) return hipErrorInvalidValue;
   int64_t lo = 0;
   for (int i = 0; i < kSplitSizes; ++i) {
     if (t.fd_split[i] <= 0) continue;
     Tile ti = t;
     ti.nf_reg = split_nfd(i);
-    ti.seg = t.seg_split[i];
+    const bool pr = pairs && ti.nf_reg == 8;
+    ti.seg = pr ? t.pair_seg : t.seg_split[i];
+    ti.pair_seg = pr ? t.pair_seg : 0;
     if (ti.nf_reg == 4 || ti.nf_reg == 16) ti.chunk = t.chunk > 3 ? 3 : t.chunk;
     else if (ti.nf_reg < 8) ti.chunk = 4;
     const hipError_t e = launch_interp_range(w, ti, st, lo, lo + t.fd_split[i]);

@@ -32,6 +32,14 @@ def test_exports_every_declared_symbol(lib):
         assert hasattr(lib, n), n
 
 
+def test_header_constants_match_the_binding():
+    src = open(os.path.join(ROOT, "include", "fstat.h")).read()
+    m = re.search(r"#define\s+FSTAT_LAST_TILE_LEN\s+([0-9]+)", src)
+    assert m and int(m.group(1)) == P.LAST_TILE_LEN
+    m = re.search(r"#define\s+FSTAT_NOALLOC_SCRATCH_BYTES\s+\(([0-9]+)u\s*<<\s*([0-9]+)\)", src)
+    assert m and int(m.group(1)) << int(m.group(2)) == P.NOALLOC_SCRATCH_BYTES
+
+
 def test_strerror(lib):
     for code in range(0, -7, -1):
         assert P.fstat_strerror(code)
@@ -54,6 +62,7 @@ def test_null_plan_and_null_arguments(lib):
     assert lib.fstat_bins(None, None, 0, None, None, None, None, None, None, None, None) == P.FSTAT_E_ARG
     assert lib.fstat_autotune(None, None, None, None, None) == P.FSTAT_E_ARG
     assert lib.fstat_last_kernel_ms(None) < 0
+    assert lib.fstat_last_tile(None, None) == P.FSTAT_E_ARG
     lib.fstat_plan_destroy(None)
     assert lib.fstat_last_error(None) == b""
     assert lib.fstat_plan_create(None, None) == P.FSTAT_E_ARG
