@@ -87,9 +87,10 @@ struct fstat_plan {
   int2* pairs_h = nullptr;              // pinned
   size_t pairs_cap = 0;
   hipStream_t cap_stream = nullptr;
-  // persistent grids of the batch kernels with split_nfd(i) spindowns per thread,
-  // with [i][1] and without [i][0] the global-memory fallback
-  int batch_grid[fstat::kSplitSizes][2] = {};
+  // persistent grids of the batch kernels with split_nfd(c % kSplitSizes)
+  // spindowns and 1 + c / kSplitSizes sky points per tile, with [c][1] and
+  // without [c][0] the global-memory fallback
+  int batch_grid[2 * fstat::kSplitSizes][2] = {};
   std::map<std::vector<int64_t>, hipGraphExec_t> graphs;
   // fault injection (host-side forcing of error paths); force_seg > 0 runs the
   // interp kernels without the global-memory path at that slice width
@@ -774,63 +775,40 @@ double status_bits(unsigned long long b) {
   return t;
 }
 
-// Tiles of two sky points for the single-unit interp kernel's range of 8
-// spindowns per thread: a tile evaluates 16 (sky point, spindown) slots per
-// thread and SFT from one staged slice, which halves the slice loads per
-// pair (and with them the L2 traffic that holds the clock down) and shares
-// each thread's per-SFT work.  The slice must then hold the windows of both
-// sky points: their bins differ by at most
+// Tiles of two sky points for the interp kernels' ranges of at most 8
+// spindowns per thread: a tile evaluates (sky point, spindown) slots of both
+// points per thread and SFT from one staged slice, which halves the slice
+// loads per pair (and with them the L2 traffic that holds the clock down)
+// and shares each thread's per-SFT work.  The slice must then hold the
+// windows of both sky points: their bins differ by at most
 //   |n0 - n1| (f_max T |v|max + |fdot|max (|tau|max T |v|max + P_max |r|max))
 // (P = Tdot T = (1 + v.n) T and tau = t - t_ref + r.n, so P0 - P1 = T v.(n0 -
-// n1) and tau0 - tau1 = r.(n0 - n1)), which is added to the single sky
-// point's spread.  Sky points are ordered in bands of z of the grid's
-// spacing, alternately by increasing and decreasing longitude, and
-// consecutive points are paired when the pair's slice still fits the LDS
-// capacity; a point without a partner forms a tile of its own sky point
-// twice (computed twice, written once).  Pairing is skipped when fewer than
-// half the points find a partner.  Needs the plan status of this unit's
-// geometry pass; waits for the stream (idle after the band check).
-int prepare_pairs(fstat_plan* p, const fstat_wu* wu, WuDev& v, Tile& t, hipStream_t st) {
-  v.sky_pairs = nullptr;
-  v.n_pairs = 0;
-  t.pair_seg = 0;
-  const bool has8 = t.nf_reg == 8 && (t.fd_split[split_index(8)] > 0 ||
-                                      std::all_of(t.fd_split, t.fd_split + fstat::kSplitSizes,
-                                                  [](int32_t x) { return x == 0; }));
-  if (resolved_kernel(p) != fstat::KERNEL_INTERP || coef16(p) || t.threads != fstat::kThreads || t.chunk < 4 ||
-      !has8 || wu->n_sky < 4 || p->force_seg > 0)
-    return FSTAT_OK;
+// n1) and tau0 - tau1 = r.(n0 - n1)), which is added to the spread of one
+// sky point at 8 spindowns per thread (the widest such range).  Sky points
+// are ordered in bands of z of the grid's spacing, alternately by
+// increasing and decreasing longitude, and consecutive points are paired
+// when the pair's slice still fits the LDS capacity; a point without a
+// partner forms a tile of its own sky point twice (computed twice, written
+// once).  Writes the n_pairs tiles to `out` (room for n_sky) and returns the
+// slice width, or 0 when pairing does not apply (fewer than half the points
+// find a partner, or no width fits).
+int make_pairs(const fstat_wu* wu, const fstat::GeoStatus& g, const double* sk, int2* out, int64_t* n_pairs) {
+  *n_pairs = 0;
   const int64_t n = wu->n_sky;
   const int nt = fstat::kThreads, cap = fstat::interp_max_seg(nt, false);
-  const double vmax = status_bits(p->status_h->max_v_bits), rmax = status_bits(p->status_h->max_r_bits);
+  const double vmax = status_bits(g.max_v_bits), rmax = status_bits(g.max_r_bits);
+  const double max_tau = status_bits(g.max_abs_tau_bits), max_p = status_bits(g.max_p_bits);
   const double f_max = std::max(fabs(wu->f0), fabs(wu->f0 + (double)(wu->n_f - 1) * wu->df));
   const double fd_max = std::max(fabs(wu->fdot0), fabs(wu->fdot0 + (double)(wu->n_fd - 1) * wu->dfdot));
   const double T = wu->t_sft;
   // bins per unit of |n0 - n1|
-  const double C = f_max * T * vmax + fd_max * (p->max_abs_tau * T * vmax + p->max_p * rmax);
-  const double spread1 = ((nt - 1.0) * wu->df + fabs(wu->dfdot) * 7.0 * p->max_abs_tau) * p->max_p;
+  const double C = f_max * T * vmax + fd_max * (max_tau * T * vmax + max_p * rmax);
+  const double spread1 = ((nt - 1.0) * wu->df + fabs(wu->dfdot) * 7.0 * max_tau) * max_p;
   const double over1 = spread1 - (nt - 1.0) > 0 ? spread1 - (nt - 1.0) : 0.0;
   // extra bins the pair may add with the width nt + 6 + ceil(over1 + extra) <= cap
   const double budget = (double)(cap - nt - 6) - over1 - 1.0;
-  if (!std::isfinite(C) || !std::isfinite(budget) || budget < 1.0) return FSTAT_OK;
+  if (n < 4 || !std::isfinite(C) || !std::isfinite(budget) || budget < 1.0) return 0;
   const double d_max = C > 0.0 ? budget / C : 4.0;
-  int rc = FSTAT_OK;
-  if (p->sky_h_cap < (size_t)(3 * n)) {
-    if (p->sky_h) (void)hipHostFree(p->sky_h);
-    p->sky_h = nullptr;
-    p->sky_h_cap = 0;
-    if (hipHostMalloc((void**)&p->sky_h, (size_t)(3 * n) * sizeof(double), hipHostMallocDefault) != hipSuccess) {
-      (void)hipGetLastError();
-      return set_err(p, FSTAT_E_NOMEM, "sky vectors: allocation of %lld entries failed", (long long)n);
-    }
-    p->sky_h_cap = (size_t)(3 * n);
-  }
-  rc = ensure_pinned_pair(p, &p->pairs_d, &p->pairs_h, &p->pairs_cap, (size_t)n, "sky pairs");
-  if (rc) return rc;
-  hipError_t e = hipMemcpyAsync(p->sky_h, wu->sky, (size_t)(3 * n) * sizeof(double), hipMemcpyDeviceToHost, st);
-  if (e == hipSuccess) e = hipStreamSynchronize(st);
-  if (e != hipSuccess) return hip_err(p, e, "sky vector copy");
-  const double* sk = p->sky_h;
   const double h = sqrt(4.0 * M_PI / (double)n);           // grid spacing
   const int64_t n_band = std::max<int64_t>(1, (int64_t)ceil(2.0 / h));
   std::vector<std::pair<std::pair<int64_t, double>, int64_t>> key((size_t)n);
@@ -853,24 +831,60 @@ int prepare_pairs(fstat_plan* p, const fstat_wu* wu, WuDev& v, Tile& t, hipStrea
       const int64_t b = key[(size_t)q + 1].second;
       const double d = dist(a, b);
       if (d <= d_max) {
-        p->pairs_h[np++] = make_int2((int)a, (int)b);
+        out[np++] = make_int2((int)a, (int)b);
         worst = std::max(worst, d);
         paired += 2;
         q += 2;
         continue;
       }
     }
-    p->pairs_h[np++] = make_int2((int)a, (int)a);
+    out[np++] = make_int2((int)a, (int)a);
     ++q;
   }
-  if (2 * paired < n) return FSTAT_OK;
   const double width = nt + 6.0 + ceil(over1 + worst * C);
-  if (!(width <= cap)) return FSTAT_OK;
+  if (2 * paired < n || !(width <= cap)) return 0;
+  *n_pairs = np;
+  return (int)width & ~3;
+}
+
+// Sky points of a single-unit tile of 8 spindowns per thread with ranges of
+// at most 8 per thread (FP32 coefficients, 256 threads, four waves), paired
+// by make_pairs after this unit's geometry pass; sets v.sky_pairs, v.n_pairs
+// and t.pair_seg, or leaves one sky point per tile.  Waits for the stream
+// (idle after the band check).
+int prepare_pairs(fstat_plan* p, const fstat_wu* wu, WuDev& v, Tile& t, hipStream_t st) {
+  v.sky_pairs = nullptr;
+  v.n_pairs = 0;
+  t.pair_seg = 0;
+  bool small = std::all_of(t.fd_split, t.fd_split + fstat::kSplitSizes, [](int32_t x) { return x == 0; });
+  for (int i = 0; i < fstat::kSplitSizes; ++i) small = small || (fstat::split_nfd(i) <= 8 && t.fd_split[i] > 0);
+  if (resolved_kernel(p) != fstat::KERNEL_INTERP || coef16(p) || t.nf_reg != 8 || t.threads != fstat::kThreads ||
+      t.chunk < 4 || !small || wu->n_sky < 4 || p->force_seg > 0)
+    return FSTAT_OK;
+  const int64_t n = wu->n_sky;
+  if (p->sky_h_cap < (size_t)(3 * n)) {
+    if (p->sky_h) (void)hipHostFree(p->sky_h);
+    p->sky_h = nullptr;
+    p->sky_h_cap = 0;
+    if (hipHostMalloc((void**)&p->sky_h, (size_t)(3 * n) * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      return set_err(p, FSTAT_E_NOMEM, "sky vectors: allocation of %lld entries failed", (long long)n);
+    }
+    p->sky_h_cap = (size_t)(3 * n);
+  }
+  int rc = ensure_pinned_pair(p, &p->pairs_d, &p->pairs_h, &p->pairs_cap, (size_t)n, "sky pairs");
+  if (rc) return rc;
+  hipError_t e = hipMemcpyAsync(p->sky_h, wu->sky, (size_t)(3 * n) * sizeof(double), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_err(p, e, "sky vector copy");
+  int64_t np = 0;
+  const int width = make_pairs(wu, *p->status_h, p->sky_h, p->pairs_h, &np);
+  if (!width) return FSTAT_OK;
   e = hipMemcpyAsync(p->pairs_d, p->pairs_h, (size_t)np * sizeof(int2), hipMemcpyHostToDevice, st);
   if (e != hipSuccess) return hip_err(p, e, "sky pair upload");
   v.sky_pairs = p->pairs_d;
   v.n_pairs = np;
-  t.pair_seg = (int)width & ~3;
+  t.pair_seg = width;
   return FSTAT_OK;
 }
 
@@ -939,8 +953,9 @@ int batch_interp(fstat_plan* p, const fstat_wu* wus, int n, const fstat_out* out
   rc = ensure_pinned_pair(p, &p->bstat_d, &p->bstat_h, &p->bstat_cap, (size_t)n, "batch status");
   if (rc) return rc;
   // per group: one entry per unit and up to one demodulation entry per unit
-  // and block size
-  constexpr int kEnts = 1 + fstat::kSplitSizes;
+  // and table (block size, one or two sky points per tile)
+  constexpr int NS = fstat::kSplitSizes, NC = 2 * NS;
+  constexpr int kEnts = 1 + NC;
   rc = ensure_pinned_pair(p, &p->ents_d, &p->ents_h, &p->ents_cap, kEnts * (size_t)n, "work-unit table");
   if (rc) return rc;
   for (int k = 0; k < n; ++k) {
@@ -949,8 +964,7 @@ int batch_interp(fstat_plan* p, const fstat_wu* wus, int n, const fstat_out* out
   }
   if (!p->counter) {               // the per-XCD tile queues of the launch of each block size
     size_t have = 0;
-    rc = dev_alloc(p, (void**)&p->counter, &have, fstat::kSplitSizes * fstat::kXcds * sizeof(unsigned long long),
-                   "tile counters");
+    rc = dev_alloc(p, (void**)&p->counter, &have, NC * fstat::kXcds * sizeof(unsigned long long), "tile counters");
     if (rc) return rc;
   }
   bool any_top = false;
@@ -970,10 +984,30 @@ int batch_interp(fstat_plan* p, const fstat_wu* wus, int n, const fstat_out* out
     if (rc) return rc;
   }
   const unsigned sizes = batch_sizes(p, bt);
-  for (int i = 0; i < fstat::kSplitSizes; ++i) {
-    const int nfd = fstat::split_nfd(i);
-    if (!((sizes >> nfd) & 1u) || p->batch_grid[i][0]) continue;
-    for (int sf = 0; sf < 2; ++sf) p->batch_grid[i][sf] = fstat::interp_batch_grid(coef16(p), nfd, sf == 0);
+  // tiles of two sky points: FP32 coefficients, ranges of at most 8 per thread
+  const bool pairing = !coef16(p) && p->force_seg <= 0;
+  for (int c = 0; c < NC; ++c) {
+    const int nfd = fstat::split_nfd(c % NS), nsky = 1 + c / NS;
+    if (!((sizes >> nfd) & 1u) || (nsky == 2 && (!pairing || nfd > 8)) || p->batch_grid[c][0]) continue;
+    for (int sf = 0; sf < 2; ++sf) p->batch_grid[c][sf] = fstat::interp_batch_grid(coef16(p), nfd, sf == 0, nsky);
+  }
+  // sky vectors and pair tables, at each unit's offset in the batch
+  std::vector<int64_t> sky_off(n + 1, 0);
+  for (int k = 0; k < n; ++k) sky_off[k + 1] = sky_off[k] + wus[k].n_sky;
+  if (pairing) {
+    if (p->sky_h_cap < (size_t)(3 * sky_off[n])) {
+      if (p->sky_h) (void)hipHostFree(p->sky_h);
+      p->sky_h = nullptr;
+      p->sky_h_cap = 0;
+      if (hipHostMalloc((void**)&p->sky_h, (size_t)(3 * sky_off[n]) * sizeof(double), hipHostMallocDefault) !=
+          hipSuccess) {
+        (void)hipGetLastError();
+        return set_err(p, FSTAT_E_NOMEM, "sky vectors: allocation of %lld entries failed", (long long)sky_off[n]);
+      }
+      p->sky_h_cap = (size_t)(3 * sky_off[n]);
+    }
+    rc = ensure_pinned_pair(p, &p->pairs_d, &p->pairs_h, &p->pairs_cap, (size_t)sky_off[n], "sky pairs");
+    if (rc) return rc;
   }
   // every work unit is checked before anything is demodulated
   if (groups.size() > 1) {
@@ -1029,10 +1063,10 @@ int batch_interp(fstat_plan* p, const fstat_wu* wus, int n, const fstat_out* out
       blocks += fstat::coef_blocks(v);
       sfts += wus[k].n_sft;
     }
-    constexpr int NS = fstat::kSplitSizes;
-    int mc[NS] = {}, off[NS] = {};
-    int64_t tiles[NS] = {};
-    bool fast[NS];                         // every entry of a table holds its windows in the slice
+    // tables c = i + NS (nsky - 1): block size split_nfd(i), nsky sky points per tile
+    int mc[NC] = {}, off[NC] = {};
+    int64_t tiles[NC] = {};
+    bool fast[NC];                         // every entry of a table holds its windows in the slice
     std::vector<FdSplit> splits(m);
     for (int q = 0; q < m; ++q) {
       const int k = order[q];
@@ -1045,13 +1079,43 @@ int batch_interp(fstat_plan* p, const fstat_wu* wus, int n, const fstat_out* out
       }
       splits[q] = split_spindowns(wus[k].n_fd, sz);
     }
-    int ne = m;
-    for (int i = 0; i < NS; ++i) {
-      const int nfd = fstat::split_nfd(i);
-      off[i] = ne;
-      fast[i] = true;
+    // sky pairs (make_pairs) of the units with ranges of at most 8 per thread
+    std::vector<int> pw(m, 0);
+    std::vector<int64_t> pn(m, 0);
+    if (pairing) {
+      std::vector<int> cand;
       for (int q = 0; q < m; ++q) {
         const int k = order[q];
+        bool small = false;
+        for (int i = 0; i < NS; ++i) small = small || (fstat::split_nfd(i) <= 8 && splits[q].n[i] > 0);
+        if (!small || wus[k].n_sky < 4) continue;
+        hipError_t e = hipMemcpyAsync(p->sky_h + 3 * sky_off[k], wus[k].sky, (size_t)(3 * wus[k].n_sky) * sizeof(double),
+                                      hipMemcpyDeviceToHost, st);
+        if (e != hipSuccess) return hip_err(p, e, "sky vector copy");
+        cand.push_back(q);
+      }
+      if (!cand.empty()) {
+        hipError_t e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return hip_err(p, e, "sky vector copy");
+        for (int q : cand) {
+          const int k = order[q];
+          pw[q] = make_pairs(&wus[k], p->bstat_h[k], p->sky_h + 3 * sky_off[k], p->pairs_h + sky_off[k], &pn[q]);
+          if (!pw[q]) continue;
+          e = hipMemcpyAsync(p->pairs_d + sky_off[k], p->pairs_h + sky_off[k], (size_t)pn[q] * sizeof(int2),
+                             hipMemcpyHostToDevice, st);
+          if (e != hipSuccess) return hip_err(p, e, "sky pair upload");
+        }
+      }
+    }
+    int ne = m;
+    for (int c = 0; c < NC; ++c) {
+      const int i = c % NS, nsky = 1 + c / NS, nfd = fstat::split_nfd(i);
+      off[c] = ne;
+      fast[c] = true;
+      for (int q = 0; q < m; ++q) {
+        const int k = order[q];
+        const bool paired = pw[q] > 0 && nfd <= 8;
+        if ((nsky == 2) != paired) continue;
         int64_t lo = 0;
         for (int j = 0; j < i; ++j) lo += splits[q].n[j];
         const int64_t hi = lo + splits[q].n[i];
@@ -1062,18 +1126,25 @@ int batch_interp(fstat_plan* p, const fstat_wu* wus, int n, const fstat_out* out
         e.fd_begin = (int32_t)lo;
         e.fd_end = (int32_t)hi;
         bool fits = false;
-        e.seg = interp_seg_tau(&wus[k], nfd, fstat::kThreads, coef16(p), status_tau(p->bstat_h[k]),
-                               status_p(p->bstat_h[k]), &fits);
+        if (paired) {                    // the pair's width holds both points' windows by construction
+          e.w.sky_pairs = p->pairs_d + sky_off[k];
+          e.w.n_pairs = pn[q];
+          e.seg = pw[q];
+          fits = true;
+        } else {
+          e.seg = interp_seg_tau(&wus[k], nfd, fstat::kThreads, coef16(p), status_tau(p->bstat_h[k]),
+                                 status_p(p->bstat_h[k]), &fits);
+        }
         if (p->force_seg > 0) {          // fault injection: a slice narrower than the windows need
           e.seg = p->force_seg;
           fits = true;
         }
         e.fast = fits ? 1 : 0;
-        fast[i] = fast[i] && fits;
-        e.n_tiles = fstat::interp_tiles(e.w, nfd, lo, hi);
-        e.tile_begin = tiles[i];
-        tiles[i] += e.n_tiles;
-        ++mc[i];
+        fast[c] = fast[c] && fits;
+        e.n_tiles = fstat::interp_tiles(e.w, nfd, lo, hi, nsky);
+        e.tile_begin = tiles[c];
+        tiles[c] += e.n_tiles;
+        ++mc[c];
       }
     }
     fstat::BatchEntry* ed = p->ents_d + kEnts * (size_t)g.first;
@@ -1090,20 +1161,20 @@ int batch_interp(fstat_plan* p, const fstat_wu* wus, int n, const fstat_out* out
     const int64_t n_blocks = (wus[order[0]].n_sft + B - 1) / B;
     std::vector<int64_t> bplan;             // per block and table: entries and tiles
     for (int64_t b = 0; b < n_blocks; ++b) {
-      for (int i = 0; i < NS; ++i) {
-        int c = 0;
-        while (c < mc[i] && eh[off[i] + c].w.n_sft > b * B) ++c;
-        bplan.insert(bplan.end(), {c, c < mc[i] ? eh[off[i] + c].tile_begin : tiles[i]});
+      for (int c = 0; c < NC; ++c) {
+        int x = 0;
+        while (x < mc[c] && eh[off[c] + x].w.n_sft > b * B) ++x;
+        bplan.insert(bplan.end(), {x, x < mc[c] ? eh[off[c] + x].tile_begin : tiles[c]});
       }
     }
     auto launch_demod_blocks = [&](hipStream_t s, bool counted) -> int {
       for (int64_t b = 0; b < n_blocks; ++b) {
-        for (int i = 0; i < NS; ++i) {
-          const int64_t* q = &bplan[2 * (NS * b + i)];
+        for (int c = 0; c < NC; ++c) {
+          const int64_t* q = &bplan[2 * (NC * b + c)];
           if (q[0] == 0) continue;
-          hipError_t ek = fstat::launch_interp_batch(ed + off[i], (int)q[0], q[1], p->counter + i * fstat::kXcds,
-                                                     bt.chunk, p->batch_grid[i][fast[i] ? 0 : 1], c16,
-                                                     fstat::split_nfd(i), fast[i],
+          hipError_t ek = fstat::launch_interp_batch(ed + off[c], (int)q[0], q[1], p->counter + c * fstat::kXcds,
+                                                     bt.chunk, p->batch_grid[c][fast[c] ? 0 : 1], c16,
+                                                     fstat::split_nfd(c % NS), fast[c], 1 + c / NS,
                                                      b * B, (b + 1) * B, s);
           const int r = counted ? check_launch(p, ek, "batch kernel")
                                 : (ek == hipSuccess ? FSTAT_OK : hip_err(p, ek, "graph capture"));
@@ -1133,7 +1204,7 @@ int batch_interp(fstat_plan* p, const fstat_wu* wus, int n, const fstat_out* out
     // everything a captured graph holds by value: addresses, counts, kernel variants
     std::vector<int64_t> sig = {(int64_t)(intptr_t)ed, (int64_t)(intptr_t)gcand, (int64_t)(intptr_t)gcount,
                                 m, blocks, sfts, max_top_k, n_blocks, B, bt.chunk};
-    for (int i = 0; i < NS; ++i) sig.insert(sig.end(), {mc[i], off[i], tiles[i], fast[i] ? 1 : 0});
+    for (int c = 0; c < NC; ++c) sig.insert(sig.end(), {mc[c], off[c], tiles[c], fast[c] ? 1 : 0});
     sig.insert(sig.end(), bplan.begin(), bplan.end());
     auto it = p->graphs.find(sig);
     if (it == p->graphs.end()) {

@@ -68,7 +68,7 @@ struct Tile {
   int32_t threads;  // interp: work-group size, 64 or 256
   int32_t fast;     // interp: 1 if the slice holds every window of every SFT (no slice width was capped), so
                     // the kernel without the global-memory fallback may run
-  int32_t pair_seg; // interp: > 0: the range of 8 spindowns per thread runs tiles of two sky points
+  int32_t pair_seg; // interp: > 0: the ranges of at most 8 spindowns per thread run tiles of two sky points
                     // (WuDev::sky_pairs) with this slice width
   // interp with nf_reg 8, filled by the host for the work unit: the
   // spindowns run as consecutive ranges of fd_split[i] spindowns,
@@ -165,19 +165,22 @@ hipError_t launch_geometry(const WuDev& w, GeoStatus* status, hipStream_t s);
 hipError_t launch_coef(const WuDev& w, hipStream_t s);
 hipError_t launch_demod(const WuDev& w, const Tile& t, int kernel, hipStream_t s);
 int interp_launches(const WuDev& w, const Tile& t);
-int64_t interp_tiles(const WuDev& w, int nfd, int64_t fd0, int64_t fd1);
+// Tiles of spindowns [fd0, fd1) at nfd per thread and nsky sky points per tile.
+int64_t interp_tiles(const WuDev& w, int nfd, int64_t fd0, int64_t fd1, int nsky);
 int64_t coef_blocks(const WuDev& w);
 hipError_t launch_coef_batch(const BatchEntry* ents_dev, int n_ent, int64_t total_blocks, bool c16, hipStream_t s);
 // SFTs [al0, al1) of the first n_ent entries (each clipped to its unit's
 // SFT count; every one of them must have more than al0 SFTs).
 // Tiles are dealt to kXcds queues (counters[0, kXcds)) in chunks of `chunk`.
 // The batched kernel exists for split_nfd(i) spindowns per thread, i <
-// kSplitSizes (with FP16 coefficients for 8 and 4 only); other sizes are
-// refused with hipErrorInvalidValue.
+// kSplitSizes (with FP16 coefficients for 8 and 4 only), with one sky point
+// per tile, and for 4 to 8 (FP32 coefficients) with tiles of two
+// (nsky = 2, the entries' WuDev::sky_pairs); other shapes are refused with
+// hipErrorInvalidValue.
 hipError_t launch_interp_batch(const BatchEntry* ents_dev, int n_ent, int64_t total_tiles,
                                unsigned long long* counters, int64_t chunk, int grid, bool c16, int nfd, bool fast,
-                               int64_t al0, int64_t al1, hipStream_t s);
-int interp_batch_grid(bool c16, int nfd, bool fast);
+                               int nsky, int64_t al0, int64_t al1, hipStream_t s);
+int interp_batch_grid(bool c16, int nfd, bool fast, int nsky);
 hipError_t launch_bins(const WuDev& w, int64_t n, const int32_t* i_sky, const int32_t* i_fd, const int32_t* i_f,
                        const int32_t* i_sft, int64_t* kstar, double* kappa, double* phi_frac, hipStream_t s);
 int interp_max_seg(int threads, bool c16);

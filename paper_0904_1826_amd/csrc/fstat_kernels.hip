@@ -1053,13 +1053,19 @@ __global__ __launch_bounds__(NT, MINW) void demod_interp_kernel(WuDev w, int W, 
 // host runs the SFT loop as a sequence of such launches (Fa, Fb carried in
 // `acc`), because over thousands of SFTs the work-groups sharing a slice
 // drift apart and L2 no longer holds it for all of them.
-template <int NFD, bool C16, bool SAFE>
-__global__ __launch_bounds__(kThreads, NFD == 16 ? 3 : NFD == 8 ? (C16 ? 5 : 4) : (NFD >= 5 ? 4 : 3)) void demod_interp_batch_kernel(
+// Waves per SIMD the registers of a batched specialisation leave room for.
+__host__ __device__ constexpr int batch_minw(int nfd, bool c16, int nsky) {
+  return nfd == 16 ? 3 : nsky == 2 ? 3 : nfd == 8 ? (c16 ? 5 : 4) : (nfd >= 5 ? 4 : 3);
+}
+
+template <int NFD, bool C16, bool SAFE, int NSKY = 1>
+__global__ __launch_bounds__(kThreads, batch_minw(NFD, C16, NSKY)) void demod_interp_batch_kernel(
     const BatchEntry* __restrict__ ents, int n_ent, int64_t total_tiles, unsigned long long* counters, int64_t chunk,
     int64_t al0, int64_t al1) {
   using F = SliceForm<kThreads, C16>;
-  constexpr int S = C16 ? 16 : 8;                  // per-SFT values per group: four work-groups' LDS fits a CU
-  __shared__ GroupMeta<NFD, S> meta[2];
+  // per-SFT values per group: four work-groups' LDS fits a CU
+  constexpr int S = C16 ? 16 : (NSKY == 2 && NFD <= 4 ? 4 : 8);
+  __shared__ GroupMeta<NFD, S, NSKY> meta[2];
   __shared__ float4 cbuf0[F::rows * F::cap];
   __shared__ float4 cbuf1[F::rows * F::cap];
   __shared__ long long next;
@@ -1103,8 +1109,10 @@ __global__ __launch_bounds__(kThreads, NFD == 16 ? 3 : NFD == 8 ? (C16 ? 5 : 4) 
     const int W = ents[lo].seg;
     const int64_t local = tile - ents[lo].tile_begin;
     const int64_t al_end = w.n_sft < al1 ? w.n_sft : al1;
-    interp_tile<NFD, S, 4, kThreads, C16, SAFE>(w, W, local, al0, al_end, cbuf0, cbuf1, meta, ents[lo].fd_begin,
-                                           ents[lo].fd_end);
+    // tiles of two sky points keep two slots' coefficients in flight (four
+    // with one): the queue loop's registers on top of 2 NFD accumulator sets
+    interp_tile<NFD, S, NSKY == 2 ? 2 : 4, kThreads, C16, SAFE, NSKY>(w, W, local, al0, al_end, cbuf0, cbuf1, meta,
+                                                                     ents[lo].fd_begin, ents[lo].fd_end);
     __syncthreads();                                 // LDS free for the next tile
   }
 }
@@ -1281,24 +1289,33 @@ hipError_t launch_coef_batch(const BatchEntry* ents_dev, int n_ent, int64_t tota
   return hipGetLastError();
 }
 
-int64_t interp_tiles(const WuDev& w, int nfd, int64_t fd0, int64_t fd1) {
-  return ((w.n_f + kThreads - 1) / kThreads) * ((fd1 - fd0 + nfd - 1) / nfd) * w.n_sky;
+int64_t interp_tiles(const WuDev& w, int nfd, int64_t fd0, int64_t fd1, int nsky) {
+  return ((w.n_f + kThreads - 1) / kThreads) * ((fd1 - fd0 + nfd - 1) / nfd) * (nsky == 2 ? w.n_pairs : w.n_sky);
 }
 
-template <int NFD, bool C16, bool SAFE>
+template <int NFD, bool C16, bool SAFE, int NSKY = 1>
 static int batch_grid_t(int cus) {
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, demod_interp_batch_kernel<NFD, C16, SAFE>, kThreads, 0) !=
-          hipSuccess ||
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, demod_interp_batch_kernel<NFD, C16, SAFE, NSKY>,
+                                                   kThreads, 0) != hipSuccess ||
       per_cu < 1)
     per_cu = 1;
   return per_cu * cus;
 }
 
-int interp_batch_grid(bool c16, int nfd, bool fast) {
+int interp_batch_grid(bool c16, int nfd, bool fast, int nsky) {
   int dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     cus = 256;
+  if (nsky == 2 && !c16) {
+    switch (nfd) {
+      case 8: return fast ? batch_grid_t<8, false, false, 2>(cus) : batch_grid_t<8, false, true, 2>(cus);
+      case 7: return fast ? batch_grid_t<7, false, false, 2>(cus) : batch_grid_t<7, false, true, 2>(cus);
+      case 6: return fast ? batch_grid_t<6, false, false, 2>(cus) : batch_grid_t<6, false, true, 2>(cus);
+      case 5: return fast ? batch_grid_t<5, false, false, 2>(cus) : batch_grid_t<5, false, true, 2>(cus);
+      default: return fast ? batch_grid_t<4, false, false, 2>(cus) : batch_grid_t<4, false, true, 2>(cus);
+    }
+  }
   if (c16) {
     if (nfd == 8) return fast ? batch_grid_t<8, true, false>(cus) : batch_grid_t<8, true, true>(cus);
     return fast ? batch_grid_t<4, true, false>(cus) : batch_grid_t<4, true, true>(cus);
@@ -1315,10 +1332,11 @@ int interp_batch_grid(bool c16, int nfd, bool fast) {
 
 hipError_t launch_interp_batch(const BatchEntry* ents_dev, int n_ent, int64_t total_tiles,
                                unsigned long long* counters, int64_t chunk, int grid, bool c16, int nfd, bool fast,
-                               int64_t al0, int64_t al1, hipStream_t st) {
+                               int nsky, int64_t al0, int64_t al1, hipStream_t st) {
   if (n_ent <= 0 || total_tiles <= 0) return hipSuccess;
   if (al0 < 0 || al1 <= al0 || chunk < 1) return hipErrorInvalidValue;
   if (c16 ? (nfd != 8 && nfd != 4) : ((nfd < 4 || nfd > 8) && nfd != 16)) return hipErrorInvalidValue;
+  if (nsky != 1 && (nsky != 2 || c16 || nfd > 8)) return hipErrorInvalidValue;
   // kernel, not memset: safe under capture
   hipError_t e = launch_fill_int((int*)counters, 0, 2 * kXcds, st);
   if (e != hipSuccess) return e;
@@ -1328,7 +1346,22 @@ hipError_t launch_interp_batch(const BatchEntry* ents_dev, int n_ent, int64_t to
                      chunk, al0, al1)
 #define FSTAT_BATCH_LAUNCH2(N, C) \
   do { if (fast) FSTAT_BATCH_LAUNCH(N, C, false); else FSTAT_BATCH_LAUNCH(N, C, true); } while (0)
-  if (c16) {
+#define FSTAT_BATCH_LAUNCH_P(N) \
+  do { \
+    if (fast) hipLaunchKernelGGL((demod_interp_batch_kernel<N, false, false, 2>), g, b, 0, st, ents_dev, n_ent, \
+                                 total_tiles, counters, chunk, al0, al1); \
+    else hipLaunchKernelGGL((demod_interp_batch_kernel<N, false, true, 2>), g, b, 0, st, ents_dev, n_ent, \
+                            total_tiles, counters, chunk, al0, al1); \
+  } while (0)
+  if (nsky == 2) {
+    switch (nfd) {
+      case 8: FSTAT_BATCH_LAUNCH_P(8); break;
+      case 7: FSTAT_BATCH_LAUNCH_P(7); break;
+      case 6: FSTAT_BATCH_LAUNCH_P(6); break;
+      case 5: FSTAT_BATCH_LAUNCH_P(5); break;
+      default: FSTAT_BATCH_LAUNCH_P(4); break;
+    }
+  } else if (c16) {
     if (nfd == 8) FSTAT_BATCH_LAUNCH2(8, true);
     else FSTAT_BATCH_LAUNCH2(4, true);
   } else {
@@ -1341,6 +1374,7 @@ hipError_t launch_interp_batch(const BatchEntry* ents_dev, int n_ent, int64_t to
       default: FSTAT_BATCH_LAUNCH2(4, false); break;
     }
   }
+#undef FSTAT_BATCH_LAUNCH_P
 #undef FSTAT_BATCH_LAUNCH2
 #undef FSTAT_BATCH_LAUNCH
   return hipGetLastError();
@@ -1423,16 +1457,29 @@ static hipError_t launch_interp_range(const WuDev& w, const Tile& t, hipStream_t
                    : w3         ? launch_interp_t<8, 16, 3, 4, kThreads, false>(w, t, st, fd0, fd1)
                                 : launch_interp_t<8, 16, 2, 4, kThreads, false>(w, t, st, fd0, fd1);
     // 16 and 7 to 5: ranges of a split 8-spindown tile (three waves per SIMD
-    // for 16, four for the others)
+    // for 16, four for the others); ranges of 4 to 7 with tiles of two sky
+    // points (t.pair_seg > 0) have their own specialisations
     case 16: return t.fast ? launch_interp_t<16, 8, 3, 4, kThreads, false, false>(w, t, st, fd0, fd1)
                            : launch_interp_t<16, 8, 3, 4, kThreads, false>(w, t, st, fd0, fd1);
-    case 7: return t.fast ? launch_interp_t<7, 8, 4, 4, kThreads, false, false>(w, t, st, fd0, fd1)
+    case 7: if (t.pair_seg > 0)
+              return t.fast ? launch_interp_t<7, 8, 3, 4, kThreads, false, false, 2>(w, t, st, fd0, fd1)
+                            : launch_interp_t<7, 8, 3, 4, kThreads, false, true, 2>(w, t, st, fd0, fd1);
+            return t.fast ? launch_interp_t<7, 8, 4, 4, kThreads, false, false>(w, t, st, fd0, fd1)
                           : launch_interp_t<7, 8, 4, 4, kThreads, false>(w, t, st, fd0, fd1);
-    case 6: return t.fast ? launch_interp_t<6, 8, 4, 4, kThreads, false, false>(w, t, st, fd0, fd1)
+    case 6: if (t.pair_seg > 0)
+              return t.fast ? launch_interp_t<6, 8, 3, 4, kThreads, false, false, 2>(w, t, st, fd0, fd1)
+                            : launch_interp_t<6, 8, 3, 4, kThreads, false, true, 2>(w, t, st, fd0, fd1);
+            return t.fast ? launch_interp_t<6, 8, 4, 4, kThreads, false, false>(w, t, st, fd0, fd1)
                           : launch_interp_t<6, 8, 4, 4, kThreads, false>(w, t, st, fd0, fd1);
-    case 5: return t.fast ? launch_interp_t<5, 8, 4, 4, kThreads, false, false>(w, t, st, fd0, fd1)
+    case 5: if (t.pair_seg > 0)
+              return t.fast ? launch_interp_t<5, 8, 3, 4, kThreads, false, false, 2>(w, t, st, fd0, fd1)
+                            : launch_interp_t<5, 8, 3, 4, kThreads, false, true, 2>(w, t, st, fd0, fd1);
+            return t.fast ? launch_interp_t<5, 8, 4, 4, kThreads, false, false>(w, t, st, fd0, fd1)
                           : launch_interp_t<5, 8, 4, 4, kThreads, false>(w, t, st, fd0, fd1);
-    case 4: return w3 ? (t.fast ? launch_interp_t<4, 16, 3, 4, kThreads, false, false>(w, t, st, fd0, fd1)
+    case 4: if (t.pair_seg > 0)        // 4 groups of per-SFT values: four work-groups' LDS fits a CU
+              return t.fast ? launch_interp_t<4, 4, 4, 4, kThreads, false, false, 2>(w, t, st, fd0, fd1)
+                            : launch_interp_t<4, 4, 4, 4, kThreads, false, true, 2>(w, t, st, fd0, fd1);
+            return w3 ? (t.fast ? launch_interp_t<4, 16, 3, 4, kThreads, false, false>(w, t, st, fd0, fd1)
                                 : launch_interp_t<4, 16, 3, 4, kThreads, false>(w, t, st, fd0, fd1))
                       : launch_interp_t<4, 16, 2, 4, kThreads, false>(w, t, st, fd0, fd1);
     case 2: return launch_interp_t<2, 16, 3, 4, kThreads, false>(w, t, st, fd0, fd1);
@@ -1443,9 +1490,10 @@ static hipError_t launch_interp_range(const WuDev& w, const Tile& t, hipStream_t
 
 // The spindowns in blocks of nf_reg, or, with a split (Tile::fd_split), as
 // consecutive ranges with 16, 8, 7, ..., 4 per thread, one launch sequence
-// per range (t.fast covers every range's slice).
+// per range (t.fast covers every range's slice); ranges of at most 8 per
+// thread run tiles of two sky points when the host paired them.
 static hipError_t launch_interp(const WuDev& w, const Tile& t, hipStream_t st) {
-  // the 8-spindown range may run tiles of two sky points (t.pair_seg)
+  // ranges of at most 8 spindowns per thread may run tiles of two sky points (t.pair_seg)
   const bool pairs = t.pair_seg > 0 && w.sky_pairs && w.n_pairs > 0 && !w.coef16 && t.threads == kThreads;
   int64_t total = 0;
   for (int i = 0; i < kSplitSizes; ++i) total += t.fd_split[i] > 0 ? t.fd_split[i] : 0;
@@ -1462,7 +1510,7 @@ static hipError_t launch_interp(const WuDev& w, const Tile& t, hipStream_t st) {
     if (t.fd_split[i] <= 0) continue;
     Tile ti = t;
     ti.nf_reg = split_nfd(i);
-    const bool pr = pairs && ti.nf_reg == 8;
+    const bool pr = pairs && ti.nf_reg <= 8;
     ti.seg = pr ? t.pair_seg : t.seg_split[i];
     ti.pair_seg = pr ? t.pair_seg : 0;
     if (ti.nf_reg == 4 || ti.nf_reg == 16) ti.chunk = t.chunk > 3 ? 3 : t.chunk;
