@@ -475,9 +475,10 @@ int interp_seg(const fstat_plan* p, const fstat_wu* w, int nfd, int threads, boo
 
 Tile default_tile(const fstat_plan* p, const fstat_wu* w) {
   if (resolved_kernel(p) == fstat::KERNEL_INTERP) {
-    // 5 or more spindowns: tiles of 8 per thread, which complete_tile splits
-    // into blocks of 4 to 8 (split_spindowns)
-    const int nfd = w->n_fd >= 5 ? 8 : (w->n_fd >= 3 ? 4 : (w->n_fd >= 2 ? 2 : 1));
+    // 3 or more spindowns: tiles of 8 per thread, which complete_tile splits
+    // into blocks of 16 and 4 to 8 (split_spindowns; 3 or 4 spindowns: one
+    // block of 4, which may take tiles of two sky points)
+    const int nfd = w->n_fd >= 3 ? 8 : (w->n_fd >= 2 ? 2 : 1);
     // measured on the work-unit-shaped case: 8 spindowns per thread with room
     // for 4 waves per SIMD (5 with FP16 coefficients, whose slices and packed
     // FP16 polynomials take fewer registers and less LDS) is fastest.  Splitting the SFT loop into launches
@@ -497,15 +498,18 @@ Tile default_tile(const fstat_plan* p, const fstat_wu* w) {
 // spindowns run split_nfd(i) per thread, as consecutive ranges (largest
 // blocks first), each range's last block possibly partial.  The split
 // minimises the lanes computed weighted by the time per lane of each block
-// size, measured with the batched kernel on the work-unit-shaped case with
-// 840 (832 for 16) spindowns, every size dividing it, identical outputs: 16:
-// 0.890, 8: 1, 7: 1.072, 6: 1.136, 5: 1.259, 4: 1.415 (more spindowns per
-// thread use each staged slice and each thread's per-SFT work for more
-// pairs).  So 5 spindowns run as one block of 5 rather than a partial 8,
-// 12 as 6 + 6 rather than 8 + 4, 32 as 16 + 16 and 13 as one partial block
-// of 16 (8 + 5 without 16).
-// All but the last two to three blocks' worth run in blocks of the largest
-// allowed size (the cheapest per lane); the tail is split exactly by
+// size (more spindowns per thread use each staged slice and each thread's
+// per-SFT work for more pairs).  Measured on the work-unit-shaped case,
+// relative to 8 per thread with one sky point per tile: with one sky point,
+// on the batched kernel with 840 (832 for 16) spindowns, every size dividing
+// it, identical outputs: 16: 0.890, 8: 1, 7: 1.072, 6: 1.136, 5: 1.259, 4:
+// 1.415; with tiles of two sky points (`paired`, the ranges of at most 8),
+// single-unit calls of 2000 sky points with that many spindowns: 8: 0.967,
+// 7: 0.996, 6: 1.034, 5: 1.093, 4: 1.102.  So without pairs 5 spindowns run
+// as one block of 5 rather than a partial 8, 12 as 6 + 6 rather than 8 + 4,
+// 32 as 16 + 16 and 13 as one partial block of 16; with pairs 13 runs as
+// 8 + 5.  All but the last two to three blocks' worth run in blocks of the
+// largest allowed size (the cheapest per lane); the tail is split exactly by
 // dynamic programming.
 struct FdSplit {
   int64_t n[fstat::kSplitSizes] = {};
@@ -513,9 +517,12 @@ struct FdSplit {
 
 int split_index(int b) { return b == 16 ? 0 : 9 - b; }
 
-FdSplit split_spindowns(int64_t nf, unsigned sizes) {
-  static const double kLaneCost[17] = {0.0, 0.0, 0.0, 0.0, 1.415, 1.259, 1.136, 1.072, 1.0,
-                                       0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.890};
+FdSplit split_spindowns(int64_t nf, unsigned sizes, bool paired = false) {
+  static const double kOne[17] = {0.0, 0.0, 0.0, 0.0, 1.415, 1.259, 1.136, 1.072, 1.0,
+                                  0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.890};
+  static const double kPaired[17] = {0.0, 0.0, 0.0, 0.0, 1.102, 1.093, 1.034, 0.996, 0.967,
+                                     0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.890};
+  const double* kLaneCost = paired ? kPaired : kOne;
   static const int kSizes[] = {16, 8, 7, 6, 5, 4};   // larger blocks first: ties take fewer tiles
   constexpr int kTail = 48;
   FdSplit r;
@@ -569,9 +576,10 @@ unsigned single_sizes(const fstat_plan* p, const Tile& t) {
 }
 
 // Slice widths of a tile for this work unit, its spindown split
-// (split_spindowns, when it is anything but one range of nf_reg per thread)
-// and whether the variant without the global-memory path may run.
-Tile complete_tile(const fstat_plan* p, const fstat_wu* w, Tile t) {
+// (split_spindowns, when it is anything but one range of nf_reg per thread,
+// with the costs of paired tiles if `paired`) and whether the variant
+// without the global-memory path may run.
+Tile complete_tile(const fstat_plan* p, const fstat_wu* w, Tile t, bool paired = false) {
   if (resolved_kernel(p) == fstat::KERNEL_INTERP) {
     bool fits = false;
     t.seg = interp_seg(p, w, t.nf_reg, t.threads, &fits);
@@ -583,7 +591,7 @@ Tile complete_tile(const fstat_plan* p, const fstat_wu* w, Tile t) {
       (void)interp_seg(p, w, 16, t.threads, &f16);
       if (!f16) sizes &= ~(1u << 16);
     }
-    const FdSplit sp = split_spindowns(w->n_fd, sizes);
+    const FdSplit sp = split_spindowns(w->n_fd, sizes, paired);
     if (sizes && sp.n[split_index(8)] != w->n_fd) {
       t.fast = 1;
       for (int i = 0; i < fstat::kSplitSizes; ++i) {
@@ -784,7 +792,7 @@ double status_bits(unsigned long long b) {
 //   |n0 - n1| (f_max T |v|max + |fdot|max (|tau|max T |v|max + P_max |r|max))
 // (P = Tdot T = (1 + v.n) T and tau = t - t_ref + r.n, so P0 - P1 = T v.(n0 -
 // n1) and tau0 - tau1 = r.(n0 - n1)), which is added to the spread of one
-// sky point at 8 spindowns per thread (the widest such range).  Sky points
+// sky point over min(n_fd, 8) spindowns (the widest such range).  Sky points
 // are ordered in bands of z of the grid's spacing, alternately by
 // increasing and decreasing longitude, and consecutive points are paired
 // when the pair's slice still fits the LDS capacity; a point without a
@@ -803,7 +811,9 @@ int make_pairs(const fstat_wu* wu, const fstat::GeoStatus& g, const double* sk, 
   const double T = wu->t_sft;
   // bins per unit of |n0 - n1|
   const double C = f_max * T * vmax + fd_max * (max_tau * T * vmax + max_p * rmax);
-  const double spread1 = ((nt - 1.0) * wu->df + fabs(wu->dfdot) * 7.0 * max_tau) * max_p;
+  // the widest range of at most 8 spindowns per thread spans min(n_fd, 8) of them
+  const double fd_span = (double)(std::min<int64_t>(wu->n_fd, 8) - 1);
+  const double spread1 = ((nt - 1.0) * wu->df + fabs(wu->dfdot) * fd_span * max_tau) * max_p;
   const double over1 = spread1 - (nt - 1.0) > 0 ? spread1 - (nt - 1.0) : 0.0;
   // extra bins the pair may add with the width nt + 6 + ceil(over1 + extra) <= cap
   const double budget = (double)(cap - nt - 6) - over1 - 1.0;
@@ -856,10 +866,8 @@ int prepare_pairs(fstat_plan* p, const fstat_wu* wu, WuDev& v, Tile& t, hipStrea
   v.sky_pairs = nullptr;
   v.n_pairs = 0;
   t.pair_seg = 0;
-  bool small = std::all_of(t.fd_split, t.fd_split + fstat::kSplitSizes, [](int32_t x) { return x == 0; });
-  for (int i = 0; i < fstat::kSplitSizes; ++i) small = small || (fstat::split_nfd(i) <= 8 && t.fd_split[i] > 0);
   if (resolved_kernel(p) != fstat::KERNEL_INTERP || coef16(p) || t.nf_reg != 8 || t.threads != fstat::kThreads ||
-      t.chunk < 4 || !small || wu->n_sky < 4 || p->force_seg > 0)
+      t.chunk < 4 || wu->n_sky < 4 || p->force_seg > 0)
     return FSTAT_OK;
   const int64_t n = wu->n_sky;
   if (p->sky_h_cap < (size_t)(3 * n)) {
@@ -880,10 +888,16 @@ int prepare_pairs(fstat_plan* p, const fstat_wu* wu, WuDev& v, Tile& t, hipStrea
   int64_t np = 0;
   const int width = make_pairs(wu, *p->status_h, p->sky_h, p->pairs_h, &np);
   if (!width) return FSTAT_OK;
+  // the split with the costs of paired tiles; pairs serve its ranges of at most 8
+  const Tile tp = complete_tile(p, wu, t, true);
+  bool small = std::all_of(tp.fd_split, tp.fd_split + fstat::kSplitSizes, [](int32_t x) { return x == 0; });
+  for (int i = 0; i < fstat::kSplitSizes; ++i) small = small || (fstat::split_nfd(i) <= 8 && tp.fd_split[i] > 0);
+  if (!small) return FSTAT_OK;
   e = hipMemcpyAsync(p->pairs_d, p->pairs_h, (size_t)np * sizeof(int2), hipMemcpyHostToDevice, st);
   if (e != hipSuccess) return hip_err(p, e, "sky pair upload");
   v.sky_pairs = p->pairs_d;
   v.n_pairs = np;
+  t = tp;
   t.pair_seg = width;
   return FSTAT_OK;
 }
@@ -1067,28 +1081,15 @@ int batch_interp(fstat_plan* p, const fstat_wu* wus, int n, const fstat_out* out
     int mc[NC] = {}, off[NC] = {};
     int64_t tiles[NC] = {};
     bool fast[NC];                         // every entry of a table holds its windows in the slice
-    std::vector<FdSplit> splits(m);
-    for (int q = 0; q < m; ++q) {
-      const int k = order[q];
-      unsigned sz = sizes;
-      if ((sz >> 16) & 1u) {          // 16 per thread only where its wider slice holds every window
-        bool f16 = false;
-        (void)interp_seg_tau(&wus[k], 16, fstat::kThreads, coef16(p), status_tau(p->bstat_h[k]),
-                             status_p(p->bstat_h[k]), &f16);
-        if (!f16) sz &= ~(1u << 16);
-      }
-      splits[q] = split_spindowns(wus[k].n_fd, sz);
-    }
-    // sky pairs (make_pairs) of the units with ranges of at most 8 per thread
+    // sky pairs (make_pairs) of every unit that may use them, then each
+    // unit's spindown split with the costs of its tiles (paired or not)
     std::vector<int> pw(m, 0);
     std::vector<int64_t> pn(m, 0);
     if (pairing) {
       std::vector<int> cand;
       for (int q = 0; q < m; ++q) {
         const int k = order[q];
-        bool small = false;
-        for (int i = 0; i < NS; ++i) small = small || (fstat::split_nfd(i) <= 8 && splits[q].n[i] > 0);
-        if (!small || wus[k].n_sky < 4) continue;
+        if (wus[k].n_sky < 4) continue;
         hipError_t e = hipMemcpyAsync(p->sky_h + 3 * sky_off[k], wus[k].sky, (size_t)(3 * wus[k].n_sky) * sizeof(double),
                                       hipMemcpyDeviceToHost, st);
         if (e != hipSuccess) return hip_err(p, e, "sky vector copy");
@@ -1106,6 +1107,18 @@ int batch_interp(fstat_plan* p, const fstat_wu* wus, int n, const fstat_out* out
           if (e != hipSuccess) return hip_err(p, e, "sky pair upload");
         }
       }
+    }
+    std::vector<FdSplit> splits(m);
+    for (int q = 0; q < m; ++q) {
+      const int k = order[q];
+      unsigned sz = sizes;
+      if ((sz >> 16) & 1u) {          // 16 per thread only where its wider slice holds every window
+        bool f16 = false;
+        (void)interp_seg_tau(&wus[k], 16, fstat::kThreads, coef16(p), status_tau(p->bstat_h[k]),
+                             status_p(p->bstat_h[k]), &f16);
+        if (!f16) sz &= ~(1u << 16);
+      }
+      splits[q] = split_spindowns(wus[k].n_fd, sz, pw[q] > 0);
     }
     int ne = m;
     for (int c = 0; c < NC; ++c) {
