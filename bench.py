@@ -520,12 +520,16 @@ def run_batch(args, torch, P, synth, say):
     torch.cuda.synchronize()
     batch = {"workload": synth.BATCH_NAMES[args.batch].replace("-bf16", ""), "n_wu": len(bws),
              "pairs_per_step": bpairs, "inputs_s": time.time() - t0, "warmup": 1, "replays": args.batch_replays}
-    nfd_mix = {8: 0, 4: 0}
-    for x in bws:
-        rem = x.n_fd % 8
-        lanes8 = x.n_fd if rem > 4 else x.n_fd - rem
-        nfd_mix[8] += x.n_sky * lanes8 * x.n_f * x.n_sft
-        nfd_mix[4] += x.n_sky * (x.n_fd - lanes8) * x.n_f * x.n_sft
+    def nfd_mix(c16):
+        # (template, SFT) pairs per spindown block size, as the library splits
+        # each unit's spindowns (16-blocks allowed; tiles of two sky points
+        # taken for units of at least 4 sky points, which the library pairs
+        # where their grid is dense enough; the pairing changes only the split)
+        mix = {}
+        for x in bws:
+            for b, n in P.fstat_spindown_split(x.n_fd, coef16=c16, allow16=True, paired=x.n_sky >= 4).items():
+                mix[b] = mix.get(b, 0) + x.n_sky * n * x.n_f * x.n_sft
+        return mix
     dmax = max(x.dterms for x in bws)
     # sampled units: most, median and fewest SFTs; sky point 0, first and
     # last spindown, every frequency
@@ -540,8 +544,7 @@ def run_batch(args, torch, P, synth, say):
     ref["templates"] = tm
 
     def timed(storage, c16=False):
-        slots_b = (slots_per_pair("interp", dmax, 8, c16) * nfd_mix[8]
-                   + slots_per_pair("interp", dmax, 4, c16) * nfd_mix[4]) / bpairs
+        slots_b = sum(slots_per_pair("interp", dmax, b, c16) * n for b, n in nfd_mix(c16).items()) / bpairs
         with P.Plan(max_sft=max(x.n_sft for x in bws), max_bins=max(x.n_bins for x in bws),
                     max_sky=max(x.n_sky for x in bws), max_fd=max(x.n_fd for x in bws),
                     max_f=max(x.n_f for x in bws), max_dterms=16, storage=storage,

@@ -320,6 +320,20 @@ int fstat_autotune(fstat_plan* p, const fstat_wu* wu, const fstat_out* out, void
 int32_t fstat_interp_slice(double df, double dfdot, int32_t nfd, int32_t threads, int32_t coef16, double max_abs_tau,
                            double max_p, int32_t* fits);
 
+/* The split of n_fd spindowns into blocks per thread that the interp kernels
+ * run (fstat_compute with its default tile, fstat_batch_compute with its
+ * default launch shape): out[0..5] = the spindowns run 16, 8, 7, 6, 5 and 4
+ * per thread, as consecutive ranges in that order, each range's last block
+ * possibly partial.  The split minimises the lanes computed weighted by the
+ * measured time per lane of each block size.  allow16: blocks of 16 allowed
+ * (the library allows them where their wider slice holds every window);
+ * paired: the unit's sky points pair into tiles of two (which makes the
+ * blocks of at most 8 cheaper); coef16: the FP16-coefficient form (blocks of
+ * 8 and 4 only, never paired).  A host function: no device, plan or
+ * allocation involved.  Returns FSTAT_OK, or FSTAT_E_ARG for n_fd < 1 or a
+ * NULL `out`. */
+int fstat_spindown_split(int64_t n_fd, int32_t coef16, int32_t allow16, int32_t paired, int64_t* out);
+
 /* Duration in milliseconds of the last demodulation kernel of the last
  * fstat_compute / fstat_batch_compute call (after fstat_semicoherent: the
  * sum over its segments' demodulation kernels), measured with HIP events on

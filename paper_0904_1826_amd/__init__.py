@@ -45,7 +45,7 @@ PHASES = {"fp64": FSTAT_PHASE_FP64, "split": FSTAT_PHASE_SPLIT_FP32}
 EXPORTS = ("fstat_plan_create", "fstat_compute", "fstat_batch_compute", "fstat_bins", "fstat_autotune",
            "fstat_last_kernel_ms", "fstat_plan_destroy", "fstat_strerror", "fstat_last_error",
            "fstat_detector_inputs", "fstat_semicoherent", "fstat_compute_noalloc", "fstat_interp_slice",
-           "fstat_last_tile")
+           "fstat_last_tile", "fstat_spindown_split")
 LAST_TILE_LEN = 13                    # FSTAT_LAST_TILE_LEN
 NOALLOC_SCRATCH_BYTES = 128 << 20     # FSTAT_NOALLOC_SCRATCH_BYTES
 
@@ -128,6 +128,8 @@ def load_library(path: str = LIB_PATH):
     lib.fstat_last_kernel_ms.restype = ctypes.c_double
     lib.fstat_last_tile.argtypes = [P, ctypes.POINTER(I32)]
     lib.fstat_last_tile.restype = ctypes.c_int
+    lib.fstat_spindown_split.argtypes = [I64, I32, I32, I32, ctypes.POINTER(I64)]
+    lib.fstat_spindown_split.restype = ctypes.c_int
     lib.fstat_plan_destroy.argtypes = [P]
     lib.fstat_plan_destroy.restype = None
     lib.fstat_strerror.argtypes = [ctypes.c_int]
@@ -449,6 +451,20 @@ def fstat_autotune(plan, wu, out, stream=None, cache_path: Optional[str] = None)
 
 def fstat_last_kernel_ms(plan) -> float:
     return float(load_library().fstat_last_kernel_ms(plan))
+
+
+SPLIT_SIZES = (16, 8, 7, 6, 5, 4)
+
+
+def fstat_spindown_split(n_fd: int, coef16: bool = False, allow16: bool = True, paired: bool = False) -> dict:
+    """{spindowns per thread: spindowns run so} for n_fd spindowns (the
+    library's split, see include/fstat.h)."""
+    buf = (ctypes.c_int64 * len(SPLIT_SIZES))()
+    rc = load_library().fstat_spindown_split(int(n_fd), int(bool(coef16)), int(bool(allow16)), int(bool(paired)),
+                                             buf)
+    if rc != 0:
+        raise FstatError(rc, f"fstat_spindown_split({n_fd}): {fstat_strerror(rc)}")
+    return {b: int(n) for b, n in zip(SPLIT_SIZES, buf) if n}
 
 
 def fstat_last_tile(plan) -> dict:

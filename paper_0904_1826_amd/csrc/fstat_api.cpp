@@ -508,7 +508,7 @@ Tile default_tile(const fstat_plan* p, const fstat_wu* w) {
 // 7: 0.996, 6: 1.034, 5: 1.093, 4: 1.102.  So without pairs 5 spindowns run
 // as one block of 5 rather than a partial 8, 12 as 6 + 6 rather than 8 + 4,
 // 32 as 16 + 16 and 13 as one partial block of 16; with pairs 13 runs as
-// 8 + 5.  All but the last two to three blocks' worth run in blocks of the
+// 7 + 6.  All but the last two to three blocks' worth run in blocks of the
 // largest allowed size (the cheapest per lane); the tail is split exactly by
 // dynamic programming.
 struct FdSplit {
@@ -1740,6 +1740,15 @@ int32_t fstat_interp_slice(double df, double dfdot, int32_t nfd, int32_t threads
   const int W = interp_seg_tau(&w, nfd, threads == 64 ? 64 : fstat::kThreads, coef16 != 0, max_abs_tau, max_p, &f);
   if (fits) *fits = f ? 1 : 0;
   return W;
+}
+
+int fstat_spindown_split(int64_t n_fd, int32_t coef16, int32_t allow16, int32_t paired, int64_t* out) {
+  if (n_fd < 1 || !out) return FSTAT_E_ARG;
+  unsigned sizes = coef16 ? (1u << 8) | (1u << 4) : kAllSplitSizes;
+  if (!allow16) sizes &= ~(1u << 16);
+  const FdSplit sp = split_spindowns(n_fd, sizes, paired && !coef16);
+  for (int i = 0; i < fstat::kSplitSizes; ++i) out[i] = sp.n[i];
+  return FSTAT_OK;
 }
 
 int fstat_last_tile(const fstat_plan* p, int32_t* out) {
