@@ -817,7 +817,8 @@ int make_pairs(const fstat_wu* wu, const fstat::GeoStatus& g, const double* sk, 
   const double over1 = spread1 - (nt - 1.0) > 0 ? spread1 - (nt - 1.0) : 0.0;
   // extra bins the pair may add with the width nt + 6 + ceil(over1 + extra) <= cap
   const double budget = (double)(cap - nt - 6) - over1 - 1.0;
-  if (n < 4 || !std::isfinite(C) || !std::isfinite(budget) || budget < 1.0) return 0;
+  // (pair tables hold 32-bit sky indices)
+  if (n < 4 || n > INT32_MAX || !std::isfinite(C) || !std::isfinite(budget) || budget < 1.0) return 0;
   const double d_max = C > 0.0 ? budget / C : 4.0;
   const double h = sqrt(4.0 * M_PI / (double)n);           // grid spacing
   const int64_t n_band = std::max<int64_t>(1, (int64_t)ceil(2.0 / h));
