@@ -486,6 +486,9 @@ Tile default_tile(const fstat_plan* p, const fstat_wu* w) {
     // L2: with FP32 coefficients launches of 512 SFTs took the case from 125.1
     // to 122.7 ms (L2 hit rate 0.62 -> 0.91); with fewer spindowns per thread
     // the staged slices are reused less and shorter launches pay more
+    // (with tiles of two sky points, which use each staged slice for twice the
+    // pairs, one launch over all SFTs is fastest: 114.7 against 115.6 ms on
+    // that case; prepare_pairs sets it)
     const int minw = nfd == 8 ? (coef16(p) ? 5 : 4) : 3;
     const int sb = nfd < 4 ? 256 : (nfd == 8 && !coef16(p) && w->n_sft > 1024 ? 512 : 0);
     return Tile{nfd, minw, 0, sb, fstat::kThreads};
@@ -611,8 +614,9 @@ Tile complete_tile(const fstat_plan* p, const fstat_wu* w, Tile t, bool paired =
   return t;
 }
 
-Tile pick_tile(const fstat_plan* p, const fstat_wu* w) {
+Tile pick_tile(const fstat_plan* p, const fstat_wu* w, bool* is_default = nullptr) {
   auto it = p->tiles.find(class_key(p, w));
+  if (is_default) *is_default = it == p->tiles.end();
   return complete_tile(p, w, it != p->tiles.end() ? it->second : default_tile(p, w));
 }
 
@@ -861,9 +865,10 @@ int make_pairs(const fstat_wu* wu, const fstat::GeoStatus& g, const double* sk, 
 // Sky points of a single-unit tile of 8 spindowns per thread with ranges of
 // at most 8 per thread (FP32 coefficients, 256 threads, four waves), paired
 // by make_pairs after this unit's geometry pass; sets v.sky_pairs, v.n_pairs
-// and t.pair_seg, or leaves one sky point per tile.  Waits for the stream
-// (idle after the band check).
-int prepare_pairs(fstat_plan* p, const fstat_wu* wu, WuDev& v, Tile& t, hipStream_t st) {
+// and t.pair_seg, or leaves one sky point per tile; with the default tile
+// (`default_tile_used`) the SFT loop then runs in one launch.  Waits for the
+// stream (idle after the band check).
+int prepare_pairs(fstat_plan* p, const fstat_wu* wu, WuDev& v, Tile& t, hipStream_t st, bool default_tile_used) {
   v.sky_pairs = nullptr;
   v.n_pairs = 0;
   t.pair_seg = 0;
@@ -900,6 +905,7 @@ int prepare_pairs(fstat_plan* p, const fstat_wu* wu, WuDev& v, Tile& t, hipStrea
   v.n_pairs = np;
   t = tp;
   t.pair_seg = width;
+  if (default_tile_used) t.sblock = 0;   // the default tile: one launch over all SFTs with pairs
   return FSTAT_OK;
 }
 
@@ -1374,8 +1380,9 @@ int fstat_compute(fstat_plan* p, const fstat_wu* wu, const fstat_out* out, void*
   WuDev v = make_dev(p, wu, out);
   rc = run_geometry(p, v, st, -1);
   if (rc) return rc;
-  Tile t = pick_tile(p, wu);
-  rc = prepare_pairs(p, wu, v, t, st);
+  bool dflt = false;
+  Tile t = pick_tile(p, wu, &dflt);
+  rc = prepare_pairs(p, wu, v, t, st, dflt);
   if (rc) return rc;
   rc = run_demod(p, v, t, st);
   if (rc == FSTAT_OK) queue_drop_check(p, p->status_d, p->status_h, 0, st);
@@ -1513,8 +1520,9 @@ int fstat_semicoherent(fstat_plan* p, const fstat_wu* segs, int32_t n_seg, const
       float ms = 0.f;
       if (hipEventElapsedTime(&ms, p->ev0, p->ev1) == hipSuccess) ms_done += ms;
     }
-    Tile t = pick_tile(p, &segs[k]);
-    rc = prepare_pairs(p, &segs[k], v, t, st);
+    bool dflt = false;
+    Tile t = pick_tile(p, &segs[k], &dflt);
+    rc = prepare_pairs(p, &segs[k], v, t, st, dflt);
     if (rc) return rc;
     rc = run_demod(p, v, t, st);
     if (rc) return rc;
@@ -1674,7 +1682,7 @@ int fstat_autotune(fstat_plan* p, const fstat_wu* wu, const fstat_out* out, void
     for (Tile t0 : cands) {
       Tile t = complete_tile(p, wu, t0);            // as pick_tile and fstat_compute run it
       WuDev vt = v;
-      rc = prepare_pairs(p, wu, vt, t, st);
+      rc = prepare_pairs(p, wu, vt, t, st, false);
       if (rc) return rc;
       float ms = 0.f;
       for (int rep = 0; rep < 2; ++rep) {
