@@ -198,7 +198,10 @@ int fstat_plan_create(fstat_plan** out, const fstat_desc* d);
  * check that every window [k*-D+1, k*+D] of the grid lies in the band; the
  * call waits for this check and returns FSTAT_E_BAND (nothing else
  * launched) if it fails; (2) the demodulation kernel, which writes `out`
- * asynchronously.  Returns after (2) is enqueued. */
+ * asynchronously.  Between the two, the interp kernel's host side copies the
+ * sky vectors back (one more short wait) to pair neighbouring sky points
+ * into tiles of two where the slice can hold both (fstat_last_tile reports
+ * the shape that ran).  Returns after (2) is enqueued. */
 int fstat_compute(fstat_plan* p, const fstat_wu* wu, const fstat_out* out, void* stream);
 
 /* fstat_compute for callers that cannot allocate device memory (code under
