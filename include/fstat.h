@@ -229,8 +229,10 @@ int fstat_compute_noalloc(fstat_plan* p, const fstat_wu* wu, const fstat_out* ou
  * unit's spindowns are split into ranges run 16 (where its slice holds every
  * window), 8, 7, 6, 5 or 4 per thread (8 or 4 with FP16 coefficients), chosen
  * per unit to waste the fewest lanes weighted by the measured cost of each
- * size (5 spindowns run as one block of 5, 12 as 6 + 6, 32 as 16 + 16).  Per
- * block of SFTs (256 unless fstat_autotune chose
+ * size (5 spindowns run as one block of 5, 12 as 6 + 6, 32 as 16 + 16); the
+ * blocks of at most 8 take tiles of two neighbouring sky points where the
+ * unit's sky grid allows (FP32 coefficients; the host reads the sky vectors
+ * back once per group to pair them).  Per block of SFTs (256 unless fstat_autotune chose
  * another) one persistent launch per spindown-block size runs over the units
  * with SFTs left; inside a launch the tiles are dealt to one queue per XCD in
  * chunks of consecutive tiles, so that tiles sharing coefficients are served
