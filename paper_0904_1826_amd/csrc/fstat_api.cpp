@@ -941,6 +941,122 @@ unsigned batch_sizes(const fstat_plan* p, const Tile& bt) {
   return coef16(p) ? (1u << 8) | (1u << 4) : kAllSplitSizes;      // {8, 4} or 16, 4..8
 }
 
+// Per unit of a batched group (in launch order): its sky pairs (make_pairs,
+// where `pairing` allows; width 0 = one sky point per tile, pair table at the
+// unit's offset sky_off[k] of the plan's pair buffer, uploaded on `st`) and
+// its spindown split with the costs of its tiles.  The sky vectors are read
+// back in one wait for the group.
+struct UnitShape {
+  int pair_width = 0;
+  int64_t n_pairs = 0;
+  FdSplit split;
+};
+
+int batch_unit_shapes(fstat_plan* p, const fstat_wu* wus, const std::vector<int>& order, unsigned sizes, bool pairing,
+                      const std::vector<int64_t>& sky_off, hipStream_t st, std::vector<UnitShape>* out) {
+  const int m = (int)order.size();
+  std::vector<UnitShape>& us = *out;
+  us.assign(m, UnitShape{});
+  if (pairing) {
+    std::vector<int> cand;
+    for (int q = 0; q < m; ++q) {
+      const int k = order[q];
+      if (wus[k].n_sky < 4) continue;
+      hipError_t e = hipMemcpyAsync(p->sky_h + 3 * sky_off[k], wus[k].sky, (size_t)(3 * wus[k].n_sky) * sizeof(double),
+                                    hipMemcpyDeviceToHost, st);
+      if (e != hipSuccess) return hip_err(p, e, "sky vector copy");
+      cand.push_back(q);
+    }
+    if (!cand.empty()) {
+      hipError_t e = hipStreamSynchronize(st);
+      if (e != hipSuccess) return hip_err(p, e, "sky vector copy");
+      for (int q : cand) {
+        const int k = order[q];
+        us[q].pair_width =
+            make_pairs(&wus[k], p->bstat_h[k], p->sky_h + 3 * sky_off[k], p->pairs_h + sky_off[k], &us[q].n_pairs);
+        if (!us[q].pair_width) continue;
+        e = hipMemcpyAsync(p->pairs_d + sky_off[k], p->pairs_h + sky_off[k], (size_t)us[q].n_pairs * sizeof(int2),
+                           hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) return hip_err(p, e, "sky pair upload");
+      }
+    }
+  }
+  for (int q = 0; q < m; ++q) {
+    const int k = order[q];
+    unsigned sz = sizes;
+    if ((sz >> 16) & 1u) {          // 16 per thread only where its wider slice holds every window
+      bool f16 = false;
+      (void)interp_seg_tau(&wus[k], 16, fstat::kThreads, coef16(p), status_tau(p->bstat_h[k]), status_p(p->bstat_h[k]),
+                           &f16);
+      if (!f16) sz &= ~(1u << 16);
+    }
+    us[q].split = split_spindowns(wus[k].n_fd, sz, us[q].pair_width > 0);
+  }
+  return FSTAT_OK;
+}
+
+// The demodulation tables of a batched group: table c = i + kSplitSizes
+// (nsky - 1) holds the ranges run split_nfd(i) spindowns per thread with
+// nsky sky points per tile, one entry per unit that has such a range (units
+// most SFTs first), written to eh[m ...) after the group's m unit entries
+// (whose device views they copy).  Per table: entries, first entry, tiles
+// and whether every entry's slice holds its windows.  Returns the number of
+// entries written in all (m included).
+constexpr int kBatchTables = 2 * fstat::kSplitSizes;
+struct BatchTables {
+  int mc[kBatchTables] = {}, off[kBatchTables] = {};
+  int64_t tiles[kBatchTables] = {};
+  bool fast[kBatchTables] = {};
+};
+
+int batch_tables(const fstat_plan* p, const fstat_wu* wus, const std::vector<int>& order,
+                 const std::vector<UnitShape>& us, const std::vector<int64_t>& sky_off, fstat::BatchEntry* eh,
+                 BatchTables* tb) {
+  constexpr int NS = fstat::kSplitSizes;
+  const int m = (int)order.size();
+  int ne = m;
+  for (int c = 0; c < kBatchTables; ++c) {
+    const int i = c % NS, nsky = 1 + c / NS, nfd = fstat::split_nfd(i);
+    tb->off[c] = ne;
+    tb->fast[c] = true;
+    for (int q = 0; q < m; ++q) {
+      const int k = order[q];
+      const bool paired = us[q].pair_width > 0 && nfd <= 8;
+      if ((nsky == 2) != paired) continue;
+      int64_t lo = 0;
+      for (int j = 0; j < i; ++j) lo += us[q].split.n[j];
+      const int64_t hi = lo + us[q].split.n[i];
+      if (hi <= lo) continue;
+      fstat::BatchEntry& e = eh[ne++];
+      e = eh[q];
+      e.nfd = nfd;
+      e.fd_begin = (int32_t)lo;
+      e.fd_end = (int32_t)hi;
+      bool fits = false;
+      if (paired) {                    // the pair's width holds both points' windows by construction
+        e.w.sky_pairs = p->pairs_d + sky_off[k];
+        e.w.n_pairs = us[q].n_pairs;
+        e.seg = us[q].pair_width;
+        fits = true;
+      } else {
+        e.seg = interp_seg_tau(&wus[k], nfd, fstat::kThreads, coef16(p), status_tau(p->bstat_h[k]),
+                               status_p(p->bstat_h[k]), &fits);
+      }
+      if (p->force_seg > 0) {          // fault injection: a slice narrower than the windows need
+        e.seg = p->force_seg;
+        fits = true;
+      }
+      e.fast = fits ? 1 : 0;
+      tb->fast[c] = tb->fast[c] && fits;
+      e.n_tiles = fstat::interp_tiles(e.w, nfd, lo, hi, nsky);
+      e.tile_begin = tb->tiles[c];
+      tb->tiles[c] += e.n_tiles;
+      ++tb->mc[c];
+    }
+  }
+  return ne;
+}
+
 // Batched interp path: work units are grouped so that one group's scratch
 // (geometry, A,B,C, coefficients) fits the budget; per group the geometry is
 // computed and checked, the work-unit table is uploaded, and the coefficient
@@ -975,7 +1091,7 @@ int batch_interp(fstat_plan* p, const fstat_wu* wus, int n, const fstat_out* out
   if (rc) return rc;
   // per group: one entry per unit and up to one demodulation entry per unit
   // and table (block size, one or two sky points per tile)
-  constexpr int NS = fstat::kSplitSizes, NC = 2 * NS;
+  constexpr int NS = fstat::kSplitSizes, NC = kBatchTables;
   constexpr int kEnts = 1 + NC;
   rc = ensure_pinned_pair(p, &p->ents_d, &p->ents_h, &p->ents_cap, kEnts * (size_t)n, "work-unit table");
   if (rc) return rc;
@@ -1084,89 +1200,15 @@ int batch_interp(fstat_plan* p, const fstat_wu* wus, int n, const fstat_out* out
       blocks += fstat::coef_blocks(v);
       sfts += wus[k].n_sft;
     }
-    // tables c = i + NS (nsky - 1): block size split_nfd(i), nsky sky points per tile
-    int mc[NC] = {}, off[NC] = {};
-    int64_t tiles[NC] = {};
-    bool fast[NC];                         // every entry of a table holds its windows in the slice
-    // sky pairs (make_pairs) of every unit that may use them, then each
-    // unit's spindown split with the costs of its tiles (paired or not)
-    std::vector<int> pw(m, 0);
-    std::vector<int64_t> pn(m, 0);
-    if (pairing) {
-      std::vector<int> cand;
-      for (int q = 0; q < m; ++q) {
-        const int k = order[q];
-        if (wus[k].n_sky < 4) continue;
-        hipError_t e = hipMemcpyAsync(p->sky_h + 3 * sky_off[k], wus[k].sky, (size_t)(3 * wus[k].n_sky) * sizeof(double),
-                                      hipMemcpyDeviceToHost, st);
-        if (e != hipSuccess) return hip_err(p, e, "sky vector copy");
-        cand.push_back(q);
-      }
-      if (!cand.empty()) {
-        hipError_t e = hipStreamSynchronize(st);
-        if (e != hipSuccess) return hip_err(p, e, "sky vector copy");
-        for (int q : cand) {
-          const int k = order[q];
-          pw[q] = make_pairs(&wus[k], p->bstat_h[k], p->sky_h + 3 * sky_off[k], p->pairs_h + sky_off[k], &pn[q]);
-          if (!pw[q]) continue;
-          e = hipMemcpyAsync(p->pairs_d + sky_off[k], p->pairs_h + sky_off[k], (size_t)pn[q] * sizeof(int2),
-                             hipMemcpyHostToDevice, st);
-          if (e != hipSuccess) return hip_err(p, e, "sky pair upload");
-        }
-      }
-    }
-    std::vector<FdSplit> splits(m);
-    for (int q = 0; q < m; ++q) {
-      const int k = order[q];
-      unsigned sz = sizes;
-      if ((sz >> 16) & 1u) {          // 16 per thread only where its wider slice holds every window
-        bool f16 = false;
-        (void)interp_seg_tau(&wus[k], 16, fstat::kThreads, coef16(p), status_tau(p->bstat_h[k]),
-                             status_p(p->bstat_h[k]), &f16);
-        if (!f16) sz &= ~(1u << 16);
-      }
-      splits[q] = split_spindowns(wus[k].n_fd, sz, pw[q] > 0);
-    }
-    int ne = m;
-    for (int c = 0; c < NC; ++c) {
-      const int i = c % NS, nsky = 1 + c / NS, nfd = fstat::split_nfd(i);
-      off[c] = ne;
-      fast[c] = true;
-      for (int q = 0; q < m; ++q) {
-        const int k = order[q];
-        const bool paired = pw[q] > 0 && nfd <= 8;
-        if ((nsky == 2) != paired) continue;
-        int64_t lo = 0;
-        for (int j = 0; j < i; ++j) lo += splits[q].n[j];
-        const int64_t hi = lo + splits[q].n[i];
-        if (hi <= lo) continue;
-        fstat::BatchEntry& e = eh[ne++];
-        e = eh[q];
-        e.nfd = nfd;
-        e.fd_begin = (int32_t)lo;
-        e.fd_end = (int32_t)hi;
-        bool fits = false;
-        if (paired) {                    // the pair's width holds both points' windows by construction
-          e.w.sky_pairs = p->pairs_d + sky_off[k];
-          e.w.n_pairs = pn[q];
-          e.seg = pw[q];
-          fits = true;
-        } else {
-          e.seg = interp_seg_tau(&wus[k], nfd, fstat::kThreads, coef16(p), status_tau(p->bstat_h[k]),
-                                 status_p(p->bstat_h[k]), &fits);
-        }
-        if (p->force_seg > 0) {          // fault injection: a slice narrower than the windows need
-          e.seg = p->force_seg;
-          fits = true;
-        }
-        e.fast = fits ? 1 : 0;
-        fast[c] = fast[c] && fits;
-        e.n_tiles = fstat::interp_tiles(e.w, nfd, lo, hi, nsky);
-        e.tile_begin = tiles[c];
-        tiles[c] += e.n_tiles;
-        ++mc[c];
-      }
-    }
+    std::vector<UnitShape> shapes;
+    rc = batch_unit_shapes(p, wus, order, sizes, pairing, sky_off, st, &shapes);
+    if (rc) return rc;
+    BatchTables tb;
+    const int ne = batch_tables(p, wus, order, shapes, sky_off, eh, &tb);
+    const int* mc = tb.mc;
+    const int* off = tb.off;
+    const int64_t* tiles = tb.tiles;
+    const bool* fast = tb.fast;
     fstat::BatchEntry* ed = p->ents_d + kEnts * (size_t)g.first;
     hipError_t e = hipMemcpyAsync(ed, eh, (size_t)ne * sizeof(fstat::BatchEntry), hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return hip_err(p, e, "work-unit table upload");
