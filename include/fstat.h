@@ -348,7 +348,8 @@ double fstat_last_kernel_ms(fstat_plan* p);
 /* The launch shape of the plan's last single-unit demodulation (the last
  * fstat_compute or fstat_compute_noalloc call, the last segment of
  * fstat_semicoherent, the last unit of fstat_batch_compute with the direct
- * kernel; the batched interp form does not set it), for tuning and tests: out[0..4] = spindowns per thread (interp) or frequencies
+ * kernel, or the last shape fstat_autotune timed; the batched interp form
+ * does not set it), for tuning and tests: out[0..4] = spindowns per thread (interp) or frequencies
  * per thread (direct), waves per SIMD or SFTs per LDS chunk, slice width,
  * SFTs per launch (0: all), work-group size; out[5] = slice width of the
  * tiles of two sky points (0: one sky point per tile); out[6] = number of
