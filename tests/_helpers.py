@@ -44,9 +44,12 @@ def slice_edge_workload(coef, side):
     every window must still be in its slice; `out` half a bin beyond, where
     the kernel with that path runs and almost every SFT still takes the LDS
     path.  tau and Tdot follow their definitions (arrival-time offset and its
-    derivative at the SFT midpoints)."""
+    derivative at the SFT midpoints).  Spindowns: 12 with FP16 coefficients
+    (blocks of 8 and 4), 16 with FP32 ones, which run as two blocks of 8 (a
+    block of 16 would need a slice twice as wide as the edge)."""
+    n_fd = 12 if coef == "f16" else 16
     base = dict(n_det=2, slots=23, keep=0.85, n_sky=3, n_f=700, dterms=8, injections=((1, 5, 333, 15.0),))
-    w = small_workload(310, n_fd=12, fdot_lo=-1e-9, **base)
+    w = small_workload(310, n_fd=n_fd, fdot_lo=-1e-9, **base)
     tau = (w.t_start + 0.5 * w.t_sft - w.t_ref)[None, :] + w.sky @ w.pos.T
     p = (1.0 + w.sky @ w.vel.T) * w.t_sft
     max_tau, max_p = float(np.abs(tau).max()), float(p.max())
@@ -54,7 +57,7 @@ def slice_edge_workload(coef, side):
     spread = cap - 9 + 0.01 if side == "in" else cap - 7 + 0.5
     dfdot = (spread / max_p - 255 * w.df) / (7 * max_tau)
     assert dfdot > 0
-    w = small_workload(310, n_fd=12, fdot_lo=-11 * dfdot, **base)
+    w = small_workload(310, n_fd=n_fd, fdot_lo=-(n_fd - 1) * dfdot, **base)
     assert math.isclose(w.dfdot, dfdot, rel_tol=1e-9)
     width = 262 + math.ceil(spread - 255)
     assert (width <= cap) == (side == "in")

@@ -121,7 +121,8 @@ INTERP_TILES = [(8, 4, 0, 256), (8, 4, 7, 256), (8, 3, 0, 256), (8, 2, 0, 256), 
 @pytest.mark.parametrize("coef", ["f32", "f16"])
 def test_slice_capacity_edge(torch_cuda, oracle_lib, coef, side):
     """Parity of every template where the slice bound is tightest, for the
-    8-spindown tiles and the 4-spindown remainder (12 spindowns)."""
+    8-spindown blocks (16 spindowns as 8 + 8 with FP32 coefficients; 12 as
+    8 + 4 with FP16 ones)."""
     torch = torch_cuda
     w = slice_edge_workload(coef, side)
     _say(f"slice edge {coef} {side}: n_sft={w.n_sft} n_bins={w.n_bins} dfdot={w.dfdot:.4e}")
@@ -130,6 +131,10 @@ def test_slice_capacity_edge(torch_cuda, oracle_lib, coef, side):
     with _plan(w, kernel="interp", max_dterms=8, coef=coef) as p:
         p.compute(wu, out)
         torch.cuda.synchronize()
+        shape = p.last_tile()
+    # one range at 8 per thread (FP32: 16 spindowns as two 8-blocks), or 8 + 4
+    assert shape["nf_reg"] == 8 and shape["pair_seg"] == 0
+    assert shape["split"] == ({} if coef == "f32" else {8: 8, 4: 4}), shape
     _compare(oracle_lib, w, out, tol=TOL if coef == "f32" else 5e-3)
 
 

@@ -16,7 +16,11 @@ def test_slice_edge_workloads_sit_at_the_capacity(coef, side):
     tile (from max |tau| and max Tdot T over sky points and SFT midpoints)
     lies 5 bins inside the slice capacity, or half a bin beyond it."""
     w = slice_edge_workload(coef, side)
-    assert w.n_fd == 12 and w.n_f > 256 and w.dfdot > 0
+    assert w.n_fd == (12 if coef == "f16" else 16) and w.n_f > 256 and w.dfdot > 0
+    # the library runs blocks of 8 there (a 16-block's slice would be twice as wide)
+    import paper_0904_1826_amd as P
+    split = P.fstat_spindown_split(w.n_fd, coef16=coef == "f16", allow16=False)
+    assert split.get(8, 0) >= 8, split
     tau = (w.t_start + 0.5 * w.t_sft - w.t_ref)[None, :] + w.sky @ w.pos.T
     p = (1.0 + w.sky @ w.vel.T) * w.t_sft
     spread = (255 * w.df + w.dfdot * 7 * np.abs(tau).max()) * p.max()
