@@ -66,8 +66,8 @@ def slice_edge_workload(coef, side):
 
 def sft_block_workloads():
     """Three units of 1100, 600 and 300 SFTs (5, 3 and 2 launches of the
-    batched form's default 256 SFTs; 3, 2 and 1 of 512) with 9 spindowns (a
-    block of 8 and a remainder)."""
+    batched form's default 256 SFTs; 3, 2 and 1 of 512) with 9 spindowns
+    (blocks of two sizes: 5 + 4 with FP32 coefficients, 8 + 4 with FP16)."""
     return [small_workload(700 + k, n_det=2, slots=s, keep=1.0, n_sky=2, n_fd=9, n_f=300, dterms=8,
                            injections=((1, 4, 150, 12.0),)) for k, s in enumerate([550, 300, 150])]
 

@@ -257,7 +257,8 @@ BATCH_TILES = [("c0", "4 64 256 256"), ("c0", "8 1 100 256"), ("c1", "4 1024 102
 @pytest.mark.parametrize("cls,shape", BATCH_TILES, ids=[f"{c}-{s.replace(' ', '_')}" for c, s in BATCH_TILES])
 def test_batch_tile_from_the_autotune_cache(torch_cuda, oracle_lib, tmp_path, cls, shape):
     """Batched launch shapes forced through the autotune cache (spindowns in
-    blocks of 4 or of 8 plus a 4-block remainder, tiles per chunk of the
+    blocks of 4 only, or split by lane cost into blocks of 16 and 4 to 8 (8
+    and 4 with FP16 coefficients), tiles per chunk of the
     per-XCD queues, SFTs per launch): every unit bit for bit equal to its
     single-unit call with the default tile, and every template within the
     oracle's tolerance."""

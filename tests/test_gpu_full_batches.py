@@ -72,8 +72,9 @@ def test_batch_64_work_units_full_size(torch_cuda, oracle_lib):
         assert e.max() <= 1e-4, (k, e.max())
         assert outs[k].twoF[x.sky_index, x.fdot_index, x.f_index].item() > 0.4 * x.snr ** 2
     _say(f"  sampled max 2F error over 64 units: {worst:.2e}")
-    # the units the persistent queues serve last (fewest SFTs) and units with a
-    # 4-spindown remainder table: every template of their last sky point
+    # the units the persistent queues serve last (fewest SFTs) and units whose
+    # spindowns split into blocks of several sizes (the tables after the
+    # first): every template of their last sky point
     # (every spindown, every frequency including the ragged last tile)
     by_sft = sorted(range(len(ws)), key=lambda k: ws[k].n_sft)
     rem4 = [k for k in range(len(ws)) if 1 <= ws[k].n_fd % 8 <= 4 and ws[k].n_fd > 8][:3]

@@ -36,7 +36,7 @@ def test_sft_block_workloads_span_several_blocks():
     ws = sft_block_workloads()
     assert [(w.n_sft + 511) // 512 for w in ws] == [3, 2, 1]
     assert [(w.n_sft + 255) // 256 for w in ws] == [5, 3, 2]
-    assert all(w.n_fd % 8 == 1 for w in ws)          # a 4-spindown remainder table as well
+    assert all(w.n_fd % 8 == 1 for w in ws)          # spindowns in blocks of two sizes as well
 
 
 @pytest.mark.parametrize("edge,kappa", [("zero", 0.0), ("one", 1.0 - 2.0 ** -34)])
