@@ -325,6 +325,27 @@ int fstat_autotune(fstat_plan* p, const fstat_wu* wu, const fstat_out* out, void
 int32_t fstat_interp_slice(double df, double dfdot, int32_t nfd, int32_t threads, int32_t coef16, double max_abs_tau,
                            double max_p, int32_t* fits);
 
+/* The pairing of sky points into tiles of two that the interp kernels use
+ * for ranges of at most 8 spindowns per thread (FP32 coefficients), for a
+ * work unit with the given template grids whose geometry has at most
+ * max_abs_tau = max |tau| (s), max_p = max Tdot T (s) over its (sky, SFT)
+ * pairs, max_v = max |v| (units of c) and max_r = max |r| (light-s) over its
+ * SFTs.  The bins of two sky points differ by at most |n0 - n1| (f_max T max_v
+ * + |fdot|max (max_abs_tau T max_v + max_p max_r)), which widens the slice
+ * of one sky point's tile (fstat_interp_slice at min(n_fd, 8) spindowns);
+ * neighbouring points (bands of z, alternately rising and falling longitude)
+ * pair while that width fits the LDS row.  sky: host array [n_sky][3] of
+ * unit vectors.  Writes the tiles to `pairs` (host [2 n_sky]: tile t covers
+ * sky points pairs[2t] and pairs[2t + 1], equal for a point without a
+ * partner) and their count to *n_pairs, and returns the paired tiles' slice
+ * width, or 0 when one sky point per tile is kept (fewer than half the
+ * points pair, or n_sky < 4; *n_pairs is then 0).  Returns FSTAT_E_ARG for
+ * NULL arrays or n_sky < 1.  A host function: no device, plan or allocation
+ * involved. */
+int32_t fstat_sky_pairs(int64_t n_sky, const double* sky, double f0, double df, int64_t n_f, double fdot0,
+                        double dfdot, int64_t n_fd, double t_sft, double max_abs_tau, double max_p, double max_v,
+                        double max_r, int32_t* pairs, int64_t* n_pairs);
+
 /* The split of n_fd spindowns into blocks per thread that the interp kernels
  * run (fstat_compute with its default tile, fstat_batch_compute with its
  * default launch shape): out[0..5] = the spindowns run 16, 8, 7, 6, 5 and 4

@@ -45,7 +45,7 @@ PHASES = {"fp64": FSTAT_PHASE_FP64, "split": FSTAT_PHASE_SPLIT_FP32}
 EXPORTS = ("fstat_plan_create", "fstat_compute", "fstat_batch_compute", "fstat_bins", "fstat_autotune",
            "fstat_last_kernel_ms", "fstat_plan_destroy", "fstat_strerror", "fstat_last_error",
            "fstat_detector_inputs", "fstat_semicoherent", "fstat_compute_noalloc", "fstat_interp_slice",
-           "fstat_last_tile", "fstat_spindown_split")
+           "fstat_last_tile", "fstat_spindown_split", "fstat_sky_pairs")
 LAST_TILE_LEN = 13                    # FSTAT_LAST_TILE_LEN
 NOALLOC_SCRATCH_BYTES = 128 << 20     # FSTAT_NOALLOC_SCRATCH_BYTES
 
@@ -130,6 +130,10 @@ def load_library(path: str = LIB_PATH):
     lib.fstat_last_tile.restype = ctypes.c_int
     lib.fstat_spindown_split.argtypes = [I64, I32, I32, I32, ctypes.POINTER(I64)]
     lib.fstat_spindown_split.restype = ctypes.c_int
+    D = ctypes.c_double
+    lib.fstat_sky_pairs.argtypes = [I64, ctypes.POINTER(D), D, D, I64, D, D, I64, D, D, D, D, D,
+                                    ctypes.POINTER(I32), ctypes.POINTER(I64)]
+    lib.fstat_sky_pairs.restype = I32
     lib.fstat_plan_destroy.argtypes = [P]
     lib.fstat_plan_destroy.restype = None
     lib.fstat_strerror.argtypes = [ctypes.c_int]
@@ -465,6 +469,25 @@ def fstat_spindown_split(n_fd: int, coef16: bool = False, allow16: bool = True, 
     if rc != 0:
         raise FstatError(rc, f"fstat_spindown_split({n_fd}): {fstat_strerror(rc)}")
     return {b: int(n) for b, n in zip(SPLIT_SIZES, buf) if n}
+
+
+def fstat_sky_pairs(sky, f0, df, n_f, fdot0, dfdot, n_fd, t_sft, max_abs_tau, max_p, max_v, max_r):
+    """(slice width, tiles as an [n, 2] int array) of the library's pairing
+    of sky points (see include/fstat.h); width 0 and no tiles when it keeps
+    one sky point per tile.  `sky` is a host array [n_sky][3]."""
+    import numpy as np
+    sky = np.ascontiguousarray(sky, dtype=np.float64)
+    if sky.ndim != 2 or sky.shape[1] != 3:
+        raise ValueError("sky must be [n_sky][3]")
+    n = sky.shape[0]
+    out = np.zeros(2 * max(n, 1), dtype=np.int32)
+    n_pairs = ctypes.c_int64(0)
+    w = load_library().fstat_sky_pairs(n, sky.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), f0, df, n_f, fdot0,
+                                       dfdot, n_fd, t_sft, max_abs_tau, max_p, max_v, max_r,
+                                       out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ctypes.byref(n_pairs))
+    if w < 0:
+        raise FstatError(w, f"fstat_sky_pairs: {fstat_strerror(w)}")
+    return int(w), out[:2 * n_pairs.value].reshape(-1, 2).copy()
 
 
 def fstat_last_tile(plan) -> dict:

@@ -1793,6 +1793,30 @@ int32_t fstat_interp_slice(double df, double dfdot, int32_t nfd, int32_t threads
   return W;
 }
 
+int32_t fstat_sky_pairs(int64_t n_sky, const double* sky, double f0, double df, int64_t n_f, double fdot0,
+                        double dfdot, int64_t n_fd, double t_sft, double max_abs_tau, double max_p, double max_v,
+                        double max_r, int32_t* pairs, int64_t* n_pairs) {
+  if (n_sky < 1 || !sky || !pairs || !n_pairs || n_f < 1 || n_fd < 1) return FSTAT_E_ARG;
+  fstat_wu w{};
+  w.n_sky = n_sky;
+  w.f0 = f0;
+  w.df = df;
+  w.n_f = n_f;
+  w.fdot0 = fdot0;
+  w.dfdot = dfdot;
+  w.n_fd = n_fd;
+  w.t_sft = t_sft;
+  fstat::GeoStatus g{};
+  memcpy(&g.max_abs_tau_bits, &max_abs_tau, sizeof(double));
+  memcpy(&g.max_p_bits, &max_p, sizeof(double));
+  memcpy(&g.max_v_bits, &max_v, sizeof(double));
+  memcpy(&g.max_r_bits, &max_r, sizeof(double));
+  int64_t np = 0;
+  const int width = make_pairs(&w, g, sky, reinterpret_cast<int2*>(pairs), &np);
+  *n_pairs = width ? np : 0;
+  return width;
+}
+
 int fstat_spindown_split(int64_t n_fd, int32_t coef16, int32_t allow16, int32_t paired, int64_t* out) {
   if (n_fd < 1 || !out) return FSTAT_E_ARG;
   unsigned sizes = coef16 ? (1u << 8) | (1u << 4) : kAllSplitSizes;
