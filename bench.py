@@ -274,8 +274,10 @@ def main():
             step = (lambda: plan.semicoherent(wus, out)) if semi_main else (lambda: plan.compute(wus[0], out))
             steps = args.steps if form == forms[0] else max(2, args.steps // 2)
             s_step, kms = time_steps(torch, step, args.warmup, steps, plan.last_kernel_ms)
+            launch = plan.last_tile()          # the shape the library ran (spindown split, sky pairs)
         samples[form] = take(out.twoF, (ss, si, sj))
-        results[form] = {"steps": steps, "ms_per_step": 1e3 * s_step, "value": pairs / s_step, "kernel_ms": kms}
+        results[form] = {"steps": steps, "ms_per_step": 1e3 * s_step, "value": pairs / s_step, "kernel_ms": kms,
+                         "launch": {k: v for k, v in launch.items() if k != "split"} | {"split": {str(b): n for b, n in launch["split"].items()}}}
         say(f"{form}: {results[form]}")
         del wus, devs, out
         torch.cuda.empty_cache()
