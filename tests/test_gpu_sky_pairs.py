@@ -50,6 +50,9 @@ CLUSTERED = [_unit_vec(0.7, 0.3), _unit_vec(0.71, 0.3), _unit_vec(1.9, 2.0), _un
              _unit_vec(2.6, -1.2), _unit_vec(2.61, -1.2), _unit_vec(1.3, -2.6)]
 # four points about 1.9 rad apart: too sparse to pair
 SPARSE = [_unit_vec(0.0, 0.0), _unit_vec(1.91, 0.0), _unit_vec(1.91, 2.094), _unit_vec(1.91, -2.094)]
+# both poles twice (longitude undefined, pair distance 0) and a close pair on the equator: 3 sky tiles
+POLES = [[0.0, 0.0, 1.0], [0.0, 0.0, -1.0], [0.0, 0.0, 1.0], _unit_vec(math.pi / 2, 0.4), [0.0, 0.0, -1.0],
+         _unit_vec(math.pi / 2 + 0.01, 0.4)]
 
 
 def _one_sky(wu, s):
@@ -78,13 +81,15 @@ def _run(torch, w, skies, nfd_split=None):
     return single.twoF.cpu().numpy(), batched.twoF.cpu().numpy(), shape, ref
 
 
-@pytest.mark.parametrize("case", ["clustered", "sparse", "fibonacci200"])
+@pytest.mark.parametrize("case", ["clustered", "sparse", "poles", "fibonacci200"])
 def test_paired_tiles_match_single_sky_tiles_and_oracle(torch_cuda, oracle_lib, case):
     torch = torch_cuda
     if case == "clustered":
         w = _unit(901, CLUSTERED)
     elif case == "sparse":
         w = _unit(902, SPARSE)
+    elif case == "poles":
+        w = _unit(905, POLES)
     else:
         w = synth.make_workload("pairs-903", seed=903, n_det=2, slots_per_det=20, keep_frac=0.9, jitter=60.0,
                                 t_sft=1800.0, f0=400.0, n_f=300, n_sky=200, n_fd=8, fdot_lo=-2e-9, fdot_hi=0.0,
@@ -96,6 +101,9 @@ def test_paired_tiles_match_single_sky_tiles_and_oracle(torch_cuda, oracle_lib, 
         assert shape["pair_seg"] > 0 and shape["sky_tiles"] == 4
     elif case == "sparse":
         assert shape["pair_seg"] == 0 and shape["sky_tiles"] == w.n_sky
+    elif case == "poles":
+        assert shape["pair_seg"] > 0 and shape["sky_tiles"] == 3
+        assert np.array_equal(a[0], a[2]) and np.array_equal(a[1], a[4])     # a sky point paired with its copy
     else:
         assert shape["pair_seg"] > 0 and w.n_sky // 2 <= shape["sky_tiles"] < 3 * w.n_sky // 4
     assert np.array_equal(a, b)

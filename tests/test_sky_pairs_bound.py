@@ -8,6 +8,8 @@ from the canonical FP64 D-hat-phi = f P + (fdot tau) P at the corners of
 random tiles (256 frequencies x min(n_fd, 8) spindowns) for every SFT, and
 at every template of the tile for a sample of pairs and SFTs; the pairing
 must also place every sky point in exactly one tile."""
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -80,6 +82,18 @@ def test_pair_slices_hold_both_points_windows(seed, f0, n_sky, slots):
                 k = _kstar(f, d, tau[s, al][None, None, :], p[s, al][None, None, :])
                 assert np.all(k >= lo[x, al]) and np.all(k <= lo[x, al] + width - 1)
     assert worst <= width
+
+
+def test_poles_and_duplicate_points_pair_with_their_copies():
+    """Both poles twice (their longitude is undefined) and a close pair on the
+    equator: three tiles of two points, each point in exactly one."""
+    w = _unit(6, 400.0, 6, 100)
+    sky = np.array([[0, 0, 1.0], [0, 0, -1.0], [0, 0, 1.0], [np.cos(0.4), np.sin(0.4), 0.0], [0, 0, -1.0],
+                    [np.cos(0.4) * np.cos(0.01), np.sin(0.4) * np.cos(0.01), -np.sin(0.01)]])
+    w = dataclasses.replace(w, sky=sky)
+    width, tiles = _pairs(w, _geometry(w))
+    assert width > 0 and len(tiles) == 3
+    assert sorted(map(sorted, tiles.tolist())) == [[0, 2], [1, 4], [3, 5]]
 
 
 def test_sparse_sky_keeps_one_point_per_tile():
