@@ -799,11 +799,15 @@ double status_bits(unsigned long long b) {
 // sky point over min(n_fd, 8) spindowns (the widest such range).  Sky points
 // are ordered in bands of z of the grid's spacing, alternately by
 // increasing and decreasing longitude, and consecutive points are paired
-// when the pair's slice still fits the LDS capacity; a point without a
-// partner forms a tile of its own sky point twice (computed twice, written
-// once).  Writes the n_pairs tiles to `out` (room for n_sky) and returns the
-// slice width, or 0 when pairing does not apply (fewer than half the points
-// find a partner, or no width fits).
+// when the pair's slice still fits the LDS capacity.  The points this leaves
+// alone (mostly at the ends of bands) are then paired among themselves: each
+// with the nearest of the next 16 unpaired ones in the same order that fits.
+// A point still without a partner forms a tile of its own sky point twice
+// (computed twice, written once).  Tiles are written in the band order of
+// their first point, so that consecutive tiles stay neighbours on the sky.
+// Writes the n_pairs tiles to `out` (room for n_sky) and returns the slice
+// width, or 0 when pairing does not apply (fewer than half the points find a
+// partner, or no width fits).
 int make_pairs(const fstat_wu* wu, const fstat::GeoStatus& g, const double* sk, int2* out, int64_t* n_pairs) {
   *n_pairs = 0;
   const int64_t n = wu->n_sky;
@@ -840,21 +844,52 @@ int make_pairs(const fstat_wu* wu, const fstat::GeoStatus& g, const double* sk, 
   };
   int64_t np = 0, paired = 0;
   double worst = 0.0;
+  std::vector<int64_t> partner((size_t)n, -1), left;
   for (int64_t q = 0; q < n;) {
     const int64_t a = key[(size_t)q].second;
     if (q + 1 < n) {
       const int64_t b = key[(size_t)q + 1].second;
       const double d = dist(a, b);
       if (d <= d_max) {
-        out[np++] = make_int2((int)a, (int)b);
+        partner[(size_t)a] = b;
+        partner[(size_t)b] = a;
         worst = std::max(worst, d);
         paired += 2;
         q += 2;
         continue;
       }
     }
-    out[np++] = make_int2((int)a, (int)a);
+    left.push_back(a);
     ++q;
+  }
+  for (size_t i = 0; i < left.size(); ++i) {
+    const int64_t a = left[i];
+    if (partner[(size_t)a] >= 0) continue;
+    int64_t best = -1;
+    double bd = 0.0;
+    for (size_t j = i + 1; j < left.size() && j <= i + 16; ++j) {
+      const int64_t b = left[j];
+      if (partner[(size_t)b] >= 0) continue;
+      const double d = dist(a, b);
+      if (d <= d_max && (best < 0 || d < bd)) {
+        best = b;
+        bd = d;
+      }
+    }
+    if (best >= 0) {
+      partner[(size_t)a] = best;
+      partner[(size_t)best] = a;
+      worst = std::max(worst, bd);
+      paired += 2;
+    }
+  }
+  std::vector<char> done((size_t)n, 0);
+  for (int64_t q = 0; q < n; ++q) {
+    const int64_t a = key[(size_t)q].second;
+    if (done[(size_t)a]) continue;
+    const int64_t b = partner[(size_t)a] >= 0 ? partner[(size_t)a] : a;
+    done[(size_t)a] = done[(size_t)b] = 1;
+    out[np++] = make_int2((int)a, (int)b);
   }
   const double width = nt + 6.0 + ceil(over1 + worst * C);
   if (2 * paired < n || !(width <= cap)) return 0;
