@@ -86,6 +86,13 @@ struct fstat_plan {
   int2* pairs_d = nullptr;
   int2* pairs_h = nullptr;              // pinned
   size_t pairs_cap = 0;
+  // the sky array whose host copy the geometry pass's wait brought into
+  // sky_h (stage_sky), for the pairing that follows it in the same call
+  const void* sky_staged = nullptr;
+  // the band order of the last sky grid paired, kept while the sky vectors
+  // stay the same (time segments, repeated calls on one grid)
+  std::vector<double> ord_sky;
+  std::vector<int64_t> ord_idx;
   hipStream_t cap_stream = nullptr;
   // persistent grids of the batch kernels with split_nfd(c % kSplitSizes)
   // spindowns and 1 + c / kSplitSizes sky points per tile, with [c][1] and
@@ -649,13 +656,23 @@ int ensure_scratch(fstat_plan* p, const fstat_wu* w) {
 
 // Geometry + band check into the status record status_d; waits for the
 // check.  Returns FSTAT_OK or an error.
-int run_geometry_at(fstat_plan* p, const WuDev& v, fstat::GeoStatus* status_d, hipStream_t st, int idx) {
+int stage_sky(fstat_plan* p, const fstat_wu* wu, hipStream_t st);
+
+// With `stage` (a unit whose sky points may be paired), the host copy of its
+// sky vectors rides on the same wait.
+int run_geometry_at(fstat_plan* p, const WuDev& v, fstat::GeoStatus* status_d, hipStream_t st, int idx,
+                    const fstat_wu* stage = nullptr) {
+  p->sky_staged = nullptr;
   int rc = check_launch(p, fstat::launch_fill_int((int*)status_d, 0, fstat::kGeoResetInts, st), "status reset");
   if (rc) return rc;
   rc = check_launch(p, fstat::launch_geometry(v, status_d, st), "geometry kernel");
   if (rc) return rc;
   hipError_t e = hipMemcpyAsync(p->status_h, status_d, sizeof(fstat::GeoStatus), hipMemcpyDeviceToHost, st);
   if (e != hipSuccess) return hip_err(p, e, "status copy");
+  if (stage) {
+    rc = stage_sky(p, stage, st);
+    if (rc) return rc;
+  }
   e = hipStreamSynchronize(st);
   if (e != hipSuccess) return hip_err(p, e, "geometry kernel");
   const int st_bits = p->status_h->flags;
@@ -670,8 +687,8 @@ int run_geometry_at(fstat_plan* p, const WuDev& v, fstat::GeoStatus* status_d, h
   return FSTAT_OK;
 }
 
-int run_geometry(fstat_plan* p, const WuDev& v, hipStream_t st, int idx) {
-  return run_geometry_at(p, v, p->status_d, st, idx);
+int run_geometry(fstat_plan* p, const WuDev& v, hipStream_t st, int idx, const fstat_wu* stage = nullptr) {
+  return run_geometry_at(p, v, p->status_d, st, idx, stage);
 }
 
 int run_demod(fstat_plan* p, const WuDev& v, const Tile& t, hipStream_t st) {
@@ -808,7 +825,28 @@ double status_bits(unsigned long long b) {
 // Writes the n_pairs tiles to `out` (room for n_sky) and returns the slice
 // width, or 0 when pairing does not apply (fewer than half the points find a
 // partner, or no width fits).
-int make_pairs(const fstat_wu* wu, const fstat::GeoStatus& g, const double* sk, int2* out, int64_t* n_pairs) {
+// Sky point indices in the order the pairing walks them: bands of z of the
+// grid's spacing, alternately by increasing and decreasing longitude (ties by
+// index).
+void band_order(const double* sk, int64_t n, std::vector<int64_t>* ord) {
+  const double h = sqrt(4.0 * M_PI / (double)n);           // grid spacing
+  const int64_t n_band = std::max<int64_t>(1, (int64_t)ceil(2.0 / h));
+  std::vector<std::pair<std::pair<int64_t, double>, int64_t>> key((size_t)n);
+  for (int64_t i = 0; i < n; ++i) {
+    const double z = sk[3 * i + 2], ph = atan2(sk[3 * i + 1], sk[3 * i]);
+    int64_t b = (int64_t)floor((z + 1.0) / 2.0 * (double)n_band);
+    b = b < 0 ? 0 : (b >= n_band ? n_band - 1 : b);
+    key[(size_t)i] = {{b, (b & 1) ? -ph : ph}, i};
+  }
+  std::sort(key.begin(), key.end());
+  ord->resize((size_t)n);
+  for (int64_t i = 0; i < n; ++i) (*ord)[(size_t)i] = key[(size_t)i].second;
+}
+
+// `order`: the band_order of these sky vectors if the caller has it (else it
+// is computed here).
+int make_pairs(const fstat_wu* wu, const fstat::GeoStatus& g, const double* sk, int2* out, int64_t* n_pairs,
+               const std::vector<int64_t>* order = nullptr) {
   *n_pairs = 0;
   const int64_t n = wu->n_sky;
   const int nt = fstat::kThreads, cap = fstat::interp_max_seg(nt, false);
@@ -828,16 +866,12 @@ int make_pairs(const fstat_wu* wu, const fstat::GeoStatus& g, const double* sk, 
   // (pair tables hold 32-bit sky indices)
   if (n < 4 || n > INT32_MAX || !std::isfinite(C) || !std::isfinite(budget) || budget < 1.0) return 0;
   const double d_max = C > 0.0 ? budget / C : 4.0;
-  const double h = sqrt(4.0 * M_PI / (double)n);           // grid spacing
-  const int64_t n_band = std::max<int64_t>(1, (int64_t)ceil(2.0 / h));
-  std::vector<std::pair<std::pair<int64_t, double>, int64_t>> key((size_t)n);
-  for (int64_t i = 0; i < n; ++i) {
-    const double z = sk[3 * i + 2], ph = atan2(sk[3 * i + 1], sk[3 * i]);
-    int64_t b = (int64_t)floor((z + 1.0) / 2.0 * (double)n_band);
-    b = b < 0 ? 0 : (b >= n_band ? n_band - 1 : b);
-    key[(size_t)i] = {{b, (b & 1) ? -ph : ph}, i};
+  std::vector<int64_t> own;
+  if (!order || (int64_t)order->size() != n) {
+    band_order(sk, n, &own);
+    order = &own;
   }
-  std::sort(key.begin(), key.end());
+  const std::vector<int64_t>& key = *order;
   auto dist = [&](int64_t a, int64_t b) {
     const double dx = sk[3 * a] - sk[3 * b], dy = sk[3 * a + 1] - sk[3 * b + 1], dz = sk[3 * a + 2] - sk[3 * b + 2];
     return sqrt((dx * dx + dy * dy) + dz * dz);
@@ -846,9 +880,9 @@ int make_pairs(const fstat_wu* wu, const fstat::GeoStatus& g, const double* sk, 
   double worst = 0.0;
   std::vector<int64_t> partner((size_t)n, -1), left;
   for (int64_t q = 0; q < n;) {
-    const int64_t a = key[(size_t)q].second;
+    const int64_t a = key[(size_t)q];
     if (q + 1 < n) {
-      const int64_t b = key[(size_t)q + 1].second;
+      const int64_t b = key[(size_t)q + 1];
       const double d = dist(a, b);
       if (d <= d_max) {
         partner[(size_t)a] = b;
@@ -885,7 +919,7 @@ int make_pairs(const fstat_wu* wu, const fstat::GeoStatus& g, const double* sk, 
   }
   std::vector<char> done((size_t)n, 0);
   for (int64_t q = 0; q < n; ++q) {
-    const int64_t a = key[(size_t)q].second;
+    const int64_t a = key[(size_t)q];
     if (done[(size_t)a]) continue;
     const int64_t b = partner[(size_t)a] >= 0 ? partner[(size_t)a] : a;
     done[(size_t)a] = done[(size_t)b] = 1;
@@ -897,20 +931,12 @@ int make_pairs(const fstat_wu* wu, const fstat::GeoStatus& g, const double* sk, 
   return (int)width & ~3;
 }
 
-// Sky points of a single-unit tile of 8 spindowns per thread with ranges of
-// at most 8 per thread (FP32 coefficients, 256 threads, four waves), paired
-// by make_pairs after this unit's geometry pass; sets v.sky_pairs, v.n_pairs
-// and t.pair_seg, or leaves one sky point per tile; with the default tile
-// (`default_tile_used`) the SFT loop then runs in one launch.  Waits for the
-// stream (idle after the band check).
-int prepare_pairs(fstat_plan* p, const fstat_wu* wu, WuDev& v, Tile& t, hipStream_t st, bool default_tile_used) {
-  v.sky_pairs = nullptr;
-  v.n_pairs = 0;
-  t.pair_seg = 0;
-  if (resolved_kernel(p) != fstat::KERNEL_INTERP || coef16(p) || t.nf_reg != 8 || t.threads != fstat::kThreads ||
-      t.chunk < 4 || wu->n_sky < 4 || p->force_seg > 0)
-    return FSTAT_OK;
+// Enqueues the host copy of the unit's sky vectors into sky_h (pinned, grown
+// as needed) on st; sky_staged names the array once the stream has been
+// waited for.
+int stage_sky(fstat_plan* p, const fstat_wu* wu, hipStream_t st) {
   const int64_t n = wu->n_sky;
+  p->sky_staged = nullptr;
   if (p->sky_h_cap < (size_t)(3 * n)) {
     if (p->sky_h) (void)hipHostFree(p->sky_h);
     p->sky_h = nullptr;
@@ -921,20 +947,56 @@ int prepare_pairs(fstat_plan* p, const fstat_wu* wu, WuDev& v, Tile& t, hipStrea
     }
     p->sky_h_cap = (size_t)(3 * n);
   }
+  const hipError_t e = hipMemcpyAsync(p->sky_h, wu->sky, (size_t)(3 * n) * sizeof(double), hipMemcpyDeviceToHost, st);
+  if (e != hipSuccess) return hip_err(p, e, "sky vector copy");
+  p->sky_staged = wu->sky;
+  return FSTAT_OK;
+}
+
+// Whether a single-unit call on this plan may pair the unit's sky points
+// (prepare_pairs decides once the tile is known).
+bool may_pair(const fstat_plan* p, const fstat_wu* wu) {
+  return resolved_kernel(p) == fstat::KERNEL_INTERP && !coef16(p) && wu->n_sky >= 4 && p->force_seg <= 0;
+}
+
+// Sky points of a single-unit tile of 8 spindowns per thread with ranges of
+// at most 8 per thread (FP32 coefficients, 256 threads, four waves), paired
+// by make_pairs after this unit's geometry pass; sets v.sky_pairs, v.n_pairs
+// and t.pair_seg, or leaves one sky point per tile; with the default tile
+// (`default_tile_used`) the SFT loop then runs in one launch.  Uses the sky
+// vectors the geometry pass's wait brought (stage_sky), else copies them and
+// waits for the stream (idle after the band check).
+int prepare_pairs(fstat_plan* p, const fstat_wu* wu, WuDev& v, Tile& t, hipStream_t st, bool default_tile_used) {
+  v.sky_pairs = nullptr;
+  v.n_pairs = 0;
+  t.pair_seg = 0;
+  if (resolved_kernel(p) != fstat::KERNEL_INTERP || coef16(p) || t.nf_reg != 8 || t.threads != fstat::kThreads ||
+      t.chunk < 4 || wu->n_sky < 4 || p->force_seg > 0)
+    return FSTAT_OK;
+  const int64_t n = wu->n_sky;
   int rc = ensure_pinned_pair(p, &p->pairs_d, &p->pairs_h, &p->pairs_cap, (size_t)n, "sky pairs");
   if (rc) return rc;
-  hipError_t e = hipMemcpyAsync(p->sky_h, wu->sky, (size_t)(3 * n) * sizeof(double), hipMemcpyDeviceToHost, st);
-  if (e == hipSuccess) e = hipStreamSynchronize(st);
-  if (e != hipSuccess) return hip_err(p, e, "sky vector copy");
+  if (p->sky_staged != wu->sky) {          // not brought by this call's geometry wait
+    rc = stage_sky(p, wu, st);
+    if (rc) return rc;
+    const hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_err(p, e, "sky vector copy");
+  }
+  p->sky_staged = nullptr;
   int64_t np = 0;
-  const int width = make_pairs(wu, *p->status_h, p->sky_h, p->pairs_h, &np);
+  if (n <= INT32_MAX &&
+      (p->ord_sky.size() != (size_t)(3 * n) || memcmp(p->ord_sky.data(), p->sky_h, (size_t)(3 * n) * sizeof(double)))) {
+    p->ord_sky.assign(p->sky_h, p->sky_h + 3 * n);
+    band_order(p->sky_h, n, &p->ord_idx);
+  }
+  const int width = make_pairs(wu, *p->status_h, p->sky_h, p->pairs_h, &np, &p->ord_idx);
   if (!width) return FSTAT_OK;
   // the split with the costs of paired tiles; pairs serve its ranges of at most 8
   const Tile tp = complete_tile(p, wu, t, true);
   bool small = std::all_of(tp.fd_split, tp.fd_split + fstat::kSplitSizes, [](int32_t x) { return x == 0; });
   for (int i = 0; i < fstat::kSplitSizes; ++i) small = small || (fstat::split_nfd(i) <= 8 && tp.fd_split[i] > 0);
   if (!small) return FSTAT_OK;
-  e = hipMemcpyAsync(p->pairs_d, p->pairs_h, (size_t)np * sizeof(int2), hipMemcpyHostToDevice, st);
+  const hipError_t e = hipMemcpyAsync(p->pairs_d, p->pairs_h, (size_t)np * sizeof(int2), hipMemcpyHostToDevice, st);
   if (e != hipSuccess) return hip_err(p, e, "sky pair upload");
   v.sky_pairs = p->pairs_d;
   v.n_pairs = np;
@@ -1167,6 +1229,7 @@ int batch_interp(fstat_plan* p, const fstat_wu* wus, int n, const fstat_out* out
   std::vector<int64_t> sky_off(n + 1, 0);
   for (int k = 0; k < n; ++k) sky_off[k + 1] = sky_off[k] + wus[k].n_sky;
   if (pairing) {
+    p->sky_staged = nullptr;                 // sky_h now holds the batch's sky vectors
     if (p->sky_h_cap < (size_t)(3 * sky_off[n])) {
       if (p->sky_h) (void)hipHostFree(p->sky_h);
       p->sky_h = nullptr;
@@ -1455,7 +1518,7 @@ int fstat_compute(fstat_plan* p, const fstat_wu* wu, const fstat_out* out, void*
   rc = reset_drops(p, p->status_d, st);
   if (rc) return rc;
   WuDev v = make_dev(p, wu, out);
-  rc = run_geometry(p, v, st, -1);
+  rc = run_geometry(p, v, st, -1, may_pair(p, wu) ? wu : nullptr);
   if (rc) return rc;
   bool dflt = false;
   Tile t = pick_tile(p, wu, &dflt);
@@ -1591,7 +1654,7 @@ int fstat_semicoherent(fstat_plan* p, const fstat_wu* segs, int32_t n_seg, const
     v.accumulate = k > 0;
     // the geometry pass waits for the stream, so the previous segment's
     // demodulation events have completed
-    rc = run_geometry(p, v, st, k);
+    rc = run_geometry(p, v, st, k, may_pair(p, &segs[k]) ? &segs[k] : nullptr);
     if (rc) return rc;
     if (k > 0) {
       float ms = 0.f;

@@ -116,6 +116,12 @@ __device__ __forceinline__ double warp_sum(double v) {
   return v;
 }
 
+// Raises the maximum stored as FP64 bits at *m to x >= 0.
+__device__ __forceinline__ void raise_max(unsigned long long* m, double x) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+  if (__hip_atomic_load(m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < b) atomicMax(m, b);
+}
+
 // One block per sky point (grid-stride).  Writes (tau, Tdot) of every SFT and
 // (A, B, C, AB - C^2), and sets status bit 1 if some window of the template
 // grid leaves the band, bit 2 if AB - C^2 <= 0.  k* is monotone in f and in
@@ -181,15 +187,19 @@ __global__ __launch_bounds__(256) void geometry_kernel(WuDev w, GeoStatus* statu
       int flags = any_bad ? 1 : 0;
       if (!(Dd > 0.0)) flags |= 2;
       if (flags) atomicOr(&status->flags, flags);
+      // the maxima are non-negative, so their bits order as the values; a
+      // block whose value does not exceed the one already stored skips the
+      // atomic (the stored value only grows), which keeps thousands of blocks
+      // from queueing on one address
       const double tm = fmax(fmax(red[3][0], red[3][1]), fmax(red[3][2], red[3][3]));
-      atomicMax(&status->max_abs_tau_bits, (unsigned long long)__double_as_longlong(tm));
+      raise_max(&status->max_abs_tau_bits, tm);
       const double pm = fmax(fmax(red[4][0], red[4][1]), fmax(red[4][2], red[4][3]));
-      atomicMax(&status->max_p_bits, (unsigned long long)__double_as_longlong(pm));   // P > 0: bits order as values
-      if (s == 0) {                  // non-negative: bits order as values
+      raise_max(&status->max_p_bits, pm);
+      if (s == 0) {
         const double vm = fmax(fmax(red[5][0], red[5][1]), fmax(red[5][2], red[5][3]));
         const double rm = fmax(fmax(red[6][0], red[6][1]), fmax(red[6][2], red[6][3]));
-        atomicMax(&status->max_v_bits, (unsigned long long)__double_as_longlong(vm));
-        atomicMax(&status->max_r_bits, (unsigned long long)__double_as_longlong(rm));
+        raise_max(&status->max_v_bits, vm);
+        raise_max(&status->max_r_bits, rm);
       }
     }
     __syncthreads();

@@ -183,3 +183,35 @@ def test_batch_mixes_paired_and_single_sky_tables(torch_cuda, oracle_lib):
             e = twoF_error(a[s, i, j], r["twoF"])
             _say(f"  wu {k}: n_sky={w.n_sky} n_fd={w.n_fd} max e {e.max():.2e}")
             assert e.max() <= 1e-4
+
+
+def test_pairing_follows_sky_vectors_changed_in_place(torch_cuda):
+    """The host copies the sky vectors back on the geometry pass's wait and
+    keeps the band order of the last grid it paired while the vectors are
+    unchanged.  A grid changed in place between calls (the same device array,
+    its points reversed) must be copied and paired afresh: the second call
+    equals a fresh plan's bit for bit, with no tile dropped."""
+    import paper_0904_1826_amd as P
+    torch = torch_cuda
+    w = _unit(906, CLUSTERED)
+    wu, _ = to_device(w)
+    a, b = alloc_output(w), alloc_output(w)
+    mk = lambda: P.Plan(max_sft=w.n_sft, max_bins=w.n_bins, max_sky=w.n_sky, max_fd=w.n_fd, max_f=w.n_f,
+                        max_dterms=8)
+    with mk() as p:
+        p.compute(wu, a)
+        torch.cuda.synchronize()
+        before = a.twoF.clone()
+        wu.sky.copy_(torch.flip(wu.sky, dims=[0]))
+        p.compute(wu, a)
+        torch.cuda.synchronize()
+        assert p.last_tile()["pair_seg"] > 0
+        p.compute(wu, a)                             # a dropped tile would be reported here
+        torch.cuda.synchronize()
+    with mk() as p:
+        p.compute(wu, b)
+        torch.cuda.synchronize()
+    _say(f"  in-place sky change: max |2F| {float(a.twoF.abs().max()):.3g}")
+    assert torch.isfinite(a.twoF).all()
+    assert torch.equal(a.twoF, b.twoF)
+    assert not torch.equal(a.twoF, before)
