@@ -654,12 +654,11 @@ int ensure_scratch(fstat_plan* p, const fstat_wu* w) {
   return rc;
 }
 
-// Geometry + band check into the status record status_d; waits for the
-// check.  Returns FSTAT_OK or an error.
 int stage_sky(fstat_plan* p, const fstat_wu* wu, hipStream_t st);
 
-// With `stage` (a unit whose sky points may be paired), the host copy of its
-// sky vectors rides on the same wait.
+// Geometry + band check into the status record status_d; waits for the
+// check.  With `stage` (a unit whose sky points may be paired) the host copy
+// of its sky vectors rides on the same wait.  Returns FSTAT_OK or an error.
 int run_geometry_at(fstat_plan* p, const WuDev& v, fstat::GeoStatus* status_d, hipStream_t st, int idx,
                     const fstat_wu* stage = nullptr) {
   p->sky_staged = nullptr;
@@ -804,6 +803,24 @@ double status_bits(unsigned long long b) {
   return t;
 }
 
+// Sky point indices in the order the pairing walks them: bands of z of the
+// grid's spacing, alternately by increasing and decreasing longitude (ties by
+// index).
+void band_order(const double* sk, int64_t n, std::vector<int64_t>* ord) {
+  const double h = sqrt(4.0 * M_PI / (double)n);           // grid spacing
+  const int64_t n_band = std::max<int64_t>(1, (int64_t)ceil(2.0 / h));
+  std::vector<std::pair<std::pair<int64_t, double>, int64_t>> key((size_t)n);
+  for (int64_t i = 0; i < n; ++i) {
+    const double z = sk[3 * i + 2], ph = atan2(sk[3 * i + 1], sk[3 * i]);
+    int64_t b = (int64_t)floor((z + 1.0) / 2.0 * (double)n_band);
+    b = b < 0 ? 0 : (b >= n_band ? n_band - 1 : b);
+    key[(size_t)i] = {{b, (b & 1) ? -ph : ph}, i};
+  }
+  std::sort(key.begin(), key.end());
+  ord->resize((size_t)n);
+  for (int64_t i = 0; i < n; ++i) (*ord)[(size_t)i] = key[(size_t)i].second;
+}
+
 // Tiles of two sky points for the interp kernels' ranges of at most 8
 // spindowns per thread: a tile evaluates (sky point, spindown) slots of both
 // points per thread and SFT from one staged slice, which halves the slice
@@ -824,27 +841,8 @@ double status_bits(unsigned long long b) {
 // their first point, so that consecutive tiles stay neighbours on the sky.
 // Writes the n_pairs tiles to `out` (room for n_sky) and returns the slice
 // width, or 0 when pairing does not apply (fewer than half the points find a
-// partner, or no width fits).
-// Sky point indices in the order the pairing walks them: bands of z of the
-// grid's spacing, alternately by increasing and decreasing longitude (ties by
-// index).
-void band_order(const double* sk, int64_t n, std::vector<int64_t>* ord) {
-  const double h = sqrt(4.0 * M_PI / (double)n);           // grid spacing
-  const int64_t n_band = std::max<int64_t>(1, (int64_t)ceil(2.0 / h));
-  std::vector<std::pair<std::pair<int64_t, double>, int64_t>> key((size_t)n);
-  for (int64_t i = 0; i < n; ++i) {
-    const double z = sk[3 * i + 2], ph = atan2(sk[3 * i + 1], sk[3 * i]);
-    int64_t b = (int64_t)floor((z + 1.0) / 2.0 * (double)n_band);
-    b = b < 0 ? 0 : (b >= n_band ? n_band - 1 : b);
-    key[(size_t)i] = {{b, (b & 1) ? -ph : ph}, i};
-  }
-  std::sort(key.begin(), key.end());
-  ord->resize((size_t)n);
-  for (int64_t i = 0; i < n; ++i) (*ord)[(size_t)i] = key[(size_t)i].second;
-}
-
-// `order`: the band_order of these sky vectors if the caller has it (else it
-// is computed here).
+// partner, or no width fits).  `order` is the band_order of these sky
+// vectors when the caller has it (else it is computed here).
 int make_pairs(const fstat_wu* wu, const fstat::GeoStatus& g, const double* sk, int2* out, int64_t* n_pairs,
                const std::vector<int64_t>* order = nullptr) {
   *n_pairs = 0;
