@@ -113,6 +113,20 @@ def test_parity_ragged_tiles(torch_cuda, oracle_lib, dterms, kernel):
     _compare(oracle_lib, w, out)
 
 
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_parity_four_detectors(torch_cuda, oracle_lib, kernel):
+    """Four detectors (the two synthetic sites twice, each with its own SFT
+    times and gaps), the largest detector count of the workloads, summed
+    coherently: every template against the oracle; the detector offsets pass
+    the library's check."""
+    w = small_workload(150, n_det=4, slots=11, keep=0.8, n_sky=5, n_fd=3, n_f=300, dterms=8,
+                       injections=((2, 1, 150, 15.0),))
+    assert len(w.det_offset) == 5
+    _say(f"four detectors {kernel}: n_sft={w.n_sft} offsets={[int(x) for x in w.det_offset]} templates={w.n_templates}")
+    out, _ = _run(torch_cuda, w, kernel=kernel)
+    _compare(oracle_lib, w, out)
+
+
 INTERP_TILES = [(8, 4, 0, 256), (8, 4, 7, 256), (8, 3, 0, 256), (8, 2, 0, 256), (8, 3, 7, 256), (4, 3, 0, 256),
                 (4, 2, 7, 256), (2, 3, 0, 256), (1, 3, 7, 256), (8, 3, 0, 64), (8, 2, 7, 64), (4, 3, 0, 64)]
 
