@@ -259,7 +259,14 @@ int fstat_batch_compute(fstat_plan* p, const fstat_wu* wus, int32_t n_wu, const 
  * segment's coherent 2F, accumulated in segment order (so the result is
  * reproducible bit for bit), and, if out->top_k > 0, the toplist of that sum
  * with the threshold applied to the sum.  out->twoF is required (it holds the
- * sum); Fa/Fb outputs are not available (must be NULL). */
+ * sum); Fa/Fb outputs are not available (must be NULL).  Every segment's
+ * geometry and band check run first, with one wait for all of them: on
+ * FSTAT_E_BAND (or a singular antenna-pattern matrix) nothing has been
+ * demodulated and fstat_last_error names the first failing segment; then
+ * the segments' demodulations are enqueued back to back.  Plan scratch: the
+ * geometry of all segments at once (16 B per sky point and SFT over all
+ * segments).  fstat_last_kernel_ms gives the sum over the segments'
+ * demodulation launches. */
 int fstat_semicoherent(fstat_plan* p, const fstat_wu* segs, int32_t n_seg, const fstat_out* out, void* stream);
 
 /* Bin index, offset and phase of (template, SFT) pairs, computed by the same

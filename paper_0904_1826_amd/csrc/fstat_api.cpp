@@ -86,6 +86,13 @@ struct fstat_plan {
   int2* pairs_d = nullptr;
   int2* pairs_h = nullptr;              // pinned
   size_t pairs_cap = 0;
+  // semi-coherent calls: the geometry and A, B, C of every segment, and an
+  // event pair per segment around its demodulation launches (seg_timed
+  // pairs recorded by the last call)
+  void* seg_arena = nullptr;
+  size_t seg_arena_bytes = 0;
+  std::vector<hipEvent_t> seg_ev;
+  int seg_timed = 0;
   // the sky array whose host copy the geometry pass's wait brought into
   // sky_h (stage_sky), for the pairing that follows it in the same call
   const void* sky_staged = nullptr;
@@ -690,7 +697,10 @@ int run_geometry(fstat_plan* p, const WuDev& v, hipStream_t st, int idx, const f
   return run_geometry_at(p, v, p->status_d, st, idx, stage);
 }
 
-int run_demod(fstat_plan* p, const WuDev& v, const Tile& t, hipStream_t st) {
+// `e0`, `e1`: the events around the demodulation launches (default: the
+// plan's ev0, ev1, which fstat_last_kernel_ms reads).
+int run_demod(fstat_plan* p, const WuDev& v, const Tile& t, hipStream_t st, hipEvent_t e0 = nullptr,
+              hipEvent_t e1 = nullptr) {
   const int kernel = resolved_kernel(p);
   p->have_last = true;
   p->last_tile = t;
@@ -707,11 +717,12 @@ int run_demod(fstat_plan* p, const WuDev& v, const Tile& t, hipStream_t st) {
     int rc = check_launch(p, fstat::launch_fill_int((int*)v.cand_count, 0, 2, st), "toplist counter reset");
     if (rc) return rc;
   }
-  (void)hipEventRecord(p->ev0, st);
+  const bool own = e0 == nullptr;
+  (void)hipEventRecord(own ? p->ev0 : e0, st);
   int rc = check_launch(p, fstat::launch_demod(v, t, kernel, st), "demodulation kernel");
-  (void)hipEventRecord(p->ev1, st);
+  (void)hipEventRecord(own ? p->ev1 : e1, st);
   p->ev_stream = st;
-  p->timed = (rc == FSTAT_OK);
+  if (own) p->timed = (rc == FSTAT_OK);
   if (rc == FSTAT_OK && v.cand) rc = check_launch(p, fstat::launch_top_select(v, st), "toplist selection");
   return rc;
 }
@@ -957,6 +968,42 @@ bool may_pair(const fstat_plan* p, const fstat_wu* wu) {
   return resolved_kernel(p) == fstat::KERNEL_INTERP && !coef16(p) && wu->n_sky >= 4 && p->force_seg <= 0;
 }
 
+// Whether the tile's ranges of at most 8 spindowns may take tiles of two sky
+// points: FP32 coefficients, 256 threads, four waves, 8 per thread.
+bool pairs_apply(const fstat_plan* p, const fstat_wu* wu, const Tile& t) {
+  return resolved_kernel(p) == fstat::KERNEL_INTERP && !coef16(p) && t.nf_reg == 8 && t.threads == fstat::kThreads &&
+         t.chunk >= 4 && wu->n_sky >= 4 && p->force_seg <= 0;
+}
+
+// The pairing itself, from a host copy of the sky vectors and the unit's
+// geometry status; the table goes to pairs_h and is uploaded to pairs_d
+// (room for n_sky entries each).
+int pair_sky(fstat_plan* p, const fstat_wu* wu, WuDev& v, Tile& t, hipStream_t st, bool default_tile_used,
+             const fstat::GeoStatus& g, const double* sky, int2* pairs_h, int2* pairs_d) {
+  const int64_t n = wu->n_sky;
+  int64_t np = 0;
+  if (n <= INT32_MAX &&
+      (p->ord_sky.size() != (size_t)(3 * n) || memcmp(p->ord_sky.data(), sky, (size_t)(3 * n) * sizeof(double)))) {
+    p->ord_sky.assign(sky, sky + 3 * n);
+    band_order(sky, n, &p->ord_idx);
+  }
+  const int width = make_pairs(wu, g, sky, pairs_h, &np, &p->ord_idx);
+  if (!width) return FSTAT_OK;
+  // the split with the costs of paired tiles; pairs serve its ranges of at most 8
+  const Tile tp = complete_tile(p, wu, t, true);
+  bool small = std::all_of(tp.fd_split, tp.fd_split + fstat::kSplitSizes, [](int32_t x) { return x == 0; });
+  for (int i = 0; i < fstat::kSplitSizes; ++i) small = small || (fstat::split_nfd(i) <= 8 && tp.fd_split[i] > 0);
+  if (!small) return FSTAT_OK;
+  const hipError_t e = hipMemcpyAsync(pairs_d, pairs_h, (size_t)np * sizeof(int2), hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return hip_err(p, e, "sky pair upload");
+  v.sky_pairs = pairs_d;
+  v.n_pairs = np;
+  t = tp;
+  t.pair_seg = width;
+  if (default_tile_used) t.sblock = 0;   // the default tile: one launch over all SFTs with pairs
+  return FSTAT_OK;
+}
+
 // Sky points of a single-unit tile of 8 spindowns per thread with ranges of
 // at most 8 per thread (FP32 coefficients, 256 threads, four waves), paired
 // by make_pairs after this unit's geometry pass; sets v.sky_pairs, v.n_pairs
@@ -968,11 +1015,8 @@ int prepare_pairs(fstat_plan* p, const fstat_wu* wu, WuDev& v, Tile& t, hipStrea
   v.sky_pairs = nullptr;
   v.n_pairs = 0;
   t.pair_seg = 0;
-  if (resolved_kernel(p) != fstat::KERNEL_INTERP || coef16(p) || t.nf_reg != 8 || t.threads != fstat::kThreads ||
-      t.chunk < 4 || wu->n_sky < 4 || p->force_seg > 0)
-    return FSTAT_OK;
-  const int64_t n = wu->n_sky;
-  int rc = ensure_pinned_pair(p, &p->pairs_d, &p->pairs_h, &p->pairs_cap, (size_t)n, "sky pairs");
+  if (!pairs_apply(p, wu, t)) return FSTAT_OK;
+  int rc = ensure_pinned_pair(p, &p->pairs_d, &p->pairs_h, &p->pairs_cap, (size_t)wu->n_sky, "sky pairs");
   if (rc) return rc;
   if (p->sky_staged != wu->sky) {          // not brought by this call's geometry wait
     rc = stage_sky(p, wu, st);
@@ -981,27 +1025,7 @@ int prepare_pairs(fstat_plan* p, const fstat_wu* wu, WuDev& v, Tile& t, hipStrea
     if (e != hipSuccess) return hip_err(p, e, "sky vector copy");
   }
   p->sky_staged = nullptr;
-  int64_t np = 0;
-  if (n <= INT32_MAX &&
-      (p->ord_sky.size() != (size_t)(3 * n) || memcmp(p->ord_sky.data(), p->sky_h, (size_t)(3 * n) * sizeof(double)))) {
-    p->ord_sky.assign(p->sky_h, p->sky_h + 3 * n);
-    band_order(p->sky_h, n, &p->ord_idx);
-  }
-  const int width = make_pairs(wu, *p->status_h, p->sky_h, p->pairs_h, &np, &p->ord_idx);
-  if (!width) return FSTAT_OK;
-  // the split with the costs of paired tiles; pairs serve its ranges of at most 8
-  const Tile tp = complete_tile(p, wu, t, true);
-  bool small = std::all_of(tp.fd_split, tp.fd_split + fstat::kSplitSizes, [](int32_t x) { return x == 0; });
-  for (int i = 0; i < fstat::kSplitSizes; ++i) small = small || (fstat::split_nfd(i) <= 8 && tp.fd_split[i] > 0);
-  if (!small) return FSTAT_OK;
-  const hipError_t e = hipMemcpyAsync(p->pairs_d, p->pairs_h, (size_t)np * sizeof(int2), hipMemcpyHostToDevice, st);
-  if (e != hipSuccess) return hip_err(p, e, "sky pair upload");
-  v.sky_pairs = p->pairs_d;
-  v.n_pairs = np;
-  t = tp;
-  t.pair_seg = width;
-  if (default_tile_used) t.sblock = 0;   // the default tile: one launch over all SFTs with pairs
-  return FSTAT_OK;
+  return pair_sky(p, wu, v, t, st, default_tile_used, *p->status_h, p->sky_h, p->pairs_h, p->pairs_d);
 }
 
 // Launch shape of the batched form (a Tile under the plan's batch class):
@@ -1494,6 +1518,8 @@ void fstat_plan_destroy(fstat_plan* p) {
   if (p->ev0) (void)hipEventDestroy(p->ev0);
   if (p->ev1) (void)hipEventDestroy(p->ev1);
   if (p->ev_drop) (void)hipEventDestroy(p->ev_drop);
+  if (p->seg_arena) (void)hipFree(p->seg_arena);
+  for (hipEvent_t e : p->seg_ev) (void)hipEventDestroy(e);
   (void)hipGetLastError();
   delete p;
 }
@@ -1503,6 +1529,7 @@ int fstat_compute(fstat_plan* p, const fstat_wu* wu, const fstat_out* out, void*
   p->err[0] = 0;
   p->timed = false;
   p->ms_prev = 0.0;
+  p->seg_timed = 0;
   int rc = check_prev_drops(p);
   if (rc) return rc;
   rc = validate_wu(p, wu, out, -1);
@@ -1532,6 +1559,7 @@ int fstat_compute_noalloc(fstat_plan* p, const fstat_wu* wu, const fstat_out* ou
   p->err[0] = 0;
   p->timed = false;
   p->ms_prev = 0.0;
+  p->seg_timed = 0;
   int rc = check_prev_drops(p);
   if (rc) return rc;
   rc = validate_wu(p, wu, out, -1);
@@ -1588,6 +1616,7 @@ int fstat_batch_compute(fstat_plan* p, const fstat_wu* wus, int32_t n_wu, const 
   p->err[0] = 0;
   p->timed = false;
   p->ms_prev = 0.0;
+  p->seg_timed = 0;
   int rc0 = check_prev_drops(p);
   if (rc0) return rc0;
   if (n_wu < 0 || (n_wu > 0 && (!wus || !outs))) return set_err(p, FSTAT_E_ARG, "bad work-unit list");
@@ -1622,6 +1651,7 @@ int fstat_semicoherent(fstat_plan* p, const fstat_wu* segs, int32_t n_seg, const
   p->err[0] = 0;
   p->timed = false;
   p->ms_prev = 0.0;
+  p->seg_timed = 0;
   int rc0 = check_prev_drops(p);
   if (rc0) return rc0;
   if (n_seg < 1 || !segs || !out) return set_err(p, FSTAT_E_ARG, "semi-coherent: need n_seg >= 1 segments and an output");
@@ -1644,28 +1674,88 @@ int fstat_semicoherent(fstat_plan* p, const fstat_wu* segs, int32_t n_seg, const
   if (rc) return rc;
   fstat_out o = *out;
   o.top_k = 0;                       // the toplist is taken of the sum, after the last segment
-  double ms_done = 0.0;
-  for (int k = 0; k < n_seg; ++k) {
+  // Every segment's geometry, A, B, C and band check first, with one wait for
+  // all of them (which also brings the sky vectors for the pairing), then the
+  // segments' coefficient passes and demodulations back to back on the
+  // stream: nothing is demodulated unless every segment passed its check,
+  // and the device does not wait for the host between segments.
+  const int64_t n = g.n_sky;
+  for (int k = 0; k < n_seg; ++k) {  // buffers reach their largest size before any pointer is taken
     rc = ensure_scratch(p, &segs[k]);
     if (rc) return rc;
-    WuDev v = make_dev(p, &segs[k], &o);
-    v.accumulate = k > 0;
-    // the geometry pass waits for the stream, so the previous segment's
-    // demodulation events have completed
-    rc = run_geometry(p, v, st, k, may_pair(p, &segs[k]) ? &segs[k] : nullptr);
-    if (rc) return rc;
-    if (k > 0) {
-      float ms = 0.f;
-      if (hipEventElapsedTime(&ms, p->ev0, p->ev1) == hipSuccess) ms_done += ms;
+  }
+  std::vector<size_t> goff((size_t)n_seg + 1, 0);
+  for (int k = 0; k < n_seg; ++k)
+    goff[k + 1] = goff[k] + align256((size_t)n * segs[k].n_sft * sizeof(double2)) + align256((size_t)n * sizeof(double4));
+  rc = dev_alloc(p, &p->seg_arena, &p->seg_arena_bytes, goff[n_seg], "segment geometry");
+  if (rc) return rc;
+  rc = ensure_pinned_pair(p, &p->bstat_d, &p->bstat_h, &p->bstat_cap, (size_t)n_seg, "segment status");
+  if (rc) return rc;
+  const bool pair = may_pair(p, &g);
+  p->sky_staged = nullptr;
+  if (pair) {
+    const size_t need = (size_t)n_seg * 3 * (size_t)n;
+    if (p->sky_h_cap < need) {
+      if (p->sky_h) (void)hipHostFree(p->sky_h);
+      p->sky_h = nullptr;
+      p->sky_h_cap = 0;
+      if (hipHostMalloc((void**)&p->sky_h, need * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        return set_err(p, FSTAT_E_NOMEM, "sky vectors: allocation of %lld entries failed", (long long)(n * n_seg));
+      }
+      p->sky_h_cap = need;
     }
-    bool dflt = false;
-    Tile t = pick_tile(p, &segs[k], &dflt);
-    rc = prepare_pairs(p, &segs[k], v, t, st, dflt);
-    if (rc) return rc;
-    rc = run_demod(p, v, t, st);
+    rc = ensure_pinned_pair(p, &p->pairs_d, &p->pairs_h, &p->pairs_cap, (size_t)n_seg * (size_t)n, "sky pairs");
     if (rc) return rc;
   }
-  p->ms_prev = ms_done;
+  while (p->seg_ev.size() < 2 * (size_t)n_seg) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return set_err(p, FSTAT_E_DEVICE, "semi-coherent: event creation failed");
+    p->seg_ev.push_back(e);
+  }
+  std::vector<WuDev> vs((size_t)n_seg);
+  for (int k = 0; k < n_seg; ++k) {
+    WuDev v = make_dev(p, &segs[k], &o);
+    char* base = (char*)p->seg_arena + goff[k];
+    v.geo = (double2*)base;
+    v.abcd = (double4*)(base + align256((size_t)n * segs[k].n_sft * sizeof(double2)));
+    v.accumulate = k > 0;
+    rc = check_launch(p, fstat::launch_fill_int((int*)(p->bstat_d + k), 0, fstat::kGeoResetInts, st), "status reset");
+    if (rc) return rc;
+    rc = check_launch(p, fstat::launch_geometry(v, p->bstat_d + k, st), "geometry kernel");
+    if (rc) return rc;
+    if (pair) {
+      const hipError_t e = hipMemcpyAsync(p->sky_h + 3 * (size_t)n * k, segs[k].sky, (size_t)(3 * n) * sizeof(double),
+                                          hipMemcpyDeviceToHost, st);
+      if (e != hipSuccess) return hip_err(p, e, "sky vector copy");
+    }
+    vs[(size_t)k] = v;
+  }
+  hipError_t e = hipMemcpyAsync(p->bstat_h, p->bstat_d, (size_t)n_seg * sizeof(fstat::GeoStatus),
+                                hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_err(p, e, "geometry kernel");
+  for (int k = 0; k < n_seg; ++k) {
+    const int bits = p->bstat_h[k].flags;
+    if (bits & 1) return set_err(p, FSTAT_E_BAND, "segment %d: a Dirichlet window [k*-D+1, k*+D] leaves the stored band", k);
+    if (bits & 2) return set_err(p, FSTAT_E_ARG, "segment %d: antenna-pattern matrix is singular (A B - C^2 <= 0)", k);
+  }
+  for (int k = 0; k < n_seg; ++k) {
+    WuDev v = vs[(size_t)k];
+    p->max_abs_tau = status_tau(p->bstat_h[k]);       // the slice widths of this segment's tile
+    p->max_p = status_p(p->bstat_h[k]);
+    bool dflt = false;
+    Tile t = pick_tile(p, &segs[k], &dflt);
+    t.pair_seg = 0;
+    if (pair && pairs_apply(p, &segs[k], t)) {
+      rc = pair_sky(p, &segs[k], v, t, st, dflt, p->bstat_h[k], p->sky_h + 3 * (size_t)n * k,
+                    p->pairs_h + (size_t)n * k, p->pairs_d + (size_t)n * k);
+      if (rc) return rc;
+    }
+    rc = run_demod(p, v, t, st, p->seg_ev[2 * (size_t)k], p->seg_ev[2 * (size_t)k + 1]);
+    if (rc) return rc;
+  }
+  p->seg_timed = n_seg;
   if (out->top_k > 0) {
     WuDev v = make_dev(p, &g, out);
     rc = check_launch(p, fstat::launch_fill_int((int*)v.cand_count, 0, 2, st), "toplist counter reset");
@@ -1932,6 +2022,16 @@ int fstat_last_tile(const fstat_plan* p, int32_t* out) {
 }
 
 double fstat_last_kernel_ms(fstat_plan* p) {
+  if (p && p->seg_timed > 0) {           // semi-coherent: the sum over the segments' launches
+    if (hipEventSynchronize(p->seg_ev[2 * (size_t)p->seg_timed - 1]) != hipSuccess) return -1.0;
+    double total = 0.0;
+    for (int k = 0; k < p->seg_timed; ++k) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, p->seg_ev[2 * (size_t)k], p->seg_ev[2 * (size_t)k + 1]) != hipSuccess) return -1.0;
+      total += ms;
+    }
+    return total;
+  }
   if (!p || !p->timed) return -1.0;
   if (hipEventSynchronize(p->ev1) != hipSuccess) return -1.0;
   float ms = 0.f;

@@ -121,6 +121,38 @@ def test_semicoherent_toplist(torch_cuda):
     assert abs(n_above - rn) <= 2
 
 
+def test_semicoherent_band_error_names_the_segment(torch_cuda, oracle_lib):
+    """Every segment is band-checked before any is demodulated: a middle
+    segment whose stored band is one bin short of its lowest window fails
+    with FSTAT_E_BAND naming it, the output is left untouched, and the plan
+    then sums the intact segments (against the oracle)."""
+    import paper_0904_1826_amd as P
+    torch = torch_cuda
+    segs = _segments(3, 77, n_f=64, injections=[(2, 1, 30, 6.0)])
+    w = segs[1]
+    k, _, _, _ = oracle_lib.bins(w, oracle_lib.all_templates(w))
+    lo = int(k.min()) - w.dterms + 1
+    cut = replace(w, sft=np.ascontiguousarray(w.sft[:, lo - w.k_first + 1:]), k_first=lo + 1)
+    bad = [segs[0], cut, segs[2]]
+    out = alloc_output(segs[0])
+    out.twoF.fill_(-1.0)
+    with _plan(bad) as p:
+        with pytest.raises(P.FstatError) as ei:
+            p.semicoherent([to_device(x)[0] for x in bad], out)
+        _say(f"  {p.last_error()}")
+        assert ei.value.code == P.FSTAT_E_BAND and "segment 1" in p.last_error()
+        torch.cuda.synchronize()
+        assert bool((out.twoF == -1.0).all())           # nothing was demodulated
+        p.semicoherent([to_device(x)[0] for x in segs], out)
+        torch.cuda.synchronize()
+        assert p.last_kernel_ms() > 0.0
+    r = oracle_lib.semicoherent(segs)
+    s_, i_, j_ = r["templates"]
+    e = twoF_error(out.twoF.cpu().numpy()[s_, i_, j_], r["twoF"])
+    _say(f"  intact segments after the error: max e {e.max():.2e}")
+    assert e.max() <= 1e-4
+
+
 def test_semicoherent_argument_errors(torch_cuda):
     import paper_0904_1826_amd as P
     segs = _segments(2, 75, n_f=64, n_sky=2, injections=[])
