@@ -121,26 +121,35 @@ def test_semicoherent_toplist(torch_cuda):
     assert abs(n_above - rn) <= 2
 
 
-def test_semicoherent_band_error_names_the_segment(torch_cuda, oracle_lib):
-    """Every segment is band-checked before any is demodulated: a middle
-    segment whose stored band is one bin short of its lowest window fails
-    with FSTAT_E_BAND naming it, the output is left untouched, and the plan
-    then sums the intact segments (against the oracle)."""
+@pytest.mark.parametrize("fault", ["band", "singular"])
+def test_semicoherent_segment_error_names_the_segment(torch_cuda, oracle_lib, fault):
+    """Every segment is checked before any is demodulated: a middle segment
+    whose stored band is one bin short of its lowest window (FSTAT_E_BAND),
+    or whose antenna patterns make A B - C^2 vanish for a sky point (a = b:
+    FSTAT_E_ARG), fails naming it, the output is left untouched, and the
+    plan then sums the intact segments (against the oracle)."""
     import paper_0904_1826_amd as P
     torch = torch_cuda
     segs = _segments(3, 77, n_f=64, injections=[(2, 1, 30, 6.0)])
     w = segs[1]
-    k, _, _, _ = oracle_lib.bins(w, oracle_lib.all_templates(w))
-    lo = int(k.min()) - w.dterms + 1
-    cut = replace(w, sft=np.ascontiguousarray(w.sft[:, lo - w.k_first + 1:]), k_first=lo + 1)
-    bad = [segs[0], cut, segs[2]]
+    if fault == "band":
+        k, _, _, _ = oracle_lib.bins(w, oracle_lib.all_templates(w))
+        lo = int(k.min()) - w.dterms + 1
+        bad1 = replace(w, sft=np.ascontiguousarray(w.sft[:, lo - w.k_first + 1:]), k_first=lo + 1)
+        code = P.FSTAT_E_BAND
+    else:
+        b = w.b.copy()
+        b[3] = w.a[3]
+        bad1 = replace(w, b=b)
+        code = P.FSTAT_E_ARG
+    bad = [segs[0], bad1, segs[2]]
     out = alloc_output(segs[0])
     out.twoF.fill_(-1.0)
     with _plan(bad) as p:
         with pytest.raises(P.FstatError) as ei:
             p.semicoherent([to_device(x)[0] for x in bad], out)
         _say(f"  {p.last_error()}")
-        assert ei.value.code == P.FSTAT_E_BAND and "segment 1" in p.last_error()
+        assert ei.value.code == code and "segment 1" in p.last_error()
         torch.cuda.synchronize()
         assert bool((out.twoF == -1.0).all())           # nothing was demodulated
         p.semicoherent([to_device(x)[0] for x in segs], out)
