@@ -1059,13 +1059,15 @@ __global__ __launch_bounds__(NT, MINW) void demod_interp_kernel(WuDev w, int W, 
 // per thread; 8 or 4 with FP16 coefficients; four waves per SIMD, five for 8
 // with FP16 coefficients, three for 16, whose 64 accumulators per thread
 // take the registers of a fourth but which uses each staged slice for twice
-// the pairs), and SFTs [al0, al1) of each: the
+// the pairs; with tiles of two sky points three, and four for 4 per thread,
+// whose 128 registers spill 28 bytes of per-tile state but which ran the 64
+// uneven units 1.4 % faster than at three), and SFTs [al0, al1) of each: the
 // host runs the SFT loop as a sequence of such launches (Fa, Fb carried in
 // `acc`), because over thousands of SFTs the work-groups sharing a slice
 // drift apart and L2 no longer holds it for all of them.
 // Waves per SIMD the registers of a batched specialisation leave room for.
 __host__ __device__ constexpr int batch_minw(int nfd, bool c16, int nsky) {
-  return nfd == 16 ? 3 : nsky == 2 ? 3 : nfd == 8 ? (c16 ? 5 : 4) : (nfd >= 5 ? 4 : 3);
+  return nfd == 16 ? 3 : nsky == 2 ? (nfd <= 4 ? 4 : 3) : nfd == 8 ? (c16 ? 5 : 4) : (nfd >= 5 ? 4 : 3);
 }
 
 template <int NFD, bool C16, bool SAFE, int NSKY = 1>
